@@ -1,0 +1,178 @@
+"""Pins of the oracle's MPPI step: weights (Eq. (4)), update (Eq. (5)) and
+the receding-horizon warm start (Sec. III-B, Alg. 1).
+
+Expected values come from limits and invariants of the softmax average, not
+from the oracle's formulas: weights sum to one and ignore a common cost
+offset, lambda -> 0 selects the cheapest sample, lambda -> inf gives the plain
+mean, one sample returns itself, zero noise returns the nominal.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_14726_amd import synth
+
+
+def problem(K=64, N=12, objective="gate", **over):
+    w = synth.single_solve_workload(K=K, N=N, objective=objective, seed=11)
+    prm = dict(w["params"], eps_dec=1e-9, n_threads=4)
+    prm.update(over)
+    pb = O.Problem(w["quad"], prm, gates=w["gates"], path=w.get("path"),
+                   path_len=w.get("path_len", 0.0), xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0))
+    return pb, w
+
+
+def samples(pb, r):
+    """All clipped samples U^m of a solve, regenerated from its nominal."""
+    K, N = pb.cfg.K, pb.cfg.N
+    return np.array([pb.sample(r["Ustar"].ravel(), r["Vstar"], m, 0)[0] for m in range(K)])
+
+
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
+def test_weights_sum_to_one_and_update_is_convex(objective):
+    pb, w = problem(objective=objective, **{"lambda": 50.0})
+    r = pb.solve(pb.warm(), w["x0"])
+    assert r["status"] == O.OK
+    assert abs(r["w"].sum() - 1.0) < 1e-12
+    assert (r["w"] >= 0).all()
+    assert 1.0 <= r["ess"] <= pb.cfg.K + 1e-9
+    Us = samples(pb, r)
+    np.testing.assert_allclose(r["U"], np.einsum("m,mkc->kc", r["w"], Us), atol=1e-12)
+    assert (r["U"] >= pb.quad.t_min - 1e-12).all() and (r["U"] <= pb.quad.t_max + 1e-12).all()
+
+
+def test_common_cost_offset_leaves_weights_unchanged():
+    pb, w = problem(**{"lambda": 30.0})
+    r = pb.solve(pb.warm(), w["x0"])
+    K = pb.cfg.K
+    r2 = pb.solve(pb.warm(), w["x0"], J_rep=r["J"] + 1234.5, rep_mask=np.ones(K, np.uint8))
+    np.testing.assert_allclose(r2["w"], r["w"], rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(r2["U"], r["U"], atol=1e-12)
+
+
+def test_small_lambda_selects_cheapest_sample():
+    pb, w = problem(**{"lambda": 1e-8})
+    r = pb.solve(pb.warm(), w["x0"])
+    m = int(np.argmin(r["J"]))
+    Us = samples(pb, r)
+    np.testing.assert_allclose(r["U"], Us[m], atol=1e-12)
+    assert abs(r["ess"] - 1.0) < 1e-9
+
+
+def test_large_lambda_gives_mean():
+    pb, w = problem(**{"lambda": 1e12})
+    r = pb.solve(pb.warm(), w["x0"])
+    Us = samples(pb, r)
+    np.testing.assert_allclose(r["U"], Us.mean(axis=0), atol=1e-7)
+    assert abs(r["ess"] - pb.cfg.K) < 1e-3
+
+
+def test_single_sample_returns_itself():
+    pb, w = problem(K=1)
+    r = pb.solve(pb.warm(), w["x0"])
+    Us = samples(pb, r)
+    np.testing.assert_allclose(r["U"], Us[0], atol=1e-15)
+    assert r["w"][0] == 1.0
+
+
+def test_zero_noise_reproduces_nominal():
+    pb, w = problem(sigma=(0.0, 0.0, 0.0, 0.0))
+    r = pb.solve(pb.warm(), w["x0"])
+    hover = synth.hover_thrust()
+    np.testing.assert_allclose(r["U"], np.full((pb.cfg.N, 4), hover), atol=1e-14)
+    np.testing.assert_allclose(r["J"], np.full(pb.cfg.K, r["J_nom"]), atol=0)
+    assert abs(r["ess"] - pb.cfg.K) < 1e-9
+
+
+def test_warm_start_shifts_previous_solution():
+    pb, w = problem(**{"lambda": 20.0})
+    warm = pb.warm()
+    r1 = pb.solve(warm, w["x0"], t_now=0.0)
+    assert warm.s == 1 and warm.warm == 1
+    r2 = pb.solve(warm, w["x0"], t_now=pb.cfg.dt)  # one step later: shift 1
+    assert r2["shift"] == 1
+    want = np.vstack([r1["U"][1:], r1["U"][-1:]])
+    np.testing.assert_allclose(r2["Ustar"], want, atol=0)
+    r3 = pb.solve(warm, w["x0"], t_now=3.9 * pb.cfg.dt)  # 2.9 steps -> shift 3
+    assert r3["shift"] == 3
+    want = np.vstack([r2["U"][3:], np.repeat(r2["U"][-1:], 3, axis=0)])
+    np.testing.assert_allclose(r3["Ustar"], want, atol=0)
+    # a fresh solve counter draws fresh noise
+    assert not np.allclose(r2["J"], r1["J"])
+
+
+def test_measured_gate_pass_advances_target_and_clears_mask():
+    pb, w = problem()
+    gates = w["gates"]
+    warm = pb.warm()
+    pb.solve(warm, w["x0"])
+    assert warm.g0 == 0
+    # put the next measured state just behind gate 0, inside its square
+    yaw = gates[0, 3]
+    n = np.array([np.cos(yaw), np.sin(yaw), 0.0])
+    x1 = w["x0"].copy()
+    x1[0:3] = gates[0, :3] + 0.1 * n
+    warm.x_prev[:] = list(gates[0, :3] - 0.1 * n) + list(w["x0"][3:])
+    warm.allow[0] = 0
+    r = pb.solve(warm, x1, t_now=pb.cfg.dt)
+    assert r["g0"] == 1 and warm.g0 == 1
+    assert all(a == 0xFFFFFFFF for a in r["allow"])
+    # a motion that misses the square does not advance it
+    warm2 = pb.warm()
+    pb.solve(warm2, w["x0"])
+    h = np.array([-np.sin(yaw), np.cos(yaw), 0.0])
+    warm2.x_prev[:] = list(gates[0, :3] - 0.1 * n + 2.0 * h) + list(w["x0"][3:])
+    x2 = w["x0"].copy(); x2[0:3] = gates[0, :3] + 0.1 * n + 2.0 * h
+    r = pb.solve(warm2, x2, t_now=pb.cfg.dt)
+    assert r["g0"] == 0
+
+
+def test_nominal_front_mask_becomes_next_allow():
+    pb, w = problem()
+    warm = pb.warm()
+    r = pb.solve(warm, w["x0"])
+    assert list(warm.allow) == r["front"]
+    # the start state is 2 m in front of gate 0
+    assert O.mask_bits(r["front"], 1)[0]
+
+
+def test_all_costs_nonfinite_is_reported_and_keeps_warm_state():
+    pb, w = problem()
+    warm = pb.warm()
+    pb.solve(warm, w["x0"])
+    before = bytes(warm)
+    K = pb.cfg.K
+    r = pb.solve(warm, w["x0"], t_now=pb.cfg.dt, J_rep=np.full(K, np.nan),
+                 rep_mask=np.ones(K, np.uint8))
+    assert r["status"] == O.ENONFINITE
+    assert bytes(warm) == before
+
+
+def test_nonfinite_samples_get_zero_weight():
+    pb, w = problem(**{"lambda": 40.0})
+    r = pb.solve(pb.warm(), w["x0"])
+    K = pb.cfg.K
+    J = r["J"].copy()
+    J[::3] = np.inf
+    J[1::7] = np.nan
+    r2 = pb.solve(pb.warm(), w["x0"], J_rep=J, rep_mask=np.ones(K, np.uint8))
+    assert (r2["w"][::3] == 0).all() and (r2["w"][1::7] == 0).all()
+    assert abs(r2["w"].sum() - 1.0) < 1e-12
+
+
+def test_invalid_arguments_rejected():
+    pb, w = problem()
+    bad = w["x0"].copy(); bad[2] = np.nan
+    assert pb.solve(pb.warm(), bad)["status"] == O.EINVAL
+    pb2, _ = problem(**{"lambda": 0.0})
+    assert pb2.solve(pb2.warm(), w["x0"])["status"] == O.EINVAL
+    pb3, _ = problem(N=O.NMAX + 1)
+    assert pb3.solve(pb3.warm(), w["x0"])["status"] == O.EINVAL
+
+
+def test_thread_count_does_not_change_results():
+    pb1, w = problem(K=200, n_threads=1, **{"lambda": 25.0})
+    pb8, _ = problem(K=200, n_threads=8, **{"lambda": 25.0})
+    r1 = pb1.solve(pb1.warm(), w["x0"])
+    r8 = pb8.solve(pb8.warm(), w["x0"])
+    assert np.array_equal(r1["J"], r8["J"]) and np.array_equal(r1["U"], r8["U"])
