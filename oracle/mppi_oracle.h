@@ -31,7 +31,7 @@ extern "C" {
 #endif
 
 #define ORC_NMAX 256          /* longest horizon the oracle accepts            */
-#define ORC_MASK_WORDS 8      /* (ORC_NMAX + 1) bits of per-state flags         */
+#define ORC_MASK_WORDS 9      /* holds (ORC_NMAX + 1) bits of per-state flags   */
 
 enum { ORC_OBJ_GATE = 0, ORC_OBJ_CONTOUR = 1, ORC_OBJ_TRACK = 2 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENONFINITE = -4 };

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liborc.so")
 SRC = os.path.join(HERE, "mppi_oracle.c")
 
 NMAX = 256
-MASK_WORDS = 8
+MASK_WORDS = 9
 OBJ_GATE, OBJ_CONTOUR, OBJ_TRACK = 0, 1, 2
 OK, EINVAL, ENONFINITE = 0, -1, -4
 

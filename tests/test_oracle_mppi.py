@@ -176,3 +176,14 @@ def test_thread_count_does_not_change_results():
     r1 = pb1.solve(pb1.warm(), w["x0"])
     r8 = pb8.solve(pb8.warm(), w["x0"])
     assert np.array_equal(r1["J"], r8["J"]) and np.array_equal(r1["U"], r8["U"])
+
+
+def test_longest_horizon_mask_fits():
+    # N = 256 needs mask bits 0..256 (nine 32-bit words)
+    pb, w = problem(K=4, N=O.NMAX)
+    warm = pb.warm()
+    r = pb.solve(warm, w["x0"])
+    assert r["status"] == O.OK
+    bits = O.mask_bits(r["front"], O.NMAX + 1)
+    assert bits[0]  # start state is in front of gate 0
+    assert list(warm.allow) == r["front"]
