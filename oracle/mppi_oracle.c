@@ -454,7 +454,7 @@ static int cfg_valid(const orc_quad *q, const orc_cfg *c)
 int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double x0[13],
               double t_now, const double *J_rep, const uint8_t *rep_mask, orc_out *out)
 {
-    if (!cfg_valid(q, c) || !warm || !x0 || !out || !out->J) return ORC_EINVAL;
+    if (!cfg_valid(q, c) || !warm || !x0 || !out || !out->J || !isfinite(t_now)) return ORC_EINVAL;
     if ((J_rep == NULL) != (rep_mask == NULL)) return ORC_EINVAL;
     for (int i = 0; i < 13; ++i) if (!isfinite(x0[i])) return ORC_EINVAL;
     const int K = c->K, N = c->N;
@@ -468,6 +468,8 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
     if (warm->warm) {
         /* shift the previous solution by the elapsed steps, repeat its tail */
         double el = (t_now - warm->t_prev) / c->dt;
+        if (!(el < 1.0e6)) el = 1.0e6; /* keeps the conversion to int defined */
+        if (el < 0.0) el = 0.0;
         shift = (int32_t)floor(el + 0.5);
         if (shift < 1) shift = 1;
         for (int k = 0; k < N; ++k) {
@@ -496,9 +498,14 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
         if (c->objective == ORC_OBJ_CONTOUR) theta0 = orc_project(c, x0, 0.0, 1);
     }
     if (c->objective == ORC_OBJ_GATE && (g0 < 0 || g0 >= c->n_gates)) return ORC_EINVAL;
+    /* reference row of x0, held at the last row past the end of the table */
     int32_t i0 = 0;
-    if (c->objective == ORC_OBJ_TRACK) i0 = (int32_t)floor(t_now / c->ref_dt + 0.5);
-    if (i0 < 0) i0 = 0;
+    if (c->objective == ORC_OBJ_TRACK) {
+        double r = floor(t_now / c->ref_dt + 0.5);
+        if (!(r >= 0.0)) r = 0.0;
+        if (r > (double)(c->n_ref - 1)) r = (double)(c->n_ref - 1);
+        i0 = (int32_t)r;
+    }
     const uint32_t s = warm->s;
 
     /* ---- samples, rollouts, costs (Alg. 1, inner loop) ---- */

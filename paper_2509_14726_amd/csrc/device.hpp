@@ -1,0 +1,153 @@
+// Device-side data layout and small helpers of the MPPI step (gfx950).
+//
+// Memory of one context (all device-resident):
+//   ctrl   N x K x 4 Real  sample controls U^m_k, step-major: element (k*K + m)*4 + c,
+//          so a wavefront at fixed k reads / writes 64 consecutive 16 B (32 B) records
+//   vctrl  N x K Real      contouring progress-speed samples, same order
+//   nomU   N x 4 Real      clipped nominal sequence (the noise-free sample, lane K)
+//   J      K Real          sample costs
+//   part   partial weighted sums of the reduction over samples (per tile, per step)
+//   warm   DevWarm + wU (N x 4 double) + wV (N double): what the next solve inherits
+//   cur    DevCur: per-solve values decided once by the head and read by every kernel
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mppi {
+
+constexpr int kNMax = 256;
+constexpr int kMaskWords = 9;   // (kNMax + 1) bits
+constexpr int kReqDoubles = 16;
+
+enum Objective { OBJ_GATE = 0, OBJ_CONTOUR = 1, OBJ_TRACK = 2 };
+enum Status { ST_OK = 0, ST_INVAL = -1, ST_NOMEM = -2, ST_DEVICE = -3, ST_NONFINITE = -4 };
+
+struct DevWarm {
+    int32_t warm, g0;
+    uint32_t s;
+    int32_t N;
+    uint32_t allow[kMaskWords];
+    int32_t pad0;
+    double t_prev, theta0;
+    double x_prev[13];
+    double pad1;
+};
+
+struct DevCur {
+    int32_t g0, i0, shift, warm;
+    uint32_t s, ticket, jmin32, pad0;
+    unsigned long long jmin64;
+    uint32_t allow[kMaskWords];
+    int32_t pad1;
+    double theta0, t_now;
+    double u_prev[4];
+    double v_prev;
+    double J_nom;
+    double x0[13];
+    double pad2;
+};
+
+struct DevResult {
+    double u0[4];
+    double J_min, S, S2, ess, J_nom, theta0;
+    int32_t status, g0, i0, shift;
+    uint32_t s, pad;
+};
+
+// Everything a kernel needs, passed by value (kernel arguments live in SGPRs).
+// Floating constants are given in double and converted by the kernel template.
+struct KArgs {
+    int32_t K, N, G, P, R, objective;
+    int32_t mt_size, n_mt;      // reduction tiles: samples per tile, tiles per step
+    int32_t proj_window, has_drag;
+    uint32_t seed_lo, seed_hi;
+    // model
+    double inv_mass, gravity, arm_s, c_tau;
+    double inv_J[3], gyro[3];   // 1/J_i and (J_z-J_y)/J_x, (J_x-J_z)/J_y, (J_y-J_x)/J_z
+    double drag[3];
+    double t_min, t_max, w_max, hover;
+    // sampling
+    double dt, lambda, sigma[4], sigma_v;
+    // costs
+    double w_lim, q_near, r_near, gate_half;
+    double Q[13], QN[13], R_dT[4];
+    double q_l, q_c, Q_w[3], r_dv, mu, v_max;
+    double path_len, ref_dt;
+    // problem data
+    const double *gates_d;      // G x 4 (head, FP64)
+    const void *gates_r;        // G x 8 Real: c, n.xy, h.xy, pad
+    const double *path_d;       // P x 6 (head, FP64)
+    const void *path_r;         // P x 8 Real: p, t, pad
+    const void *xref_r;         // R x 16 Real
+    // per-context state
+    DevWarm *warm;
+    double *wU, *wV;
+    DevCur *cur;
+    DevResult *res;
+    void *ctrl, *vctrl, *nomU, *nomV, *J;
+    void *part;                 // Acc: [N][n_mt][C] tile sums, [n_mt][2] weight sums, [N][C] + 2 step sums
+    uint32_t *tickets;          // kNMax + 1 completion counters of the reduction
+    uint8_t *front8;            // N + 1 bytes written by the nominal lane
+    // per-call
+    const double *req;          // x0[13], t_now
+    double *u0_out;             // 4 doubles or null
+};
+
+template <typename T> __device__ __forceinline__ T clampT(T v, T lo, T hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Order-preserving maps of finite floats to unsigned integers (for atomicMin).
+__device__ __forceinline__ uint32_t ordered_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float from_ordered(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+__device__ __forceinline__ unsigned long long ordered_bits(double f)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(f);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordered(unsigned long long u)
+{
+    return __longlong_as_double((long long)((u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u));
+}
+
+// Compensated (Kahan) running sum.  For double the compensation is dropped.
+template <typename Real> struct KSum {
+    Real s = Real(0), c = Real(0);
+    __device__ __forceinline__ void add(Real x)
+    {
+        Real y = x - c;
+        Real t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ Real value() const { return s - c; }
+};
+template <> struct KSum<double> {
+    double s = 0.0;
+    __device__ __forceinline__ void add(double x) { s += x; }
+    __device__ __forceinline__ double value() const { return s; }
+};
+
+// Rounding of the warm-start shift and reference row: floor(x + 1/2).
+__device__ __forceinline__ int round_half_up(double x) { return (int)floor(x + 0.5); }
+
+__device__ __forceinline__ int solve_shift(int warm, double t_now, double t_prev, double dt)
+{
+    if (!warm) return 0;
+    double el = (t_now - t_prev) / dt;
+    if (!(el < 1.0e6)) el = 1.0e6;  // keeps the conversion to int defined
+    if (el < 0.0) el = 0.0;
+    const int s = round_half_up(el);
+    return s < 1 ? 1 : s;
+}
+
+}  // namespace mppi

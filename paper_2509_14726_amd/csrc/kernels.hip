@@ -1,0 +1,651 @@
+// Kernels of one MPPI step on gfx950 (wave64).
+//
+//   k_setup    once per context: problem tables -> device layout in Real
+//   k_sample   head (block 0) + noise -> clipped samples, Eq. (3)
+//   k_rollout  one sample per lane: RK4 rollout (Eq. (2)) with the per-step
+//              cost fused in (gate Eq. (6)-(7), tracking Eq. (8), contouring
+//              Eq. (9)), cost write and running minimum
+//   k_average  max-shifted softmax weights (Eq. (4)) and the weighted sum of
+//              the samples (Eq. (5)) over (step-tile, sample-tile) blocks;
+//              the last block merges the tiles in a fixed order, writes the
+//              update, the first input and the warm-start state
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+#include "noise.hpp"
+#include "rollout.hpp"
+
+namespace mppi {
+
+template <typename Real> struct Vec4;
+template <> struct Vec4<float> { using T = float4; };
+template <> struct Vec4<double> { using T = double4; };
+
+// ---------------------------------------------------------------- setup
+
+template <typename Real> __global__ void k_setup(KArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.G && a.gates_d) {
+        const double *g = a.gates_d + 4 * i;
+        Real *o = (Real *)a.gates_r + 8 * i;
+        const double cy = cos(g[3]), sy = sin(g[3]);
+        o[0] = (Real)g[0]; o[1] = (Real)g[1]; o[2] = (Real)g[2];
+        o[3] = (Real)cy; o[4] = (Real)sy;     // normal n
+        o[5] = (Real)(-sy); o[6] = (Real)cy;  // lateral h
+        o[7] = Real(0);
+    }
+    if (i < a.P && a.path_d) {
+        const double *p = a.path_d + 6 * i;
+        Real *o = (Real *)a.path_r + 8 * i;
+        for (int c = 0; c < 6; ++c) o[c] = (Real)p[c];
+        o[6] = o[7] = Real(0);
+    }
+    if (i < a.R && a.xref_r) {
+        // the FP64 reference was staged in the upper half of the same buffer
+        const double *r = (const double *)((const char *)a.xref_r + (size_t)a.R * 16 * sizeof(Real)) + 13 * i;
+        Real *o = (Real *)a.xref_r + 16 * i;
+        for (int c = 0; c < 13; ++c) o[c] = (Real)r[c];
+        o[13] = o[14] = o[15] = Real(0);
+    }
+}
+
+// ---------------------------------------------------------------- head
+
+// Measured gate pass x_prev -> x0 (same geometry as the in-horizon switch).
+__device__ bool gate_cross_d(const double *pa, const double *pb, const double *gate, double half)
+{
+    const double nx = cos(gate[3]), ny = sin(gate[3]);
+    const double hx = -sin(gate[3]), hy = cos(gate[3]);
+    const double sa = (pa[0] - gate[0]) * nx + (pa[1] - gate[1]) * ny;
+    const double sb = (pb[0] - gate[0]) * nx + (pb[1] - gate[1]) * ny;
+    if (!(sa < 0.0 && sb >= 0.0)) return false;
+    const double t = sa / (sa - sb);
+    const double y0 = pa[0] + t * (pb[0] - pa[0]);
+    const double y1 = pa[1] + t * (pb[1] - pa[1]);
+    const double y2 = pa[2] + t * (pb[2] - pa[2]);
+    const double lat = (y0 - gate[0]) * hx + (y1 - gate[1]) * hy;
+    const double ver = y2 - gate[2];
+    return fabs(lat) <= half && fabs(ver) <= half;
+}
+
+__device__ double wrap_len_d(double th, double L)
+{
+    double r = fmod(th, L);
+    if (r < 0.0) r += L;
+    if (r >= L) r -= L;
+    return r;
+}
+
+// Decides, once per solve, everything inherited from the previous solve:
+// warm-start shift, current gate and pass mask, start arc length, reference
+// row, last applied input.  Run by all threads of one block.
+__device__ void solve_head(const KArgs &a)
+{
+    __shared__ double s_d2[256];
+    __shared__ double s_th[256];
+    __shared__ int s_j[256];
+    const int tid = threadIdx.x;
+    const DevWarm *w = a.warm;
+    DevCur *c = a.cur;
+    const int warm = w->warm;
+
+    double theta0 = 0.0;
+    if (a.objective == OBJ_CONTOUR) {
+        const int P = a.P;
+        const double L = a.path_len, ds = L / (double)P;
+        const bool global = !warm;
+        const int W = a.proj_window;
+        int ic = 0;
+        if (!global) {
+            ic = (int)floor(wrap_len_d(w->theta0, L) / ds);
+            if (ic >= P) ic = P - 1;
+        }
+        const int count = global ? P : 2 * W + 1;
+        double best = INFINITY, best_th = 0.0;
+        int best_j = 0x7fffffff;
+        const double p0 = a.req[0], p1 = a.req[1], p2 = a.req[2];
+        for (int j = tid; j < count; j += blockDim.x) {
+            const int i = global ? j : (((ic + (j - W)) % P) + P) % P;
+            const int i1 = (i + 1) % P;
+            const double *A = a.path_d + 6 * i, *B = a.path_d + 6 * i1;
+            const double ab0 = B[0] - A[0], ab1 = B[1] - A[1], ab2 = B[2] - A[2];
+            const double ap0 = p0 - A[0], ap1 = p1 - A[1], ap2 = p2 - A[2];
+            const double l2 = ab0 * ab0 + ab1 * ab1 + ab2 * ab2;
+            double t = l2 > 0.0 ? (ap0 * ab0 + ap1 * ab1 + ap2 * ab2) / l2 : 0.0;
+            t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+            const double d0 = ap0 - t * ab0, d1 = ap1 - t * ab1, d2 = ap2 - t * ab2;
+            const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+            if (dd < best) { best = dd; best_th = ((double)i + t) * ds; best_j = j; }
+        }
+        s_d2[tid] = best; s_th[tid] = best_th; s_j[tid] = best_j;
+        __syncthreads();
+        for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+            if (tid < st) {
+                const double d_o = s_d2[tid + st];
+                const int j_o = s_j[tid + st];
+                if (d_o < s_d2[tid] || (d_o == s_d2[tid] && j_o < s_j[tid])) {
+                    s_d2[tid] = d_o; s_th[tid] = s_th[tid + st]; s_j[tid] = j_o;
+                }
+            }
+            __syncthreads();
+        }
+        theta0 = wrap_len_d(s_th[0], L);
+    }
+
+    for (int k = tid; k < a.N; k += blockDim.x) a.tickets[k] = 0u;
+    if (tid == 0) {
+        const double t_now = a.req[13];
+        int g0 = w->g0;
+        uint32_t allow[kMaskWords];
+        for (int j = 0; j < kMaskWords; ++j) allow[j] = warm ? w->allow[j] : 0xffffffffu;
+        if (warm && a.objective == OBJ_GATE && g0 >= 0 && g0 < a.G &&
+            gate_cross_d(w->x_prev, a.req, a.gates_d + 4 * g0, a.gate_half)) {
+            g0 = (g0 + 1) % a.G;
+            for (int j = 0; j < kMaskWords; ++j) allow[j] = 0xffffffffu;
+        }
+        int i0 = 0;
+        if (a.objective == OBJ_TRACK) {
+            double r = floor(t_now / a.ref_dt + 0.5);
+            if (!(r >= 0.0)) r = 0.0;
+            if (r > (double)(a.R - 1)) r = (double)(a.R - 1);
+            i0 = (int)r;
+        }
+        c->g0 = g0;
+        c->i0 = i0;
+        c->shift = solve_shift(warm, t_now, w->t_prev, a.dt);
+        c->warm = warm;
+        c->s = w->s;
+        c->ticket = 0u;
+        a.tickets[kNMax] = 0u;
+        c->jmin32 = ordered_bits(INFINITY);
+        c->jmin64 = ordered_bits((double)INFINITY);
+        for (int j = 0; j < kMaskWords; ++j) c->allow[j] = allow[j];
+        c->theta0 = theta0;
+        c->t_now = t_now;
+        for (int i = 0; i < 4; ++i) c->u_prev[i] = warm ? a.wU[i] : a.hover;
+        c->v_prev = warm ? a.wV[0] : 0.0;
+        c->J_nom = 0.0;
+        for (int i = 0; i < 13; ++i) c->x0[i] = a.req[i];
+    }
+}
+
+// ---------------------------------------------------------------- sample
+
+template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_sample(KArgs a)
+{
+    if (blockIdx.x == 0 && blockIdx.y == 0) solve_head(a);
+
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (m > a.K || k >= a.N) return;
+
+    // nominal of this solve: the previous solution shifted, or hover (cold)
+    const DevWarm *w = a.warm;
+    const int warm = w->warm;
+    const int shift = solve_shift(warm, a.req[13], w->t_prev, a.dt);
+    int src = k + shift;
+    if (src > a.N - 1) src = a.N - 1;
+    Real us[4];
+    for (int i = 0; i < 4; ++i) us[i] = warm ? (Real)a.wU[4 * src + i] : (Real)a.hover;
+    const Real vs = warm ? (Real)a.wV[src] : Real(0);
+    const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max;
+
+    typedef typename Vec4<Real>::T R4;
+    if (m == a.K) {  // the noise-free sample
+        R4 o;
+        o.x = clampT(us[0], tmin, tmax); o.y = clampT(us[1], tmin, tmax);
+        o.z = clampT(us[2], tmin, tmax); o.w = clampT(us[3], tmin, tmax);
+        ((R4 *)a.nomU)[k] = o;
+        if (HAS_V) ((Real *)a.nomV)[k] = clampT(vs, Real(0), (Real)a.v_max);
+        return;
+    }
+    const uint32_t s = w->s;
+    const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, s, 0u, a.seed_lo, a.seed_hi);
+    R4 o;
+    o.x = clampT(us[0] + (Real)a.sigma[0] * z.z0, tmin, tmax);
+    o.y = clampT(us[1] + (Real)a.sigma[1] * z.z1, tmin, tmax);
+    o.z = clampT(us[2] + (Real)a.sigma[2] * z.z2, tmin, tmax);
+    o.w = clampT(us[3] + (Real)a.sigma[3] * z.z3, tmin, tmax);
+    const size_t idx = (size_t)k * (size_t)a.K + (size_t)m;
+    ((R4 *)a.ctrl)[idx] = o;
+    if (HAS_V) {
+        const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, s, 1u, a.seed_lo, a.seed_hi);
+        ((Real *)a.vctrl)[idx] = clampT(vs + (Real)a.sigma_v * zv, Real(0), (Real)a.v_max);
+    }
+}
+
+// ---------------------------------------------------------------- rollout
+
+__device__ __forceinline__ void wave_min_atomic(uint32_t v, uint32_t *dst)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMin(dst, v);
+}
+__device__ __forceinline__ void wave_min_atomic(unsigned long long v, unsigned long long *dst)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMin(dst, v);
+}
+
+template <typename Real> struct GateRegs {
+    Real cx, cy, cz, nx, ny, hx, hy;
+    __device__ __forceinline__ void load(const Real *tab, int g)
+    {
+        const Real *r = tab + 8 * g;
+        cx = r[0]; cy = r[1]; cz = r[2]; nx = r[3]; ny = r[4]; hx = r[5]; hy = r[6];
+    }
+};
+
+template <int OBJ, typename Real> __global__ __launch_bounds__(64) void k_rollout(KArgs a)
+{
+    typedef typename Vec4<Real>::T R4;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int K = a.K, N = a.N;
+    const bool active = m <= K;
+    const bool nominal = m == K;
+    const DevCur *cur = a.cur;
+    Real Jfinal = Real(0);
+
+    if (active) {
+        const Model<Real> M(a);
+        const Real dt = (Real)a.dt;
+        const Real w_max = (Real)a.w_max, w_lim = (Real)a.w_lim;
+        State<Real> st;
+        load_state(st, cur->x0);
+        KSum<Real> J;
+
+        const R4 *urow = nominal ? (const R4 *)a.nomU : (const R4 *)a.ctrl + m;
+        const size_t ustride = nominal ? 1 : (size_t)K;
+        const Real *vrow = nullptr;
+        if (OBJ == OBJ_CONTOUR) vrow = nominal ? (const Real *)a.nomV : (const Real *)a.vctrl + m;
+
+        // gate objective state
+        const Real *gtab = (const Real *)a.gates_r;
+        GateRegs<Real> gt, g0r;
+        int g = 0, passes = 0;
+        Real q_near = 0, r_near2 = 0, half = 0;
+        if (OBJ == OBJ_GATE) {
+            g = cur->g0;
+            gt.load(gtab, g);
+            g0r = gt;
+            q_near = (Real)a.q_near;
+            r_near2 = (Real)(a.r_near * a.r_near);
+            half = (Real)a.gate_half;
+        }
+        // tracking / contouring state
+        Real up[4];
+        for (int i = 0; i < 4; ++i) up[i] = (Real)cur->u_prev[i];
+        Real vp = (Real)cur->v_prev;
+        Real rdt[4];
+        for (int i = 0; i < 4; ++i) rdt[i] = (Real)(a.R_dT[i] / (a.dt * a.dt));
+        const int i0 = cur->i0;
+        const Real *xref = (const Real *)a.xref_r;
+        const Real *path = (const Real *)a.path_r;
+        // arc length theta = th_hi + th_lo (th_lo stays 0 in binary64)
+        Real th_hi = 0, th_lo = 0;
+        Real ds = 0, inv_ds = 0, L = 0;
+        if (OBJ == OBJ_CONTOUR) {
+            th_hi = (Real)cur->theta0;
+            if (sizeof(Real) == 4) th_lo = (Real)(cur->theta0 - (double)th_hi);
+            L = (Real)a.path_len;
+            ds = (Real)(a.path_len / (double)a.P);
+            inv_ds = (Real)((double)a.P / a.path_len);
+        }
+
+        R4 u = urow[0];
+        for (int k = 0; k < N; ++k) {
+            const R4 un = (k + 1 < N) ? urow[(size_t)(k + 1) * ustride] : u;
+            Real term = Real(0);
+
+            // ---- stage terms at state k
+            Real ax = 0, ay = 0, az = 0;  // p_k - c_g (gate)
+            if (OBJ == OBJ_GATE) {
+                ax = (st.x[0] - gt.cx) + lo_of(st, 0);
+                ay = (st.x[1] - gt.cy) + lo_of(st, 1);
+                az = (st.x[2] - gt.cz) + lo_of(st, 2);
+                const Real bx = (st.x[0] - g0r.cx) + lo_of(st, 0);
+                const Real by = (st.x[1] - g0r.cy) + lo_of(st, 1);
+                const Real bz = (st.x[2] - g0r.cz) + lo_of(st, 2);
+                const Real d2 = bx * bx + by * by + bz * bz;
+                if (d2 < r_near2) term += q_near * d2;  // Eq. (7), current gate
+                if (nominal) a.front8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+            } else if (OBJ == OBJ_TRACK) {
+                int r = i0 + k;
+                if (r > a.R - 1) r = a.R - 1;
+                const Real *xr = xref + 16 * r;
+#pragma unroll
+                for (int i = 0; i < 13; ++i) {
+                    const Real e = (st.x[i] - xr[i]) + lo_of(st, i);
+                    term += (Real)a.Q[i] * e * e;
+                }
+                const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
+                term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+            } else {  // contouring
+                const Real fl = floor(th_hi * inv_ds);
+                const Real f = ((th_hi - fl * ds) + th_lo) * inv_ds;
+                // table row of theta, always inside [0, P)
+                int i = (fl >= Real(0) && fl < Real(1 << 30)) ? ((int)fl % a.P) : 0;
+                const int i1 = (i + 1 == a.P) ? 0 : i + 1;
+                const Real *A = path + 8 * i, *B = path + 8 * i1;
+                const Real g1 = Real(1) - f;
+                const Real px = g1 * A[0] + f * B[0], py = g1 * A[1] + f * B[1], pz = g1 * A[2] + f * B[2];
+                Real tx = g1 * A[3] + f * B[3], ty = g1 * A[4] + f * B[4], tz = g1 * A[5] + f * B[5];
+                const Real tn = Real(1) / sqrt(tx * tx + ty * ty + tz * tz);
+                tx *= tn; ty *= tn; tz *= tn;
+                const Real ex = (st.x[0] - px) + lo_of(st, 0);
+                const Real ey = (st.x[1] - py) + lo_of(st, 1);
+                const Real ez = (st.x[2] - pz) + lo_of(st, 2);
+                const Real et = ex * tx + ey * ty + ez * tz;
+                const Real lx = et * tx, ly = et * ty, lz = et * tz;
+                const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
+                term += (Real)a.q_l * (lx * lx + ly * ly + lz * lz);
+                term += (Real)a.q_c * (cxe * cxe + cye * cye + cze * cze);
+                term += (Real)a.Q_w[0] * st.x[10] * st.x[10] + (Real)a.Q_w[1] * st.x[11] * st.x[11] +
+                        (Real)a.Q_w[2] * st.x[12] * st.x[12];
+                const Real vk = vrow[(size_t)k * ustride];
+                const Real dv = vk - vp;
+                term += (Real)(a.r_dv / (a.dt * a.dt)) * dv * dv;
+                const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
+                term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                term -= (Real)a.mu * vk;
+                vp = vk;
+                {   // theta_{k+1} = theta_k + V_k dt (mod L), compensated in binary32
+                    const Real y = vk * dt + th_lo;
+                    const Real t = th_hi + y;
+                    th_lo = (sizeof(Real) == 4) ? y - (t - th_hi) : Real(0);
+                    th_hi = t;
+                    if (th_hi >= L) th_hi -= L;
+                }
+            }
+
+            // ---- dynamics
+            const StepInput<Real> in = step_input(M, u.x, u.y, u.z, u.w);
+            Real dx[13];
+            rk4_increment(M, in, st.x, dt, dx);
+            commit(st, dx);
+
+            // ---- progress and switching (gate)
+            if (OBJ == OBJ_GATE) {
+                // |p_{k+1} - c|^2 - |p_k - c|^2 = dp . (2 (p_k - c) + dp)
+                term += dx[0] * (Real(2) * ax + dx[0]) + dx[1] * (Real(2) * ay + dx[1]) +
+                        dx[2] * (Real(2) * az + dx[2]);
+                const Real sa = ax * gt.nx + ay * gt.ny;
+                const Real sb = (ax + dx[0]) * gt.nx + (ay + dx[1]) * gt.ny;
+                if (sa < Real(0) && sb >= Real(0)) {
+                    const Real t = sa / (sa - sb);
+                    const Real yx = ax + t * dx[0], yy = ay + t * dx[1], yz = az + t * dx[2];
+                    const Real lat = yx * gt.hx + yy * gt.hy;
+                    const bool inside = fabs(lat) <= half && fabs(yz) <= half;
+                    const int j = k + 1;
+                    const bool allowed = passes > 0 || ((cur->allow[j >> 5] >> (j & 31)) & 1u);
+                    if (inside && allowed) {
+                        g = (g + 1 == a.G) ? 0 : g + 1;
+                        ++passes;
+                        gt.load(gtab, g);
+                    }
+                }
+            }
+            // ---- body-rate penalty on the new state
+#pragma unroll
+            for (int i = 10; i < 13; ++i) {
+                const Real e = fmax(fabs(st.x[i]) - w_max, Real(0));
+                term += w_lim * e * e;
+            }
+            J.add(term);
+            up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
+            u = un;
+        }
+        if (OBJ == OBJ_TRACK) {
+            int r = i0 + N;
+            if (r > a.R - 1) r = a.R - 1;
+            const Real *xr = xref + 16 * r;
+            Real term = 0;
+#pragma unroll
+            for (int i = 0; i < 13; ++i) {
+                const Real e = (st.x[i] - xr[i]) + lo_of(st, i);
+                term += (Real)a.QN[i] * e * e;
+            }
+            J.add(term);
+        }
+        if (OBJ == OBJ_GATE && nominal) {
+            const Real bx = (st.x[0] - g0r.cx) + lo_of(st, 0);
+            const Real by = (st.x[1] - g0r.cy) + lo_of(st, 1);
+            a.front8[N] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+        }
+        Jfinal = J.value();
+        if (nominal) a.cur->J_nom = (double)Jfinal;
+        else ((Real *)a.J)[m] = Jfinal;
+    }
+    // running minimum over the finite sample costs
+    const bool use = active && !nominal && isfinite(Jfinal);
+    if (sizeof(Real) == 4) {
+        const uint32_t v = use ? ordered_bits((float)Jfinal) : ordered_bits(INFINITY);
+        wave_min_atomic(v, &a.cur->jmin32);
+    } else {
+        const unsigned long long v = use ? ordered_bits((double)Jfinal) : ordered_bits((double)INFINITY);
+        wave_min_atomic(v, &a.cur->jmin64);
+    }
+}
+
+// ---------------------------------------------------------------- average
+
+template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block (mt, k) forms, for sample tile mt of step k,
+//   sum_m w~_m U^m_k  (C channels)   and, for k == 0,  sum_m w~_m, sum_m w~_m^2
+// with w~_m = exp(-(J_m - J_min)/lambda) (0 for non-finite J_m).  The last
+// block of step k to finish adds the tiles of that step in tile order; the
+// last step to be merged runs the tail: U = sums / S, first input, report and
+// warm-start hand-over.  Every sum has a fixed order, so results repeat bit
+// for bit.
+template <typename Real, typename Acc, bool HAS_V>
+__global__ __launch_bounds__(256) void k_average(KArgs a)
+{
+    constexpr int C = HAS_V ? 5 : 4;
+    constexpr int NV = C + 2;
+    typedef typename Vec4<Real>::T R4;
+    __shared__ Acc s_red[4][NV];
+    __shared__ unsigned s_last;
+
+    const int tid = threadIdx.x;
+    const int K = a.K, N = a.N;
+    const int mt = blockIdx.x, k = blockIdx.y;
+    const int n_mt = a.n_mt;
+    const int m_lo = mt * a.mt_size;
+    const int m_hi = min(K, m_lo + a.mt_size);
+    const Real jmin = sizeof(Real) == 4 ? (Real)from_ordered(a.cur->jmin32)
+                                        : (Real)from_ordered(a.cur->jmin64);
+    const Real inv_lambda = (Real)(1.0 / a.lambda);
+    const Real *J = (const Real *)a.J;
+    const R4 *ctrl = (const R4 *)a.ctrl + (size_t)k * (size_t)K;
+    const Real *vctrl = HAS_V ? (const Real *)a.vctrl + (size_t)k * (size_t)K : nullptr;
+
+    Acc v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = Acc(0);
+    for (int m = m_lo + tid; m < m_hi; m += 256) {
+        const Real Jm = J[m];
+        const Real wr = isfinite(Jm) ? exp(-(Jm - jmin) * inv_lambda) : Real(0);
+        const Acc w = (Acc)wr;
+        const R4 u = ctrl[m];
+        v[0] += w * (Acc)u.x;
+        v[1] += w * (Acc)u.y;
+        v[2] += w * (Acc)u.z;
+        v[3] += w * (Acc)u.w;
+        if (HAS_V) v[4] += w * (Acc)vctrl[m];
+        v[C] += w;
+        v[C + 1] += w * w;
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const Acc r = wave_sum(v[i]);
+        if (lane == 0) s_red[wv][i] = r;
+    }
+    __syncthreads();
+    Acc *part = (Acc *)a.part;                          // [N][n_mt][C]
+    Acc *part_den = part + (size_t)N * n_mt * C;        // [n_mt][2]
+    Acc *stage = part_den + 2 * (size_t)n_mt;           // [N][C] step sums, then [2] S, S2
+    if (tid < NV) {
+        const Acc r = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
+        if (tid < C) part[((size_t)k * n_mt + mt) * C + tid] = r;
+        else if (k == 0) part_den[2 * mt + (tid - C)] = r;
+    }
+
+    // last tile of this step: merge the step
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned t = __hip_atomic_fetch_add(&a.tickets[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (t == (unsigned)n_mt - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (tid < C) {
+        Acc s = 0;
+        for (int t = 0; t < n_mt; ++t) s += part[((size_t)k * n_mt + t) * C + tid];
+        stage[(size_t)k * C + tid] = s;
+    } else if (k == 0 && tid < C + 2) {
+        Acc s = 0;
+        for (int t = 0; t < n_mt; ++t) s += part_den[2 * t + (tid - C)];
+        stage[(size_t)N * C + (tid - C)] = s;
+    }
+
+    // last merged step: the tail
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned t = __hip_atomic_fetch_add(&a.tickets[kNMax], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (t == (unsigned)N - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+
+    const Acc den = stage[(size_t)N * C], den2 = stage[(size_t)N * C + 1];
+    const bool ok = isfinite((double)jmin) && den > Acc(0);
+    DevWarm *w = a.warm;
+    const DevCur *cur = a.cur;
+    if (ok) {
+        for (int idx = tid; idx < N * C; idx += 256) {
+            const int kk = idx / C, ch = idx % C;
+            const double u = (double)(stage[idx] / den);
+            if (ch < 4) a.wU[4 * kk + ch] = u;
+            else a.wV[kk] = u;
+        }
+        if (!HAS_V)
+            for (int kk = tid; kk < N; kk += 256) a.wV[kk] = 0.0;
+    }
+    if (tid < kMaskWords && ok) {
+        uint32_t word = 0u;
+        if (a.objective == OBJ_GATE) {
+            for (int b = 0; b < 32; ++b) {
+                const int j = tid * 32 + b;
+                if (j <= N && a.front8[j]) word |= 1u << b;
+            }
+        } else {
+            word = 0xffffffffu;
+        }
+        w->allow[tid] = word;
+    }
+    if (tid == 0) {
+        DevResult *r = a.res;
+        for (int i = 0; i < 4; ++i) {
+            const double u0 = ok ? (double)(stage[i] / den) : (double)NAN;
+            r->u0[i] = u0;
+            if (a.u0_out) a.u0_out[i] = u0;
+        }
+        r->J_min = (double)jmin;
+        r->S = (double)den;
+        r->S2 = (double)den2;
+        r->ess = ok ? (double)den * (double)den / (double)den2 : 0.0;
+        r->J_nom = cur->J_nom;
+        r->theta0 = cur->theta0;
+        r->status = ok ? ST_OK : ST_NONFINITE;
+        r->g0 = cur->g0;
+        r->i0 = cur->i0;
+        r->shift = cur->shift;
+        r->s = cur->s;
+        if (ok) {
+            w->warm = 1;
+            w->g0 = cur->g0;
+            w->s = cur->s + 1u;
+            w->N = N;
+            w->t_prev = cur->t_now;
+            w->theta0 = cur->theta0;
+            for (int i = 0; i < 13; ++i) w->x_prev[i] = cur->x0[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launches
+
+template <typename Real> static hipError_t launch_setup_t(const KArgs &a, hipStream_t st)
+{
+    int n = a.G > a.P ? a.G : a.P;
+    if (a.R > n) n = a.R;
+    if (n < 1) n = 1;
+    hipLaunchKernelGGL(k_setup<Real>, dim3((n + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const KArgs &a, bool fp64, hipStream_t st)
+{
+    return fp64 ? launch_setup_t<double>(a, st) : launch_setup_t<float>(a, st);
+}
+
+template <typename Real, typename Acc, bool HAS_V>
+static hipError_t launch_average_t(const KArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_average<Real, Acc, HAS_V>), dim3(a.n_mt, a.N), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename Real, int OBJ>
+static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hipEvent_t *ev)
+{
+    constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
+    const dim3 gs((a.K + 1 + 255) / 256, a.N);
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL((k_rollout<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(64), 0, st, a);
+    if (ev) (void)hipEventRecord(ev[2], st);
+    hipError_t e = (acc64 || sizeof(Real) == 8) ? launch_average_t<Real, double, HAS_V>(a, st)
+                                                : launch_average_t<Real, float, HAS_V>(a, st);
+    if (ev) (void)hipEventRecord(ev[3], st);
+    return e;
+}
+
+hipError_t launch_solve(const KArgs &a, bool fp64, bool acc64, hipStream_t st, hipEvent_t *ev)
+{
+    if (fp64) {
+        switch (a.objective) {
+        case OBJ_CONTOUR: return launch_solve_t<double, OBJ_CONTOUR>(a, true, st, ev);
+        case OBJ_TRACK: return launch_solve_t<double, OBJ_TRACK>(a, true, st, ev);
+        default: return launch_solve_t<double, OBJ_GATE>(a, true, st, ev);
+        }
+    }
+    switch (a.objective) {
+    case OBJ_CONTOUR: return launch_solve_t<float, OBJ_CONTOUR>(a, acc64, st, ev);
+    case OBJ_TRACK: return launch_solve_t<float, OBJ_TRACK>(a, acc64, st, ev);
+    default: return launch_solve_t<float, OBJ_GATE>(a, acc64, st, ev);
+    }
+}
+
+}  // namespace mppi

@@ -1,0 +1,19 @@
+// Launch entry points of the device code (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace mppi {
+
+// Convert the problem tables of a context to the device layout.
+hipError_t launch_setup(const KArgs &a, bool fp64, hipStream_t st);
+
+// Enqueue one MPPI step: sample (with the head), rollout, average (+ tail).
+// acc64 selects binary64 accumulation of the weighted average.
+// When ev is non-null, ev[0..3] are recorded before the sample, rollout and
+// average kernels and after the average kernel.
+hipError_t launch_solve(const KArgs &a, bool fp64, bool acc64, hipStream_t st, hipEvent_t *ev = nullptr);
+
+}  // namespace mppi

@@ -1,0 +1,110 @@
+"""Shared helpers of the parity tests: build the device solver and the oracle
+problem from one seeded workload, and compare their results with the
+tolerances stated here.
+
+Tolerances (derived in the design notes):
+  FP64 device path, end to end:
+      costs |dJ| <= 1e-9 * max(|J|, 1), controls |dU| <= 1e-9 * max(|U|, sigma)
+  FP32 device path, stage by stage:
+      costs   |dJ| <= 1e-4 * max(|J|, 1) against the oracle's costs;
+      update  |dU| <= 1e-4 * max(|U|, sigma) against the oracle's weights and
+              average (Eq. (4)-(5)) formed from the device's costs.
+  The FP32 end-to-end control error (oracle costs in, oracle update out) is
+  reported, not gated: it is the cost error times the sensitivity of the
+  softmax average, (1/lambda) * sum_m w_m |dJ_m| |U_m - U|, which exceeds
+  1e-4 whenever near-tied samples meet small lambda.
+A sample whose oracle decision margin (distance of a gate-plane, aperture or
+near-radius test to its threshold) is below EPS_DEC of the precision is
+ambiguous: both outcomes are correct.  Such samples are excluded from the
+per-sample cost check and the oracle's weights are recomputed with the
+device's cost for them (decision replay); everything else must match as is.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_2509_14726_amd import mppi as M
+from paper_2509_14726_amd import synth
+
+TOL = {M.FP64: 1e-9, M.FP32: 1e-4}
+EPS_DEC = {M.FP64: 1e-9, M.FP32: 1e-4}
+
+
+def build_pair(w: dict, precision: int, n_threads: int = 8):
+    """(device solver, oracle problem) over the same workload."""
+    prm = w["params"]
+    dev = M.Solver(w["quad"], prm, gates=w["gates"], path=w.get("path"), path_len=w.get("path_len", 0.0),
+                   xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0), precision=precision)
+    oprm = dict(prm, eps_dec=EPS_DEC[precision], n_threads=n_threads)
+    orc = O.Problem(w["quad"], oprm, gates=w["gates"], path=w.get("path"),
+                    path_len=w.get("path_len", 0.0), xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0))
+    return dev, orc
+
+
+def warm_to_oracle(wd: M.mppi_warm, orc: O.Problem) -> O.Warm:
+    """Oracle warm state equal to the device's exported warm state."""
+    o = orc.warm(wd.g0)
+    o.warm = wd.warm
+    o.s = wd.solve_index
+    for j in range(O.MASK_WORDS):
+        o.allow[j] = wd.allow[j]
+    o.t_prev = wd.t_prev
+    o.x_prev[:] = list(wd.x_prev)
+    o.theta0 = wd.theta0
+    o.U[:] = list(wd.U)
+    o.V[:] = list(wd.V)
+    return o
+
+
+def solve_and_compare(dev: M.Solver, orc: O.Problem, x0, t_now: float, precision: int,
+                      sigma: float = 1.0, check_warm: bool = True):
+    """Import the device's warm state into the oracle, solve on both sides,
+    compare (with decision replay), then check the warm states they hand on."""
+    tol = TOL[precision]
+    wd = dev.get_warm()
+    ow = warm_to_oracle(wd, orc)
+    ow_replay = warm_to_oracle(wd, orc)
+    u0, U, info = dev.solve(x0, t_now)
+    Jd, _ = dev.read_samples()
+    r = orc.solve(ow, x0, t_now)
+    assert r["status"] == O.OK
+    assert info["g0"] == r["g0"] and info["shift"] == r["shift"] and info["i0"] == r["i0"]
+    assert info["solve_index"] == wd.solve_index
+    amb = r["margin"] < EPS_DEC[precision]
+    scale = np.maximum(np.abs(r["J"]), 1.0)
+    err_J = np.abs(Jd - r["J"]) / scale
+    bad = np.where((err_J > tol) & ~amb)[0]
+    assert bad.size == 0, f"{bad.size} costs off, worst {err_J[bad].max():.3e} at m={bad[:5]}"
+    ref = r
+    e2e = float((np.abs(U - r["U"]) / np.maximum(np.abs(r["U"]), sigma)).max())
+    if precision == M.FP32:
+        # the update stage, fed with the device's costs
+        ref = orc.solve(ow_replay, x0, t_now, J_rep=Jd, rep_mask=np.ones(Jd.size, np.uint8))
+        assert ref["status"] == O.OK
+    elif amb.any():
+        ref = orc.solve(ow_replay, x0, t_now, J_rep=Jd, rep_mask=amb.astype(np.uint8))
+        assert ref["status"] == O.OK
+    err_U = np.abs(U - ref["U"]) / np.maximum(np.abs(ref["U"]), sigma)
+    assert err_U.max() <= tol, f"controls off by {err_U.max():.3e}"
+    np.testing.assert_allclose(u0, ref["U"][0], rtol=0, atol=tol * max(np.abs(ref["U"][0]).max(), sigma))
+    err_min = abs(info["J_min"] - ref["J_min"]) / max(abs(ref["J_min"]), 1.0)
+    assert err_min <= tol, err_min
+    assert abs(info["ess"] - ref["ess"]) <= tol * max(ref["ess"], 1.0) * 10 + 1e-12, (info["ess"], ref["ess"])
+    if np.isfinite(r["J_nom"]):
+        assert abs(info["J_nom"] - r["J_nom"]) <= tol * max(abs(r["J_nom"]), 1.0)
+    if orc.cfg.objective == O.OBJ_CONTOUR:
+        assert abs(info["theta0"] - r["theta0"]) <= 1e-9 * max(orc.cfg.path_len, 1.0)
+    if check_warm:
+        wn = dev.get_warm()
+        assert wn.warm == 1 and wn.g0 == r["g0"] and wn.solve_index == wd.solve_index + 1
+        # the pass mask handed on: bits whose nominal state lies within eps of
+        # the gate plane may differ
+        n = orc.cfg.N + 1
+        dbits = O.mask_bits(list(wn.allow), n)
+        obits = O.mask_bits(r["front"], n)
+        famb = O.mask_bits(r["front_amb"], n)
+        assert np.array_equal(dbits[~famb], obits[~famb])
+        np.testing.assert_allclose(np.array(wn.U[:4 * orc.cfg.N]).reshape(-1, 4), U, rtol=0, atol=0)
+    return dict(err_J=float(err_J[~amb].max()) if (~amb).any() else 0.0, err_U=float(err_U.max()),
+                err_U_e2e=e2e, n_amb=int(amb.sum()), info=info, ref=ref, J=Jd, U=U)

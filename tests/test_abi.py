@@ -1,0 +1,81 @@
+"""CPU checks of the C ABI boundary: the library loads, exports every entry
+point that include/mppi.h declares, the binding mirrors the header's structs,
+and the host-only paths (argument validation, status strings, plant step)
+behave as documented.  No compute call needs a GPU here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_14726_amd import mppi as M
+from paper_2509_14726_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mppi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mppi_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 13
+    lib = C.CDLL(M.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(M.EXPORTS) == names
+
+
+def test_struct_sizes_match_header_layout():
+    # sizes implied by the C declarations (x86-64 ABI)
+    assert C.sizeof(M.mppi_quad) == 8 * 13
+    assert C.sizeof(M.mppi_info) == 5 * 8 + 6 * 4
+    assert C.sizeof(M.mppi_warm) == 4 * 4 + 9 * 4 + 4 + 8 + 13 * 8 + 8 + 256 * 4 * 8 + 256 * 8
+    assert M.mppi_params.R_dT.offset == 4 * 4 + 8 * 2 + 8 * 4 + 8 + 8 + 8 * 3 + 13 * 8 * 2
+
+
+def test_status_strings():
+    assert M.lib.mppi_status_string(M.E_NONFINITE) == b"MPPI_E_NONFINITE"
+    assert M.lib.mppi_status_string(M.OK) == b"MPPI_OK"
+    assert M.lib.mppi_status_string(-99) == b"MPPI_E_UNKNOWN"
+
+
+@pytest.mark.parametrize("over,frag", [
+    (dict(K=0), "K=0"), (dict(N=0), "N=0"), (dict(N=257), "N=257"), (dict(dt=0.0), "dt"),
+    (dict(**{"lambda": -1.0}), "lambda"), (dict(sigma=(1.0, -1.0, 1.0, 1.0)), "sigma[1]"),
+    (dict(objective=7), "objective"),
+])
+def test_create_rejects_invalid_parameters_before_touching_the_device(over, frag):
+    w = synth.single_solve_workload(K=64, N=10)
+    prm = dict(w["params"], **over)
+    with pytest.raises(M.MppiError) as e:
+        M.Solver(w["quad"], prm, gates=w["gates"])
+    assert e.value.status == M.E_INVAL
+    assert frag in str(e.value)
+
+
+def test_create_rejects_missing_problem_data():
+    w = synth.single_solve_workload(K=64, N=10)
+    with pytest.raises(M.MppiError):
+        M.Solver(w["quad"], w["params"])  # gate objective without gates
+    prm = dict(w["params"], objective=M.OBJ_CONTOUR)
+    with pytest.raises(M.MppiError):
+        M.Solver(w["quad"], prm, gates=w["gates"])  # no path
+    with pytest.raises(M.MppiError):
+        M.Solver(w["quad"], prm, path=np.zeros((10, 6)), path_len=1.0)  # v_max dt >= L
+
+
+def test_plant_step_free_fall_and_hover():
+    q = synth.QUAD
+    x = np.zeros(13); x[6] = 1.0; x[2] = 10.0; x[3] = 1.0
+    y = M.plant_step(q, x, np.zeros(4), 0.1, 3)
+    np.testing.assert_allclose(y[0:3], [0.1, 0.0, 10.0 - 0.5 * 9.81 * 0.01], atol=1e-13)
+    h = synth.hover_thrust()
+    x = np.zeros(13); x[6] = 1.0
+    np.testing.assert_allclose(M.plant_step(q, x, np.full(4, h), 0.02, 1), x, atol=1e-14)
+    with pytest.raises(M.MppiError):
+        M.plant_step(q, x, np.zeros(4), 0.02, 0)

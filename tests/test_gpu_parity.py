@@ -1,0 +1,146 @@
+"""Parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Every case prints its name and sizes before it touches the GPU.  Tolerances
+and the decision-replay rule are stated in tests/parity.py.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_14726_amd import mppi as M
+from paper_2509_14726_amd import synth
+from tests.parity import EPS_DEC, TOL, build_pair, solve_and_compare, warm_to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _workload(K, N, objective="gate", seed=1, track_seed=1, **over):
+    return synth.single_solve_workload(K=K, N=N, objective=objective, seed=seed, track_seed=track_seed,
+                                       **over)
+
+
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+@pytest.mark.parametrize("seed,lam", [(1, 1.0), (2, 1.0), (3, 200.0)])
+def test_single_solve_gate(precision, seed, lam):
+    say("single gate solve", precision, seed, lam, "K=1024 N=50")
+    w = _workload(1024, 50, seed=seed, **{"lambda": lam})
+    dev, orc = build_pair(w, precision)
+    st = solve_and_compare(dev, orc, w["x0"], 0.0, precision)
+    say("  err_J", st["err_J"], "err_U", st["err_U"], "e2e", st["err_U_e2e"], "ambiguous", st["n_amb"])
+    dev.close()
+
+
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
+def test_closed_loop_warm_start(precision, objective):
+    """A few control steps with the host plant in the loop: each step is
+    compared from the same inherited (warm) state on both sides."""
+    say("closed loop", objective, precision, "K=2048 N=60")
+    w = _workload(2048, 60, objective=objective, seed=5, track_seed=2, **{"lambda": 50.0})
+    dev, orc = build_pair(w, precision)
+    x = w["x0"].copy()
+    dt = w["params"]["dt"]
+    for step in range(6):
+        st = solve_and_compare(dev, orc, x, step * dt, precision)
+        say("  step", step, "err_J", st["err_J"], "err_U", st["err_U"], "e2e", st["err_U_e2e"])
+        u0 = st["U"][0]
+        x = M.plant_step(w["quad"], x, u0, dt, 4)
+    dev.close()
+
+
+@pytest.mark.parametrize("K,N", [(1, 1), (1, 9), (63, 5), (65, 17), (257, 33), (1000, 3), (130, 256)])
+def test_ragged_and_extreme_shapes(K, N):
+    say("shape", K, N)
+    w = _workload(K, N, seed=7, **{"lambda": 30.0})
+    dev, orc = build_pair(w, M.FP64)
+    solve_and_compare(dev, orc, w["x0"], 0.0, M.FP64)
+    # a second, warm solve through the same context
+    solve_and_compare(dev, orc, w["x0"], w["params"]["dt"], M.FP64)
+    dev.close()
+
+
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+def test_zero_noise_returns_nominal(precision):
+    say("zero noise", precision)
+    w = _workload(512, 40, sigma=(0.0, 0.0, 0.0, 0.0))
+    dev, orc = build_pair(w, precision)
+    u0, U, info = dev.solve(w["x0"], 0.0)
+    J, _ = dev.read_samples()
+    assert np.all(J == J[0])
+    np.testing.assert_allclose(U, synth.hover_thrust(), rtol=0, atol=1e-6 if precision == M.FP32 else 1e-14)
+    assert abs(info["J_nom"] - J[0]) <= 1e-6 * max(1.0, abs(J[0]))
+    dev.close()
+
+
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+def test_deterministic_repeat(precision):
+    say("determinism", precision)
+    w = _workload(3000, 70, seed=9, **{"lambda": 10.0})
+    outs = []
+    for _ in range(2):
+        dev, _ = build_pair(w, precision)
+        u0, U, info = dev.solve(w["x0"], 0.0)
+        J, _ = dev.read_samples()
+        outs.append((U.copy(), J.copy()))
+        dev.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_metric_configuration_fp32():
+    """K = 8192, N = 100: the configuration the benchmark times."""
+    say("metric configuration fp32 K=8192 N=100")
+    w = _workload(8192, 100, seed=1)
+    dev, orc = build_pair(w, M.FP32, n_threads=16)
+    st = solve_and_compare(dev, orc, w["x0"], 0.0, M.FP32)
+    say("  err_J", st["err_J"], "err_U", st["err_U"], "e2e", st["err_U_e2e"], "ambiguous", st["n_amb"])
+    st = solve_and_compare(dev, orc, w["x0"], w["params"]["dt"], M.FP32)
+    dev.close()
+
+
+def test_nonfinite_costs_leave_warm_state():
+    say("nonfinite")
+    w = _workload(256, 20)
+    dev, _ = build_pair(w, M.FP32)
+    dev.solve(w["x0"], 0.0)
+    before = bytes(dev.get_warm())
+    x = w["x0"].copy()
+    x[3] = 1e38  # positions overflow within the horizon
+    with pytest.raises(M.MppiError) as e:
+        dev.solve(x, 0.02)
+    assert e.value.status == M.E_NONFINITE
+    assert bytes(dev.get_warm()) == before
+    dev.close()
+
+
+def test_device_entry_point_matches_host_entry_point():
+    say("solve_device vs solve")
+    import torch
+    w = _workload(1500, 45, seed=4, **{"lambda": 20.0})
+    a, _ = build_pair(w, M.FP32)
+    stream = torch.cuda.current_stream().cuda_stream
+    b = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32, stream=stream,
+                 allocator=M.TorchAllocator(0))
+    req = torch.zeros(M.REQ_DOUBLES, dtype=torch.float64, device="cuda")
+    u0d = torch.zeros(4, dtype=torch.float64, device="cuda")
+    x = w["x0"].copy()
+    for step in range(3):
+        t = step * w["params"]["dt"]
+        u0, U, info = a.solve(x, t)
+        req[:13] = torch.from_numpy(x)
+        req[13] = t
+        b.solve_device(req.data_ptr(), u0d.data_ptr())
+        st, info_b = b.read_info()
+        assert st == M.OK
+        assert np.array_equal(u0d.cpu().numpy(), u0)
+        assert info_b["J_min"] == info["J_min"] and info_b["g0"] == info["g0"]
+        x = M.plant_step(w["quad"], x, u0, w["params"]["dt"], 2)
+    a.close()
+    b.close()
