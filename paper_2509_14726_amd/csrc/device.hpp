@@ -61,6 +61,7 @@ struct KArgs {
     int32_t K, N, G, P, R, objective;
     int32_t mt_size, n_mt;      // reduction tiles: samples per tile, tiles per step
     int32_t proj_window, has_drag;
+    int32_t rollout_waves, pad_;  // 1: one wave per 64 samples; 2: attitude and translation on two waves
     uint32_t seed_lo, seed_hi;
     // model
     double inv_mass, gravity, arm_s, c_tau;

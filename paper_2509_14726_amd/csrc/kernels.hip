@@ -436,6 +436,406 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(64) void k_rollou
     }
 }
 
+// ---------------------------------------------------------------- rollout, two waves
+
+// The rotational subsystem (q, omega) of Eq. (2) does not depend on position
+// or velocity, so one sample's rollout splits over two waves of a workgroup:
+// wave 0 integrates (q, omega) and hands the four RK4 stage quaternions of
+// every step to wave 1 through an LDS ring of B steps; wave 1 integrates
+// (p, v) from them and evaluates the position-dependent cost terms.  Each
+// wave accumulates the cost terms of its own state components; the two
+// partial costs are added at the end.  The arithmetic of every component is
+// the same as in the one-wave rollout; only the two halves run concurrently
+// on two SIMDs, which halves the critical path of a step.
+template <typename Real> struct SplitRing;
+template <> struct SplitRing<float> { static constexpr int B = 8; };
+template <> struct SplitRing<double> { static constexpr int B = 4; };
+
+template <int OBJ, typename Real> __global__ __launch_bounds__(128) void k_rollout_split(KArgs a)
+{
+    typedef typename Vec4<Real>::T R4;
+    constexpr int B = SplitRing<Real>::B;
+    __shared__ R4 s_q[2][B][4][64];
+    __shared__ Real s_jr[64];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = blockIdx.x * 64 + lane;
+    const int K = a.K, N = a.N;
+    const bool active = m <= K;
+    const bool nominal = m == K;
+    const DevCur *cur = a.cur;
+    const Model<Real> M(a);
+    const Real dt = (Real)a.dt;
+    const Real h2 = Real(0.5) * dt;
+    const Real dt6 = dt / Real(6);
+    const Real w_max = (Real)a.w_max, w_lim = (Real)a.w_lim;
+    const bool use_nom = m >= K;  // lanes past K read the nominal row, results unused
+    const R4 *urow = use_nom ? (const R4 *)a.nomU : (const R4 *)a.ctrl + m;
+    const size_t ustride = use_nom ? 1 : (size_t)K;
+    const Real *xref = (const Real *)a.xref_r;
+    const int i0 = cur->i0;
+    Real rdt[4];
+    for (int i = 0; i < 4; ++i) rdt[i] = (Real)(a.R_dT[i] / (a.dt * a.dt));
+
+    KSum<Real> J;
+    // ---- wave 0: attitude and body rates (hi + lo parts in binary32)
+    Real q[4], ql[4], w[3], wl[3], up[4];
+    // ---- wave 1: position and velocity
+    Real p[3], pl[3], v[3], vl[3];
+    GateRegs<Real> gt, g0r;
+    int g = 0, passes = 0;
+    Real vp = 0, th_hi = 0, th_lo = 0, ds = 0, inv_ds = 0, L = 0;
+    const Real *vrow = nullptr;
+    const Real *gtab = (const Real *)a.gates_r;
+    const Real *path = (const Real *)a.path_r;
+    {
+        const double *x0 = cur->x0;
+        for (int i = 0; i < 4; ++i) {
+            q[i] = (Real)x0[6 + i];
+            ql[i] = sizeof(Real) == 4 ? (Real)(x0[6 + i] - (double)q[i]) : Real(0);
+        }
+        for (int i = 0; i < 3; ++i) {
+            w[i] = (Real)x0[10 + i];
+            wl[i] = sizeof(Real) == 4 ? (Real)(x0[10 + i] - (double)w[i]) : Real(0);
+            p[i] = (Real)x0[i];
+            pl[i] = sizeof(Real) == 4 ? (Real)(x0[i] - (double)p[i]) : Real(0);
+            v[i] = (Real)x0[3 + i];
+            vl[i] = sizeof(Real) == 4 ? (Real)(x0[3 + i] - (double)v[i]) : Real(0);
+        }
+        for (int i = 0; i < 4; ++i) up[i] = (Real)cur->u_prev[i];
+    }
+    if (wave == 1) {
+        if (OBJ == OBJ_GATE) {
+            g = cur->g0;
+            gt.load(gtab, g);
+            g0r = gt;
+        }
+        if (OBJ == OBJ_CONTOUR) {
+            vrow = use_nom ? (const Real *)a.nomV : (const Real *)a.vctrl + m;
+            vp = (Real)cur->v_prev;
+            th_hi = (Real)cur->theta0;
+            if (sizeof(Real) == 4) th_lo = (Real)(cur->theta0 - (double)th_hi);
+            L = (Real)a.path_len;
+            ds = (Real)(a.path_len / (double)a.P);
+            inv_ds = (Real)((double)a.P / a.path_len);
+        }
+    }
+    const Real q_near = (Real)a.q_near, r_near2 = (Real)(a.r_near * a.r_near), half = (Real)a.gate_half;
+
+    const int nch = (N + B - 1) / B;
+    for (int c = 0; c <= nch; ++c) {
+        if (wave == 0 && c < nch) {
+            const int kb = c * B, ke = min(N, kb + B);
+            for (int k = kb; k < ke; ++k) {
+                R4 (*slot)[64] = s_q[c & 1][k - kb];
+                const R4 u = urow[(size_t)k * ustride];
+                Real term = Real(0);
+                if (OBJ == OBJ_TRACK) {
+                    int r = i0 + k;
+                    if (r > a.R - 1) r = a.R - 1;
+                    const Real *xr = xref + 16 * r;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real e = (q[i] - xr[6 + i]) + ql[i];
+                        term += (Real)a.Q[6 + i] * e * e;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (w[i] - xr[10 + i]) + wl[i];
+                        term += (Real)a.Q[10 + i] * e * e;
+                    }
+                }
+                if (OBJ == OBJ_CONTOUR)
+                    term += (Real)a.Q_w[0] * w[0] * w[0] + (Real)a.Q_w[1] * w[1] * w[1] +
+                            (Real)a.Q_w[2] * w[2] * w[2];
+                if (OBJ != OBJ_GATE) {
+                    const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
+                    term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                }
+                const StepInput<Real> in = step_input(M, u.x, u.y, u.z, u.w);
+                // RK4 on (q, omega)
+                Real ws[3], qs[4], kw[3], kq[4], dw[3], dq[4];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) ws[i] = w[i];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) qs[i] = q[i];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    R4 o;
+                    o.x = qs[0]; o.y = qs[1]; o.z = qs[2]; o.w = qs[3];
+                    slot[st][lane] = o;
+                    kw[0] = in.tx - M.gx * ws[1] * ws[2];
+                    kw[1] = in.ty - M.gy * ws[2] * ws[0];
+                    kw[2] = in.tz - M.gz * ws[0] * ws[1];
+                    kq[0] = Real(0.5) * (-qs[1] * ws[0] - qs[2] * ws[1] - qs[3] * ws[2]);
+                    kq[1] = Real(0.5) * (qs[0] * ws[0] + qs[2] * ws[2] - qs[3] * ws[1]);
+                    kq[2] = Real(0.5) * (qs[0] * ws[1] - qs[1] * ws[2] + qs[3] * ws[0]);
+                    kq[3] = Real(0.5) * (qs[0] * ws[2] + qs[1] * ws[1] - qs[2] * ws[0]);
+                    if (st == 0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] = kw[i];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] = kq[i];
+                    } else if (st < 3) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] += Real(2) * kw[i];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] += Real(2) * kq[i];
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] = dt6 * (dw[i] + kw[i]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] = dt6 * (dq[i] + kq[i]);
+                    }
+                    if (st < 3) {
+                        const Real hh = st < 2 ? h2 : dt;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) ws[i] = w[i] + hh * kw[i];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) qs[i] = q[i] + hh * kq[i];
+                    }
+                }
+                // commit the step (compensated in binary32), unit quaternion
+                if (sizeof(Real) == 4) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real y = dw[i] + wl[i];
+                        const Real t = w[i] + y;
+                        wl[i] = y - (t - w[i]);
+                        w[i] = t;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real y = dq[i] + ql[i];
+                        const Real t = q[i] + y;
+                        ql[i] = y - (t - q[i]);
+                        q[i] = t;
+                    }
+                    const Real n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+                    const Real r = Real(1) / sqrt(n2);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real ph = q[i] * r;
+                        const Real pl2 = fma(q[i], r, -ph) + ql[i] * r;
+                        const Real hsum = ph + pl2;
+                        ql[i] = pl2 - (hsum - ph);
+                        q[i] = hsum;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) w[i] += dw[i];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) q[i] += dq[i];
+                    const Real nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) q[i] /= nq;
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const Real e = fmax(fabs(w[i]) - w_max, Real(0));
+                    term += w_lim * e * e;
+                }
+                J.add(term);
+                up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
+            }
+        } else if (wave == 1 && c >= 1) {
+            const int kb = (c - 1) * B, ke = min(N, kb + B);
+            for (int k = kb; k < ke; ++k) {
+                R4 (*slot)[64] = s_q[(c - 1) & 1][k - kb];
+                const R4 u = urow[(size_t)k * ustride];
+                const Real fm = ((u.x + u.y) + (u.z + u.w)) * M.inv_m;
+                Real term = Real(0);
+                Real ax = 0, ay = 0, az = 0;
+                if (OBJ == OBJ_GATE) {
+                    ax = (p[0] - gt.cx) + pl[0];
+                    ay = (p[1] - gt.cy) + pl[1];
+                    az = (p[2] - gt.cz) + pl[2];
+                    const Real bx = (p[0] - g0r.cx) + pl[0];
+                    const Real by = (p[1] - g0r.cy) + pl[1];
+                    const Real bz = (p[2] - g0r.cz) + pl[2];
+                    const Real d2 = bx * bx + by * by + bz * bz;
+                    if (d2 < r_near2) term += q_near * d2;
+                    if (nominal) a.front8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+                } else if (OBJ == OBJ_TRACK) {
+                    int r = i0 + k;
+                    if (r > a.R - 1) r = a.R - 1;
+                    const Real *xr = xref + 16 * r;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (p[i] - xr[i]) + pl[i];
+                        term += (Real)a.Q[i] * e * e;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (v[i] - xr[3 + i]) + vl[i];
+                        term += (Real)a.Q[3 + i] * e * e;
+                    }
+                } else {
+                    const Real fl = floor(th_hi * inv_ds);
+                    const Real f = ((th_hi - fl * ds) + th_lo) * inv_ds;
+                    const int i = (fl >= Real(0) && fl < Real(1 << 30)) ? ((int)fl % a.P) : 0;
+                    const int i1 = (i + 1 == a.P) ? 0 : i + 1;
+                    const Real *A = path + 8 * i, *Bp = path + 8 * i1;
+                    const Real g1 = Real(1) - f;
+                    const Real px = g1 * A[0] + f * Bp[0], py = g1 * A[1] + f * Bp[1], pz = g1 * A[2] + f * Bp[2];
+                    Real tx = g1 * A[3] + f * Bp[3], ty = g1 * A[4] + f * Bp[4], tz = g1 * A[5] + f * Bp[5];
+                    const Real tn = Real(1) / sqrt(tx * tx + ty * ty + tz * tz);
+                    tx *= tn; ty *= tn; tz *= tn;
+                    const Real ex = (p[0] - px) + pl[0];
+                    const Real ey = (p[1] - py) + pl[1];
+                    const Real ez = (p[2] - pz) + pl[2];
+                    const Real et = ex * tx + ey * ty + ez * tz;
+                    const Real lx = et * tx, ly = et * ty, lz = et * tz;
+                    const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
+                    term += (Real)a.q_l * (lx * lx + ly * ly + lz * lz);
+                    term += (Real)a.q_c * (cxe * cxe + cye * cye + cze * cze);
+                    const Real vk = vrow[(size_t)k * ustride];
+                    const Real dv = vk - vp;
+                    term += (Real)(a.r_dv / (a.dt * a.dt)) * dv * dv;
+                    term -= (Real)a.mu * vk;
+                    vp = vk;
+                    const Real y = vk * dt + th_lo;
+                    const Real t = th_hi + y;
+                    th_lo = (sizeof(Real) == 4) ? y - (t - th_hi) : Real(0);
+                    th_hi = t;
+                    if (th_hi >= L) th_hi -= L;
+                }
+                // RK4 on (p, v) with the stage quaternions of wave 0
+                Real vs[3], kv[3], dpv[3], dvv[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) vs[i] = v[i];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const R4 qq = slot[st][lane];
+                    const Real r3x = Real(2) * (qq.y * qq.w + qq.x * qq.z);
+                    const Real r3y = Real(2) * (qq.z * qq.w - qq.x * qq.y);
+                    const Real r3z = Real(1) - Real(2) * (qq.y * qq.y + qq.z * qq.z);
+                    kv[0] = fm * r3x;
+                    kv[1] = fm * r3y;
+                    kv[2] = fm * r3z - M.g;
+                    if (M.drag) {
+                        const Real qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
+                        const Real r11 = Real(1) - Real(2) * (qy * qy + qz * qz), r12 = Real(2) * (qx * qy - qw * qz);
+                        const Real r21 = Real(2) * (qx * qy + qw * qz), r22 = Real(1) - Real(2) * (qx * qx + qz * qz);
+                        const Real r31 = Real(2) * (qx * qz - qw * qy), r32 = Real(2) * (qy * qz + qw * qx);
+                        const Real b0 = M.d0 * (r11 * vs[0] + r21 * vs[1] + r31 * vs[2]);
+                        const Real b1 = M.d1 * (r12 * vs[0] + r22 * vs[1] + r32 * vs[2]);
+                        const Real b2 = M.d2 * (r3x * vs[0] + r3y * vs[1] + r3z * vs[2]);
+                        kv[0] -= r11 * b0 + r12 * b1 + r3x * b2;
+                        kv[1] -= r21 * b0 + r22 * b1 + r3y * b2;
+                        kv[2] -= r31 * b0 + r32 * b1 + r3z * b2;
+                    }
+                    if (st == 0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] = vs[i]; dvv[i] = kv[i]; }
+                    } else if (st < 3) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] += Real(2) * vs[i]; dvv[i] += Real(2) * kv[i]; }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] = dt6 * (dpv[i] + vs[i]); dvv[i] = dt6 * (dvv[i] + kv[i]); }
+                    }
+                    if (st < 3) {
+                        const Real hh = st < 2 ? h2 : dt;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) vs[i] = v[i] + hh * kv[i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (sizeof(Real) == 4) {
+                        Real y = dpv[i] + pl[i];
+                        Real t = p[i] + y;
+                        pl[i] = y - (t - p[i]);
+                        p[i] = t;
+                        y = dvv[i] + vl[i];
+                        t = v[i] + y;
+                        vl[i] = y - (t - v[i]);
+                        v[i] = t;
+                    } else {
+                        p[i] += dpv[i];
+                        v[i] += dvv[i];
+                    }
+                }
+                if (OBJ == OBJ_GATE) {
+                    term += dpv[0] * (Real(2) * ax + dpv[0]) + dpv[1] * (Real(2) * ay + dpv[1]) +
+                            dpv[2] * (Real(2) * az + dpv[2]);
+                    const Real sa = ax * gt.nx + ay * gt.ny;
+                    const Real sb = (ax + dpv[0]) * gt.nx + (ay + dpv[1]) * gt.ny;
+                    if (sa < Real(0) && sb >= Real(0)) {
+                        const Real t = sa / (sa - sb);
+                        const Real yx = ax + t * dpv[0], yy = ay + t * dpv[1], yz = az + t * dpv[2];
+                        const Real lat = yx * gt.hx + yy * gt.hy;
+                        const bool inside = fabs(lat) <= half && fabs(yz) <= half;
+                        const int j = k + 1;
+                        const bool allowed = passes > 0 || ((cur->allow[j >> 5] >> (j & 31)) & 1u);
+                        if (inside && allowed) {
+                            g = (g + 1 == a.G) ? 0 : g + 1;
+                            ++passes;
+                            gt.load(gtab, g);
+                        }
+                    }
+                }
+                J.add(term);
+            }
+        }
+        __syncthreads();
+    }
+
+    // terminal terms, then the two partial costs are added
+    if (OBJ == OBJ_TRACK) {
+        int r = i0 + N;
+        if (r > a.R - 1) r = a.R - 1;
+        const Real *xr = xref + 16 * r;
+        Real term = 0;
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const Real e = (q[i] - xr[6 + i]) + ql[i];
+                term += (Real)a.QN[6 + i] * e * e;
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const Real e = (w[i] - xr[10 + i]) + wl[i];
+                term += (Real)a.QN[10 + i] * e * e;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const Real e = (p[i] - xr[i]) + pl[i];
+                term += (Real)a.QN[i] * e * e;
+                const Real f = (v[i] - xr[3 + i]) + vl[i];
+                term += (Real)a.QN[3 + i] * f * f;
+            }
+        }
+        J.add(term);
+    }
+    if (wave == 0) s_jr[lane] = J.value();
+    __syncthreads();
+    if (wave == 1) {
+        Real Jfinal = Real(0);
+        if (active) {
+            Jfinal = J.value() + s_jr[lane];
+            if (OBJ == OBJ_GATE && nominal) {
+                const Real bx = (p[0] - g0r.cx) + pl[0];
+                const Real by = (p[1] - g0r.cy) + pl[1];
+                a.front8[N] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+            }
+            if (nominal) a.cur->J_nom = (double)Jfinal;
+            else ((Real *)a.J)[m] = Jfinal;
+        }
+        const bool use = active && !nominal && isfinite(Jfinal);
+        if (sizeof(Real) == 4) {
+            const uint32_t vb = use ? ordered_bits((float)Jfinal) : ordered_bits(INFINITY);
+            wave_min_atomic(vb, &a.cur->jmin32);
+        } else {
+            const unsigned long long vb = use ? ordered_bits((double)Jfinal) : ordered_bits((double)INFINITY);
+            wave_min_atomic(vb, &a.cur->jmin64);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- average
 
 template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
@@ -624,7 +1024,10 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     if (ev) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL((k_rollout<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(64), 0, st, a);
+    if (a.rollout_waves == 2)
+        hipLaunchKernelGGL((k_rollout_split<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(128), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_rollout<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(64), 0, st, a);
     if (ev) (void)hipEventRecord(ev[2], st);
     hipError_t e = (acc64 || sizeof(Real) == 8) ? launch_average_t<Real, double, HAS_V>(a, st)
                                                 : launch_average_t<Real, float, HAS_V>(a, st);

@@ -6,6 +6,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -179,6 +180,16 @@ static void plan_average(mppi_ctx *c)
     mt = (mt + 255) / 256 * 256;
     a.mt_size = mt;
     a.n_mt = (K + mt - 1) / mt;
+    // Rollout layout: with fewer waves than SIMDs (1024 on MI355X) the chip
+    // is latency bound and the two-wave split shortens each step; with more,
+    // one wave per 64 samples issues fewer instructions in total.  The
+    // environment variable MPPI_ROLLOUT_WAVES (1 or 2) overrides the choice.
+    const int waves = (K + 1 + 63) / 64;
+    a.rollout_waves = waves < 1024 ? 2 : 1;
+    if (const char *e = getenv("MPPI_ROLLOUT_WAVES")) {
+        if (e[0] == '1') a.rollout_waves = 1;
+        if (e[0] == '2') a.rollout_waves = 2;
+    }
 }
 
 extern "C" {

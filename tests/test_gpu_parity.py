@@ -38,12 +38,19 @@ def test_single_solve_gate(precision, seed, lam):
     dev.close()
 
 
+@pytest.fixture(params=["1", "2"], ids=["one-wave", "two-wave"])
+def rollout_waves(request, monkeypatch):
+    """Both rollout layouts (read by mppi_create)."""
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", request.param)
+    return request.param
+
+
 @pytest.mark.parametrize("precision", [M.FP64, M.FP32])
 @pytest.mark.parametrize("objective", ["gate", "contour", "track"])
-def test_closed_loop_warm_start(precision, objective):
+def test_closed_loop_warm_start(precision, objective, rollout_waves):
     """A few control steps with the host plant in the loop: each step is
     compared from the same inherited (warm) state on both sides."""
-    say("closed loop", objective, precision, "K=2048 N=60")
+    say("closed loop", objective, precision, "K=2048 N=60", "waves", rollout_waves)
     w = _workload(2048, 60, objective=objective, seed=5, track_seed=2, **{"lambda": 50.0})
     dev, orc = build_pair(w, precision)
     x = w["x0"].copy()
@@ -57,8 +64,8 @@ def test_closed_loop_warm_start(precision, objective):
 
 
 @pytest.mark.parametrize("K,N", [(1, 1), (1, 9), (63, 5), (65, 17), (257, 33), (1000, 3), (130, 256)])
-def test_ragged_and_extreme_shapes(K, N):
-    say("shape", K, N)
+def test_ragged_and_extreme_shapes(K, N, rollout_waves):
+    say("shape", K, N, "waves", rollout_waves)
     w = _workload(K, N, seed=7, **{"lambda": 30.0})
     dev, orc = build_pair(w, M.FP64)
     solve_and_compare(dev, orc, w["x0"], 0.0, M.FP64)
@@ -94,9 +101,9 @@ def test_deterministic_repeat(precision):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
-def test_metric_configuration_fp32():
+def test_metric_configuration_fp32(rollout_waves):
     """K = 8192, N = 100: the configuration the benchmark times."""
-    say("metric configuration fp32 K=8192 N=100")
+    say("metric configuration fp32 K=8192 N=100 waves", rollout_waves)
     w = _workload(8192, 100, seed=1)
     dev, orc = build_pair(w, M.FP32, n_threads=16)
     st = solve_and_compare(dev, orc, w["x0"], 0.0, M.FP32)
@@ -144,3 +151,22 @@ def test_device_entry_point_matches_host_entry_point():
         x = M.plant_step(w["quad"], x, u0, w["params"]["dt"], 2)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+def test_rollout_layouts_agree(precision, monkeypatch):
+    """The one-wave and two-wave rollouts compute the same per-component
+    arithmetic: costs agree to a few ulps, the update to rounding."""
+    say("layouts agree", precision)
+    w = _workload(4096, 80, seed=12, **{"lambda": 40.0})
+    out = []
+    for waves in ("1", "2"):
+        monkeypatch.setenv("MPPI_ROLLOUT_WAVES", waves)
+        dev, _ = build_pair(w, precision)
+        u0, U, info = dev.solve(w["x0"], 0.0)
+        J, _ = dev.read_samples()
+        out.append((J, U))
+        dev.close()
+    eps = 1e-13 if precision == M.FP64 else 1e-5
+    np.testing.assert_allclose(out[0][0], out[1][0], rtol=eps, atol=eps)
+    np.testing.assert_allclose(out[0][1], out[1][1], rtol=0, atol=1e-3 if precision == M.FP32 else 1e-12)
