@@ -87,8 +87,14 @@ typedef struct {
     double mu;            /* contouring: progress reward                       */
     double v_max;         /* contouring: progress-speed bound, m/s             */
     int32_t proj_window;  /* contouring: +- table points searched for theta0   */
-    int32_t pad_;
+    int32_t flags;        /* MPPI_FLAG_* (0 for a stand-alone context)          */
 } mppi_params;
+
+/* The context allocates no per-solve workspace (sample tensor, costs,
+ * reduction partials); a server lends one to each admitted solve.  Such a
+ * context is solved only through a server (mppi_solve, mppi_solve_device and
+ * mppi_read_samples return MPPI_E_INVAL). */
+#define MPPI_FLAG_EXTERNAL_WORKSPACE 1
 
 /* Problem data: the inputs of Alg. 1 (waypoints W, path P_arc, tau_ref). */
 typedef struct {
@@ -202,6 +208,118 @@ mppi_status mppi_set_warm(mppi_ctx *ctx, const mppi_warm *in);
  * then starts a new collection. */
 mppi_status mppi_set_profiling(mppi_ctx *ctx, int32_t enable);
 mppi_status mppi_read_profile(mppi_ctx *ctx, double mean_ms[3], int32_t *n_solves);
+
+/* ---- Batches of independent solves (one persistent launch per kernel) ----
+ *
+ * A batch registers n contexts (all of one precision; objectives, K and N may
+ * differ).  Each mppi_batch_solve_device call runs one MPPI step for a chosen
+ * subset of them in a single launch sequence: a grid-stride sample kernel, a
+ * persistent rollout kernel that pulls 64-sample tiles from a device queue in
+ * order of decreasing horizon, and a grid-stride reduction kernel, per group
+ * of contexts sharing an objective and accumulation type.  Grids are fixed
+ * and the work description lives in device memory, so the sequence is
+ * captured once in a HIP graph (cfg.use_graph) and replayed for any subset.
+ * Each context's result, report and warm-start state are the same as those
+ * of mppi_solve_device on that context alone with the same rollout layout. */
+typedef struct mppi_batch mppi_batch;
+
+typedef struct {
+    int32_t rollout_waves;     /* 1 or 2 waves per 64-sample tile; 0: 2 when the
+                                  batch has fewer tiles than SIMDs, else 1       */
+    int32_t rollout_groups;    /* persistent rollout workgroups; 0: automatic    */
+    int32_t sample_groups;     /* workgroups of the sample and reduction kernels;
+                                  0: automatic                                   */
+    int32_t use_graph;         /* 1: capture the launch sequence in a HIP graph  */
+} mppi_batch_cfg;
+
+/* Register ctxs[0..n-1] (distinct, same precision, each used by no other
+ * batch or call while the batch runs).  stream: hipStream_t of the batch's
+ * launches (NULL: one owned by the batch).  cfg NULL: all automatic, graph on.
+ * The contexts must outlive the batch. */
+mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, const mppi_batch_cfg *cfg,
+                              mppi_batch **out);
+
+/* One MPPI step for the contexts active[0..n_active-1] (indices into the
+ * registered list, distinct; NULL with n_active = n: all, in order).  Solve i
+ * reads its request record (layout of mppi_solve_device) at d_reqs + 16 i and
+ * writes its first input to d_u0s + 4 i; both are device pointers that must
+ * stay valid until the stream reaches the end of the step.  Asynchronous. */
+mppi_status mppi_batch_solve_device(mppi_batch *b, const int32_t *active, int32_t n_active,
+                                    const double *d_reqs, double *d_u0s);
+
+/* Change the launch shape (drops a captured graph). */
+mppi_status mppi_batch_set_cfg(mppi_batch *b, const mppi_batch_cfg *cfg);
+mppi_status mppi_batch_get_cfg(const mppi_batch *b, mppi_batch_cfg *cfg);
+
+/* Autotuner: time every candidate launch shape (rollout waves x persistent
+ * rollout workgroups x reduction workgroups) over `reps` steps of the whole
+ * batch with the given requests, keep the fastest, and report it and its
+ * mean step time in ms.  Runs real solves: the warm-start state of every
+ * context advances by (candidates x reps) steps. */
+mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u0s, int32_t reps,
+                                mppi_batch_cfg *best, double *best_ms);
+
+void mppi_batch_destroy(mppi_batch *b);
+const char *mppi_batch_last_error(const mppi_batch *b);
+
+/* ---- Serving: continuous batching of solves from many drones ----
+ *
+ * The server owns no drone state: it registers contexts created with
+ * MPPI_FLAG_EXTERNAL_WORKSPACE (one per drone, all of one precision; each
+ * keeps its warm-start state, gate index and problem data resident on the
+ * device).  Requests queue per drone in arrival order; a drone has at most
+ * one solve in flight, since each solve starts from the previous one's warm
+ * state.  mppi_server_progress retires finished launches and then, for every
+ * idle launch slot (a stream with its own batch and graph), admits queued
+ * heads in arrival order as long as their workspace (sample tensor, costs,
+ * partials) fits in the free part of a device arena of budget_bytes, and
+ * launches them as one batch.  Requests that arrive while others run are
+ * admitted as slots and memory free up; the slots' work overlaps on the
+ * device.  A solve's result is the same as that of the context stepped alone. */
+typedef struct mppi_server mppi_server;
+
+typedef struct {
+    double budget_bytes;   /* device arena lent to in-flight solves, > 0        */
+    int32_t n_slots;       /* concurrent launches (streams), 1..16               */
+    int32_t max_batch;     /* most solves per launch; 0: no limit                */
+    int32_t use_graph;     /* capture each slot's launch sequence once           */
+    int32_t pad_;
+} mppi_server_cfg;
+
+typedef struct {
+    uint64_t ticket;       /* as returned by mppi_server_submit                  */
+    int32_t drone;
+    int32_t status;        /* MPPI_OK or MPPI_E_NONFINITE                        */
+    double u0[4];          /* first input of the solution                        */
+    double t_arrival;      /* caller's arrival time of the request               */
+    double t_launch;       /* caller's clock when the solve was launched         */
+    double t_done;         /* caller's clock when it was retired                 */
+} mppi_result;
+
+typedef struct {
+    uint64_t submitted, completed, launches;
+    int64_t queued, in_flight;
+    double arena_bytes, peak_bytes_in_flight;
+    double rollout_steps;  /* sum of K*N over completed solves                   */
+} mppi_server_stats;
+
+mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_server_cfg *cfg,
+                               mppi_server **out);
+/* Queue a solve of drone `drone` from state x0 at time t_now (the same
+ * arguments as mppi_solve); t_arrival only stamps the result.  MPPI_E_NOMEM
+ * when that drone's workspace alone exceeds the arena. */
+mppi_status mppi_server_submit(mppi_server *s, int32_t drone, const double x0[13], double t_now, double t_arrival,
+                               uint64_t *ticket);
+/* Retire finished launches (non-blocking) and launch what can be admitted;
+ * `now` is the caller's clock, used only for the result stamps. */
+mppi_status mppi_server_progress(mppi_server *s, double now, int32_t *n_launched);
+/* Move up to max finished results into out (oldest first). */
+mppi_status mppi_server_poll(mppi_server *s, mppi_result *out, int32_t max, int32_t *n_out);
+/* Block until nothing is queued or in flight (calls progress). */
+mppi_status mppi_server_drain(mppi_server *s, double now);
+mppi_status mppi_server_get_stats(const mppi_server *s, mppi_server_stats *out);
+void mppi_server_destroy(mppi_server *s);
+const char *mppi_server_last_error(const mppi_server *s);
 
 /* Human-readable description of the last error on this context ("" if none);
  * valid until the next call on the context.  ctx may be NULL (creation). */

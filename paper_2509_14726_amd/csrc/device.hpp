@@ -59,6 +59,7 @@ struct DevResult {
 // Floating constants are given in double and converted by the kernel template.
 struct KArgs {
     int32_t K, N, G, P, R, objective;
+    int32_t C, real_bytes, acc_bytes, pad2;   // channels (4, 5 contouring), sizes for ws_layout
     int32_t mt_size, n_mt;      // reduction tiles: samples per tile, tiles per step
     int32_t proj_window, has_drag;
     int32_t rollout_waves, pad_;  // 1: one wave per 64 samples; 2: attitude and translation on two waves
@@ -93,6 +94,59 @@ struct KArgs {
     // per-call
     const double *req;          // x0[13], t_now
     double *u0_out;             // 4 doubles or null
+};
+
+// Per-solve scratch of one context, carved out of one block: the sample
+// tensor, costs, reduction partials and counters.  Offsets are multiples of
+// 256 bytes.  rs / as: bytes of Real and of the accumulation type.
+struct WsLayout {
+    size_t ctrl, vctrl, nomU, nomV, J, part, tickets, front8, total;
+};
+
+__host__ __device__ inline WsLayout ws_layout(int K, int N, int C, int n_mt, int rs, int as)
+{
+    WsLayout l;
+    size_t o = 0;
+    const size_t k = (size_t)K, n = (size_t)N;
+    l.ctrl = o; o += (rs * 4 * k * n + 255) / 256 * 256;
+    l.vctrl = o; o += C == 5 ? (rs * k * n + 255) / 256 * 256 : 0;
+    l.nomU = o; o += (rs * 4 * n + 255) / 256 * 256;
+    l.nomV = o; o += (rs * n + 255) / 256 * 256;
+    l.J = o; o += (rs * k + 255) / 256 * 256;
+    l.part = o; o += (as * ((size_t)n_mt * n * C + 2 * (size_t)n_mt + n * C + 2) + 255) / 256 * 256;
+    l.tickets = o; o += (sizeof(uint32_t) * (kNMax + 1) + 255) / 256 * 256;
+    l.front8 = o; o += (n + 1 + 255) / 256 * 256;
+    l.total = o;
+    return l;
+}
+
+// One solve of a batch: which context, where its request and first input
+// live, and (when the context has none of its own) its workspace.
+struct BatchItem {
+    int32_t ctx;
+    int32_t pad;
+    const double *req;
+    double *u0_out;
+    char *ws;                   // null: the context's own workspace
+};
+
+// Work description of one launch group of a batch (one objective and one
+// accumulation type), device-resident so that a captured launch sequence
+// replays any batch composition.  Items are ordered by horizon, longest first.
+struct BatchDesc {
+    int32_t n;                  // items
+    int32_t n_sample_units;     // sum over items of ceil((K+1)/256) * N
+    int32_t n_tiles;            // sum over items of ceil((K+1)/64)
+    int32_t n_avg_units;        // sum over items of n_mt * N
+    uint32_t queue;             // rollout tile counter, reset by the sample kernel
+    uint32_t pad[3];
+};
+
+struct BArgs {
+    const KArgs *table;         // kernel arguments of every registered context
+    BatchDesc *desc;
+    const BatchItem *items;     // n entries
+    const int32_t *sample_prefix, *tile_prefix, *avg_prefix;  // n + 1 entries each
 };
 
 template <typename T> __device__ __forceinline__ T clampT(T v, T lo, T hi)

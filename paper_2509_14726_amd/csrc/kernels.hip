@@ -174,12 +174,12 @@ __device__ void solve_head(const KArgs &a)
 
 // ---------------------------------------------------------------- sample
 
-template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_sample(KArgs a)
+// One block of 256 samples at step k; block (0, 0) also runs the head.
+template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body(const KArgs &a, int bx, int k)
 {
-    if (blockIdx.x == 0 && blockIdx.y == 0) solve_head(a);
+    if (bx == 0 && k == 0) solve_head(a);
 
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
+    const int m = bx * 256 + threadIdx.x;
     if (m > a.K || k >= a.N) return;
 
     // nominal of this solve: the previous solution shifted, or hover (cold)
@@ -217,6 +217,11 @@ template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_sa
     }
 }
 
+template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_sample(KArgs a)
+{
+    sample_body<Real, HAS_V>(a, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------- rollout
 
 __device__ __forceinline__ void wave_min_atomic(uint32_t v, uint32_t *dst)
@@ -245,10 +250,11 @@ template <typename Real> struct GateRegs {
     }
 };
 
-template <int OBJ, typename Real> __global__ __launch_bounds__(64) void k_rollout(KArgs a)
+// One wave: samples 64*blk .. 64*blk+63 (sample K is the noise-free nominal).
+template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
 {
     typedef typename Vec4<Real>::T R4;
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blk * 64 + (int)(threadIdx.x & 63);
     const int K = a.K, N = a.N;
     const bool active = m <= K;
     const bool nominal = m == K;
@@ -436,6 +442,11 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(64) void k_rollou
     }
 }
 
+template <int OBJ, typename Real> __global__ __launch_bounds__(64) void k_rollout(KArgs a)
+{
+    rollout1_body<OBJ, Real>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- rollout, two waves
 
 // The rotational subsystem (q, omega) of Eq. (2) does not depend on position
@@ -451,7 +462,7 @@ template <typename Real> struct SplitRing;
 template <> struct SplitRing<float> { static constexpr int B = 8; };
 template <> struct SplitRing<double> { static constexpr int B = 4; };
 
-template <int OBJ, typename Real> __global__ __launch_bounds__(128) void k_rollout_split(KArgs a)
+template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(const KArgs &a, int blk)
 {
     typedef typename Vec4<Real>::T R4;
     constexpr int B = SplitRing<Real>::B;
@@ -460,7 +471,7 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(128) void k_rollo
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int m = blockIdx.x * 64 + lane;
+    const int m = blk * 64 + lane;
     const int K = a.K, N = a.N;
     const bool active = m <= K;
     const bool nominal = m == K;
@@ -836,6 +847,11 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(128) void k_rollo
     }
 }
 
+template <int OBJ, typename Real> __global__ __launch_bounds__(128) void k_rollout_split(KArgs a)
+{
+    rollout2_body<OBJ, Real>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------- average
 
 template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
@@ -852,7 +868,7 @@ template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
 // warm-start hand-over.  Every sum has a fixed order, so results repeat bit
 // for bit.
 template <typename Real, typename Acc, bool HAS_V>
-__global__ __launch_bounds__(256) void k_average(KArgs a)
+__device__ __forceinline__ void average_body(const KArgs &a, int mt, int k)
 {
     constexpr int C = HAS_V ? 5 : 4;
     constexpr int NV = C + 2;
@@ -862,7 +878,6 @@ __global__ __launch_bounds__(256) void k_average(KArgs a)
 
     const int tid = threadIdx.x;
     const int K = a.K, N = a.N;
-    const int mt = blockIdx.x, k = blockIdx.y;
     const int n_mt = a.n_mt;
     const int m_lo = mt * a.mt_size;
     const int m_hi = min(K, m_lo + a.mt_size);
@@ -913,7 +928,9 @@ __global__ __launch_bounds__(256) void k_average(KArgs a)
         s_last = (t == (unsigned)n_mt - 1) ? 1u : 0u;
     }
     __syncthreads();
-    if (!s_last) return;
+    const bool merge_step = s_last != 0u;
+    __syncthreads();
+    if (!merge_step) return;
     __threadfence();
     if (tid < C) {
         Acc s = 0;
@@ -934,7 +951,9 @@ __global__ __launch_bounds__(256) void k_average(KArgs a)
         s_last = (t == (unsigned)N - 1) ? 1u : 0u;
     }
     __syncthreads();
-    if (!s_last) return;
+    const bool run_tail = s_last != 0u;
+    __syncthreads();
+    if (!run_tail) return;
     __threadfence();
 
     const Acc den = stage[(size_t)N * C], den2 = stage[(size_t)N * C + 1];
@@ -990,6 +1009,141 @@ __global__ __launch_bounds__(256) void k_average(KArgs a)
             w->theta0 = cur->theta0;
             for (int i = 0; i < 13; ++i) w->x_prev[i] = cur->x0[i];
         }
+    }
+}
+
+template <typename Real, typename Acc, bool HAS_V>
+__global__ __launch_bounds__(256) void k_average(KArgs a)
+{
+    average_body<Real, Acc, HAS_V>(a, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------- batched (persistent)
+
+// Largest i in [0, n) with prefix[i] <= u (prefix[0] = 0, prefix[n] = total).
+__device__ __forceinline__ int find_item(const int32_t *prefix, int n, int u)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Stage the kernel arguments of an item's context in LDS, with the item's
+// request and output pointers.
+__device__ __forceinline__ void stage_args(KArgs &s_a, int &s_ctx, const BArgs &b, int item)
+{
+    const BatchItem it = b.items[item];
+    if (it.ctx != s_ctx) {
+        const uint32_t *src = (const uint32_t *)(b.table + it.ctx);
+        uint32_t *dst = (uint32_t *)&s_a;
+        for (int t = threadIdx.x; t < (int)(sizeof(KArgs) / 4); t += blockDim.x) dst[t] = src[t];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_a.req = it.req;
+        s_a.u0_out = it.u0_out;
+        if (it.ws) {
+            const WsLayout l = ws_layout(s_a.K, s_a.N, s_a.C, s_a.n_mt, s_a.real_bytes, s_a.acc_bytes);
+            s_a.ctrl = it.ws + l.ctrl;
+            s_a.vctrl = s_a.C == 5 ? it.ws + l.vctrl : nullptr;
+            s_a.nomU = it.ws + l.nomU;
+            s_a.nomV = it.ws + l.nomV;
+            s_a.J = it.ws + l.J;
+            s_a.part = it.ws + l.part;
+            s_a.tickets = (uint32_t *)(it.ws + l.tickets);
+            s_a.front8 = (uint8_t *)(it.ws + l.front8);
+        }
+        // a workspace is bound per item: restage the next item in any case
+        s_ctx = it.ws ? -1 : it.ctx;
+    }
+    __syncthreads();
+}
+
+template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void kb_sample(BArgs b)
+{
+    __shared__ KArgs s_a;
+    __shared__ int s_ctx;
+    if (threadIdx.x == 0) s_ctx = -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) b.desc->queue = 0u;
+    const int n = b.desc->n, total = b.desc->n_sample_units;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int item = find_item(b.sample_prefix, n, u);
+        stage_args(s_a, s_ctx, b, item);
+        const int local = u - b.sample_prefix[item];
+        const int nbx = (s_a.K + 1 + 255) / 256;
+        sample_body<Real, HAS_V>(s_a, local % nbx, local / nbx);
+        __syncthreads();
+    }
+}
+
+template <int OBJ, typename Real, int WAVES> __global__ __launch_bounds__(64 * WAVES) void kb_rollout(BArgs b)
+{
+    __shared__ KArgs s_a;
+    __shared__ int s_ctx, s_unit;
+    if (threadIdx.x == 0) s_ctx = -1;
+    const int n = b.desc->n, total = b.desc->n_tiles;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_unit = (int)atomicAdd(&b.desc->queue, 1u);
+        __syncthreads();
+        const int u = s_unit;
+        if (u >= total) break;
+        const int item = find_item(b.tile_prefix, n, u);
+        stage_args(s_a, s_ctx, b, item);
+        const int blk = u - b.tile_prefix[item];
+        if (WAVES == 2) rollout2_body<OBJ, Real>(s_a, blk);
+        else rollout1_body<OBJ, Real>(s_a, blk);
+    }
+}
+
+template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(256) void kb_average(BArgs b)
+{
+    __shared__ KArgs s_a;
+    __shared__ int s_ctx;
+    if (threadIdx.x == 0) s_ctx = -1;
+    const int n = b.desc->n, total = b.desc->n_avg_units;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int item = find_item(b.avg_prefix, n, u);
+        stage_args(s_a, s_ctx, b, item);
+        const int local = u - b.avg_prefix[item];
+        average_body<Real, Acc, HAS_V>(s_a, local % s_a.n_mt, local / s_a.n_mt);
+        __syncthreads();
+    }
+}
+
+template <typename Real, int OBJ>
+static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream_t st)
+{
+    constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
+    hipLaunchKernelGGL((kb_sample<Real, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
+    if (L.rollout_waves == 2)
+        hipLaunchKernelGGL((kb_rollout<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(128), 0, st, b);
+    else
+        hipLaunchKernelGGL((kb_rollout<OBJ, Real, 1>), dim3(L.rollout_groups), dim3(64), 0, st, b);
+    if (L.acc64 || sizeof(Real) == 8)
+        hipLaunchKernelGGL((kb_average<Real, double, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
+    else
+        hipLaunchKernelGGL((kb_average<Real, float, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BArgs &b, const BatchLaunch &L, hipStream_t st)
+{
+    if (L.fp64) {
+        switch (L.objective) {
+        case OBJ_CONTOUR: return launch_batch_t<double, OBJ_CONTOUR>(b, L, st);
+        case OBJ_TRACK: return launch_batch_t<double, OBJ_TRACK>(b, L, st);
+        default: return launch_batch_t<double, OBJ_GATE>(b, L, st);
+        }
+    }
+    switch (L.objective) {
+    case OBJ_CONTOUR: return launch_batch_t<float, OBJ_CONTOUR>(b, L, st);
+    case OBJ_TRACK: return launch_batch_t<float, OBJ_TRACK>(b, L, st);
+    default: return launch_batch_t<float, OBJ_GATE>(b, L, st);
     }
 }
 

@@ -16,4 +16,16 @@ hipError_t launch_setup(const KArgs &a, bool fp64, hipStream_t st);
 // average kernels and after the average kernel.
 hipError_t launch_solve(const KArgs &a, bool fp64, bool acc64, hipStream_t st, hipEvent_t *ev = nullptr);
 
+// Launch shape of one batch group.
+struct BatchLaunch {
+    int objective;
+    bool fp64, acc64;
+    int rollout_waves;    // 1 or 2
+    int rollout_groups;   // persistent rollout workgroups
+    int sample_groups;    // grid-stride workgroups of the sample and average kernels
+};
+
+// Enqueue one batched MPPI step over the items described in device memory.
+hipError_t launch_batch(const BArgs &b, const BatchLaunch &L, hipStream_t st);
+
 }  // namespace mppi

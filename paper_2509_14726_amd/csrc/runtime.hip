@@ -9,8 +9,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mppi.h"
@@ -44,6 +46,8 @@ struct mppi_ctx {
     bool profiling = false;
     std::vector<hipEvent_t> events;  // kProfSlots x 4
     int prof_count = 0;
+    bool external_ws = false;   // per-solve scratch is lent by a server
+    size_t ws_bytes = 0;        // size of that scratch
     std::string err;
 };
 
@@ -279,20 +283,23 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
 
     const size_t rs = c->fp64 ? sizeof(double) : sizeof(float);
     const size_t as = c->acc64 ? sizeof(double) : sizeof(float);
-    const size_t K = (size_t)c->K, N = (size_t)c->N;
+    a.C = c->C;
+    a.real_bytes = (int32_t)rs;
+    a.acc_bytes = (int32_t)as;
+    c->external_ws = (params->flags & MPPI_FLAG_EXTERNAL_WORKSPACE) != 0;
     struct Want { void **dst; size_t bytes; };
     void *gates_d = nullptr, *gates_r = nullptr, *path_d = nullptr, *path_r = nullptr, *xref_r = nullptr;
     void *warm = nullptr, *wU = nullptr, *wV = nullptr, *cur = nullptr, *res = nullptr, *req = nullptr;
-    void *ctrl = nullptr, *vctrl = nullptr, *nomU = nullptr, *nomV = nullptr, *J = nullptr, *part = nullptr;
-    void *front8 = nullptr, *tickets = nullptr;
+    void *ws = nullptr;
+    const WsLayout wl = ws_layout(c->K, c->N, c->C, a.n_mt, (int)rs, (int)as);
+    c->ws_bytes = wl.total;
     Want wants[] = {
         {&warm, sizeof(DevWarm)}, {&wU, sizeof(double) * kNMax * 4}, {&wV, sizeof(double) * kNMax},
         {&cur, sizeof(DevCur)}, {&res, sizeof(DevResult)}, {&req, sizeof(double) * kReqDoubles},
-        {&ctrl, rs * 4 * K * N}, {&nomU, rs * 4 * N}, {&nomV, rs * N}, {&J, rs * K},
-        {&part, as * ((size_t)a.n_mt * N * (size_t)c->C + 2 * (size_t)a.n_mt + N * (size_t)c->C + 2)},
-        {&tickets, sizeof(uint32_t) * (kNMax + 1)}, {&front8, N + 1},
+        {&ws, c->external_ws ? 0 : wl.total},
     };
     for (auto &w : wants) {
+        if (w.dst == &ws && c->external_ws) continue;
         *w.dst = dev_alloc(c, w.bytes);
         if (!*w.dst) {
             release(c);
@@ -300,10 +307,9 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
         }
     }
     if (c->objective == MPPI_OBJ_CONTOUR) {
-        vctrl = dev_alloc(c, rs * K * N);
         path_d = dev_alloc(c, sizeof(double) * 6 * (size_t)c->P);
         path_r = dev_alloc(c, rs * 8 * (size_t)c->P);
-        if (!vctrl || !path_d || !path_r) { release(c); return fail(nullptr, MPPI_E_NOMEM, "device allocation failed"); }
+        if (!path_d || !path_r) { release(c); return fail(nullptr, MPPI_E_NOMEM, "device allocation failed"); }
     }
     if (c->objective == MPPI_OBJ_GATE) {
         gates_d = dev_alloc(c, sizeof(double) * 4 * (size_t)c->G);
@@ -324,9 +330,17 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.path_d = (const double *)path_d; a.path_r = path_r; a.xref_r = xref_r;
     a.warm = (DevWarm *)warm; a.wU = (double *)wU; a.wV = (double *)wV;
     a.cur = (DevCur *)cur; a.res = (DevResult *)res;
-    a.ctrl = ctrl; a.vctrl = vctrl; a.nomU = nomU; a.nomV = nomV; a.J = J; a.part = part;
-    a.front8 = (uint8_t *)front8;
-    a.tickets = (uint32_t *)tickets;
+    if (ws) {
+        char *w = (char *)ws;
+        a.ctrl = w + wl.ctrl;
+        a.vctrl = c->C == 5 ? w + wl.vctrl : nullptr;
+        a.nomU = w + wl.nomU;
+        a.nomV = w + wl.nomV;
+        a.J = w + wl.J;
+        a.part = w + wl.part;
+        a.tickets = (uint32_t *)(w + wl.tickets);
+        a.front8 = (uint8_t *)(w + wl.front8);
+    }
     c->warm = (DevWarm *)warm; c->res = (DevResult *)res; c->req = (double *)req;
 
     // problem data, initial (cold) warm state
@@ -360,6 +374,7 @@ mppi_status mppi_solve_device(mppi_ctx *ctx, const double *d_req, double *d_u0)
 {
     if (!ctx) return fail(nullptr, MPPI_E_INVAL, "ctx is NULL");
     if (!d_req) return fail(ctx, MPPI_E_INVAL, "d_req is NULL");
+    if (ctx->external_ws) return fail(ctx, MPPI_E_INVAL, "context has no workspace of its own (server context)");
     ctx->err.clear();
     KArgs a = ctx->args;
     a.req = d_req;
@@ -424,6 +439,7 @@ mppi_status mppi_solve(mppi_ctx *ctx, const double x0[13], double t_now, double 
     if (!ctx) return fail(nullptr, MPPI_E_INVAL, "ctx is NULL");
     if (!x0 || !u0_out) return fail(ctx, MPPI_E_INVAL, "x0 and u0_out are required");
     if (!finite_all(x0, 13) || !isfinite(t_now)) return fail(ctx, MPPI_E_INVAL, "x0 and t_now must be finite");
+    if (ctx->external_ws) return fail(ctx, MPPI_E_INVAL, "context has no workspace of its own (server context)");
     const double qn = x0[6] * x0[6] + x0[7] * x0[7] + x0[8] * x0[8] + x0[9] * x0[9];
     if (!(qn > 0.0)) return fail(ctx, MPPI_E_INVAL, "quaternion of x0 has zero norm");
     ctx->err.clear();
@@ -460,6 +476,7 @@ mppi_status mppi_read_info(mppi_ctx *ctx, mppi_info *info)
 mppi_status mppi_read_samples(mppi_ctx *ctx, double *J, double *U_samples)
 {
     if (!ctx) return fail(nullptr, MPPI_E_INVAL, "ctx is NULL");
+    if (ctx->external_ws) return fail(ctx, MPPI_E_INVAL, "context has no workspace of its own (server context)");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const size_t K = (size_t)ctx->K, N = (size_t)ctx->N;
     if (J) {
@@ -579,6 +596,693 @@ mppi_status mppi_plant_step(const mppi_quad *quad, const double x[13], const dou
         for (int i = 6; i < 10; ++i) s[i] /= nq;
     }
     memcpy(x_out, s, sizeof s);
+    return MPPI_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== batches
+
+namespace {
+
+struct BatchGroup {
+    int objective = 0;
+    bool acc64 = false;
+    std::vector<int> regs;       // registered contexts of this group
+    int cap = 0;                 // = regs.size()
+    size_t bytes = 0;
+    void *d_block = nullptr;     // BatchDesc, items[cap], 3 x prefix[cap + 1]
+    void *h_block = nullptr;     // pinned mirror
+    BArgs bargs{};
+    BatchLaunch launch{};
+    int active = 0;              // items in the current step
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct mppi_batch {
+    std::vector<mppi_ctx *> ctxs;
+    std::vector<int> group_of, tiles_of;
+    bool fp64 = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    KArgs *d_table = nullptr;
+    std::vector<BatchGroup> groups;
+    mppi_batch_cfg cfg{};
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipEvent_t copy_done = nullptr;
+    bool copy_pending = false;
+    int n_cu = 256;
+    int total_tiles = 0;
+    std::string err;
+};
+
+static mppi_status bfail(mppi_batch *b, mppi_status s, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+static mppi_status bfail(mppi_batch *b, mppi_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    else g_create_err = buf;
+    return s;
+}
+
+#define BHIP_TRY(b, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return bfail((b), MPPI_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+static void drop_graph(mppi_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Resolve automatic fields of the launch shape for this batch.
+static void resolve_cfg(mppi_batch *b)
+{
+    mppi_batch_cfg &c = b->cfg;
+    int waves = c.rollout_waves;
+    if (waves != 1 && waves != 2) waves = b->total_tiles < 4 * b->n_cu ? 2 : 1;
+    int rg = c.rollout_groups > 0 ? c.rollout_groups : (waves == 2 ? 2 * b->n_cu : 8 * b->n_cu);
+    int sg = c.sample_groups > 0 ? c.sample_groups : 4 * b->n_cu;
+    for (auto &g : b->groups) {
+        g.launch.objective = g.objective;
+        g.launch.fp64 = b->fp64;
+        g.launch.acc64 = g.acc64;
+        g.launch.rollout_waves = waves;
+        g.launch.rollout_groups = rg;
+        g.launch.sample_groups = sg;
+    }
+}
+
+static void release_batch(mppi_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    for (auto &g : b->groups) {
+        if (g.d_block) (void)hipFree(g.d_block);
+        if (g.h_block) (void)hipHostFree(g.h_block);
+    }
+    if (b->d_table) (void)hipFree(b->d_table);
+    if (b->copy_done) (void)hipEventDestroy(b->copy_done);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+extern "C" {
+
+const char *mppi_batch_last_error(const mppi_batch *b) { return b ? b->err.c_str() : g_create_err.c_str(); }
+
+void mppi_batch_destroy(mppi_batch *b) { release_batch(b); }
+
+mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, const mppi_batch_cfg *cfg,
+                              mppi_batch **out)
+{
+    if (!out) return bfail(nullptr, MPPI_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1) return bfail(nullptr, MPPI_E_INVAL, "a batch needs at least one context");
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d is NULL", i);
+        if (ctxs[i]->fp64 != ctxs[0]->fp64) return bfail(nullptr, MPPI_E_INVAL, "contexts differ in precision");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d registered twice", i);
+    }
+    mppi_batch *b = new (std::nothrow) mppi_batch();
+    if (!b) return bfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
+    b->ctxs.assign(ctxs, ctxs + n);
+    b->fp64 = ctxs[0]->fp64;
+    b->cfg = cfg ? *cfg : mppi_batch_cfg{0, 0, 0, 1};
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (b->n_cu < 1) b->n_cu = 256;
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            release_batch(b);
+            return bfail(nullptr, MPPI_E_DEVICE, "hipStreamCreateWithFlags failed");
+        }
+        b->own_stream = true;
+    }
+    if (hipEventCreateWithFlags(&b->copy_done, hipEventDisableTiming) != hipSuccess) {
+        release_batch(b);
+        return bfail(nullptr, MPPI_E_DEVICE, "hipEventCreate failed");
+    }
+    // groups by (objective, accumulation type)
+    b->group_of.resize(n);
+    b->tiles_of.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const mppi_ctx *c = ctxs[i];
+        int gi = -1;
+        for (size_t g = 0; g < b->groups.size(); ++g)
+            if (b->groups[g].objective == c->objective && b->groups[g].acc64 == c->acc64) gi = (int)g;
+        if (gi < 0) {
+            b->groups.emplace_back();
+            b->groups.back().objective = c->objective;
+            b->groups.back().acc64 = c->acc64;
+            gi = (int)b->groups.size() - 1;
+        }
+        b->groups[gi].regs.push_back(i);
+        b->group_of[i] = gi;
+        b->tiles_of[i] = (c->K + 1 + 63) / 64;
+        b->total_tiles += b->tiles_of[i];
+    }
+    // device table of kernel arguments
+    std::vector<KArgs> table(n);
+    for (int i = 0; i < n; ++i) table[i] = ctxs[i]->args;
+    if (hipMalloc((void **)&b->d_table, sizeof(KArgs) * n) != hipSuccess ||
+        hipMemcpy(b->d_table, table.data(), sizeof(KArgs) * n, hipMemcpyHostToDevice) != hipSuccess) {
+        release_batch(b);
+        return bfail(nullptr, MPPI_E_NOMEM, "device table allocation failed");
+    }
+    for (auto &g : b->groups) {
+        g.cap = (int)g.regs.size();
+        const size_t o_items = align_up(sizeof(BatchDesc), 64);
+        const size_t o_sp = align_up(o_items + sizeof(BatchItem) * g.cap, 64);
+        const size_t o_tp = align_up(o_sp + sizeof(int32_t) * (g.cap + 1), 64);
+        const size_t o_ap = align_up(o_tp + sizeof(int32_t) * (g.cap + 1), 64);
+        g.bytes = align_up(o_ap + sizeof(int32_t) * (g.cap + 1), 64);
+        if (hipMalloc(&g.d_block, g.bytes) != hipSuccess || hipHostMalloc(&g.h_block, g.bytes, 0) != hipSuccess) {
+            release_batch(b);
+            return bfail(nullptr, MPPI_E_NOMEM, "batch descriptor allocation failed");
+        }
+        memset(g.h_block, 0, g.bytes);
+        char *d = (char *)g.d_block;
+        g.bargs.table = b->d_table;
+        g.bargs.desc = (BatchDesc *)d;
+        g.bargs.items = (const BatchItem *)(d + o_items);
+        g.bargs.sample_prefix = (const int32_t *)(d + o_sp);
+        g.bargs.tile_prefix = (const int32_t *)(d + o_tp);
+        g.bargs.avg_prefix = (const int32_t *)(d + o_ap);
+    }
+    resolve_cfg(b);
+    *out = b;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_set_cfg(mppi_batch *b, const mppi_batch_cfg *cfg)
+{
+    if (!b || !cfg) return bfail(b, MPPI_E_INVAL, "batch and cfg are required");
+    if (cfg->rollout_waves < 0 || cfg->rollout_waves > 2 || cfg->rollout_groups < 0 || cfg->sample_groups < 0)
+        return bfail(b, MPPI_E_INVAL, "invalid launch shape");
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    b->cfg = *cfg;
+    resolve_cfg(b);
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_get_cfg(const mppi_batch *b, mppi_batch_cfg *cfg)
+{
+    if (!b || !cfg) return MPPI_E_INVAL;
+    *cfg = b->cfg;
+    if (!b->groups.empty()) {
+        cfg->rollout_waves = b->groups[0].launch.rollout_waves;
+        cfg->rollout_groups = b->groups[0].launch.rollout_groups;
+        cfg->sample_groups = b->groups[0].launch.sample_groups;
+    }
+    return MPPI_OK;
+}
+
+static mppi_status enqueue_groups(mppi_batch *b, bool skip_empty)
+{
+    for (auto &g : b->groups) {
+        if (skip_empty && g.active == 0) continue;
+        BHIP_TRY(b, launch_batch(g.bargs, g.launch, b->stream));
+    }
+    return MPPI_OK;
+}
+
+}  // extern "C"
+
+// One batched step; ws (optional, n_active entries) lends each solve its
+// workspace when its context has none of its own.
+static mppi_status batch_solve(mppi_batch *b, const int32_t *active, int32_t n_active, const double *d_reqs,
+                               double *d_u0s, char *const *ws)
+{
+    if (!b) return bfail(nullptr, MPPI_E_INVAL, "batch is NULL");
+    const int n = (int)b->ctxs.size();
+    if (!d_reqs) return bfail(b, MPPI_E_INVAL, "d_reqs is NULL");
+    if (active == nullptr && n_active != n) return bfail(b, MPPI_E_INVAL, "NULL active list needs n_active = n");
+    if (n_active < 0 || n_active > n) return bfail(b, MPPI_E_INVAL, "n_active=%d outside [0, %d]", n_active, n);
+    std::vector<char> seen(n, 0);
+    for (auto &g : b->groups) g.active = 0;
+    std::vector<std::vector<std::pair<int, int>>> per(b->groups.size());  // (registered index, slot)
+    for (int i = 0; i < n_active; ++i) {
+        const int r = active ? active[i] : i;
+        if (r < 0 || r >= n) return bfail(b, MPPI_E_INVAL, "active[%d]=%d outside [0, %d)", i, r, n);
+        if (seen[r]) return bfail(b, MPPI_E_INVAL, "context %d listed twice", r);
+        if (b->ctxs[r]->external_ws && !(ws && ws[i]))
+            return bfail(b, MPPI_E_INVAL, "context %d has no workspace and none was lent", r);
+        seen[r] = 1;
+        per[b->group_of[r]].push_back({r, i});
+    }
+    // the previous step's descriptor copy must have left the pinned buffers
+    if (b->copy_pending) BHIP_TRY(b, hipEventSynchronize(b->copy_done));
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        BatchGroup &g = b->groups[gi];
+        auto &lst = per[gi];
+        // longest horizon first (tile order of the persistent rollout), ties by registration
+        std::stable_sort(lst.begin(), lst.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+            return b->ctxs[x.first]->N > b->ctxs[y.first]->N;
+        });
+        char *h = (char *)g.h_block;
+        const char *d = (const char *)g.d_block;
+        BatchDesc *desc = (BatchDesc *)h;
+        BatchItem *items = (BatchItem *)(h + ((const char *)g.bargs.items - d));
+        int32_t *sp = (int32_t *)(h + ((const char *)g.bargs.sample_prefix - d));
+        int32_t *tp = (int32_t *)(h + ((const char *)g.bargs.tile_prefix - d));
+        int32_t *ap = (int32_t *)(h + ((const char *)g.bargs.avg_prefix - d));
+        int64_t s_units = 0, t_units = 0, a_units = 0;
+        sp[0] = tp[0] = ap[0] = 0;
+        for (size_t j = 0; j < lst.size(); ++j) {
+            const mppi_ctx *c = b->ctxs[lst[j].first];
+            items[j].ctx = lst[j].first;
+            items[j].pad = 0;
+            items[j].req = d_reqs + (size_t)kReqDoubles * lst[j].second;
+            items[j].u0_out = d_u0s ? d_u0s + 4 * (size_t)lst[j].second : nullptr;
+            items[j].ws = ws ? ws[lst[j].second] : nullptr;
+            s_units += (int64_t)((c->K + 1 + 255) / 256) * c->N;
+            t_units += (c->K + 1 + 63) / 64;
+            a_units += (int64_t)c->args.n_mt * c->N;
+            if (s_units > INT32_MAX || a_units > INT32_MAX) return bfail(b, MPPI_E_INVAL, "batch too large");
+            sp[j + 1] = (int32_t)s_units;
+            tp[j + 1] = (int32_t)t_units;
+            ap[j + 1] = (int32_t)a_units;
+        }
+        desc->n = (int32_t)lst.size();
+        desc->n_sample_units = (int32_t)s_units;
+        desc->n_tiles = (int32_t)t_units;
+        desc->n_avg_units = (int32_t)a_units;
+        desc->queue = 0u;
+        g.active = (int)lst.size();
+        BHIP_TRY(b, hipMemcpyAsync(g.d_block, g.h_block, g.bytes, hipMemcpyHostToDevice, b->stream));
+    }
+    BHIP_TRY(b, hipEventRecord(b->copy_done, b->stream));
+    b->copy_pending = true;
+    if (b->cfg.use_graph) {
+        if (!b->exec) {
+            BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            mppi_status st = enqueue_groups(b, false);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &graph);
+            if (st != MPPI_OK) { if (graph) (void)hipGraphDestroy(graph); return st; }
+            if (e != hipSuccess) return bfail(b, MPPI_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            b->graph = graph;
+            BHIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        }
+        BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+        return MPPI_OK;
+    }
+    return enqueue_groups(b, true);
+}
+
+extern "C" {
+
+mppi_status mppi_batch_solve_device(mppi_batch *b, const int32_t *active, int32_t n_active, const double *d_reqs,
+                                    double *d_u0s)
+{
+    return batch_solve(b, active, n_active, d_reqs, d_u0s, nullptr);
+}
+
+mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u0s, int32_t reps,
+                                mppi_batch_cfg *best, double *best_ms)
+{
+    if (!b || !d_reqs || reps < 1) return bfail(b, MPPI_E_INVAL, "batch, requests and reps >= 1 are required");
+    const int n = (int)b->ctxs.size();
+    const mppi_batch_cfg saved = b->cfg;
+    std::vector<mppi_batch_cfg> cand;
+    const int cu = b->n_cu;
+    for (int waves = 1; waves <= 2; ++waves) {
+        const int rg_mult[] = {1, 2, 4, 8};
+        for (int rm : rg_mult) {
+            if (waves == 2 && rm > 2) continue;  // two 64 KB LDS rings fit one CU
+            for (int sm : {1, 4}) cand.push_back(mppi_batch_cfg{waves, rm * cu, sm * cu, 1});
+        }
+    }
+    hipEvent_t e0, e1;
+    BHIP_TRY(b, hipEventCreate(&e0));
+    BHIP_TRY(b, hipEventCreate(&e1));
+    double best_t = 1e300;
+    mppi_batch_cfg best_c = saved;
+    mppi_status st = MPPI_OK;
+    for (const auto &c : cand) {
+        if ((st = mppi_batch_set_cfg(b, &c)) != MPPI_OK) break;
+        if ((st = mppi_batch_solve_device(b, nullptr, n, d_reqs, d_u0s)) != MPPI_OK) break;  // capture + warm-up
+        if (hipEventRecord(e0, b->stream) != hipSuccess) { st = MPPI_E_DEVICE; break; }
+        for (int r = 0; r < reps && st == MPPI_OK; ++r) st = mppi_batch_solve_device(b, nullptr, n, d_reqs, d_u0s);
+        if (st != MPPI_OK) break;
+        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            st = MPPI_E_DEVICE;
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double t = ms / reps;
+        if (t < best_t) { best_t = t; best_c = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MPPI_OK) { (void)mppi_batch_set_cfg(b, &saved); return st; }
+    if ((st = mppi_batch_set_cfg(b, &best_c)) != MPPI_OK) return st;
+    if (best) *best = best_c;
+    if (best_ms) *best_ms = best_t;
+    return MPPI_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== server
+
+namespace {
+
+// First-fit allocator over one device arena (offsets, 256-byte granules).
+struct Arena {
+    size_t size = 0;
+    std::vector<std::pair<size_t, size_t>> free_list;  // (offset, bytes), sorted by offset
+    size_t in_use = 0, peak = 0;
+
+    void reset(size_t n)
+    {
+        size = n;
+        free_list.assign(1, {0, n});
+        in_use = peak = 0;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = align_up(bytes, 256);
+        for (size_t i = 0; i < free_list.size(); ++i) {
+            if (free_list[i].second >= bytes) {
+                *off = free_list[i].first;
+                free_list[i].first += bytes;
+                free_list[i].second -= bytes;
+                if (free_list[i].second == 0) free_list.erase(free_list.begin() + (long)i);
+                in_use += bytes;
+                if (in_use > peak) peak = in_use;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = align_up(bytes, 256);
+        in_use -= bytes;
+        auto it = std::lower_bound(free_list.begin(), free_list.end(), std::make_pair(off, (size_t)0));
+        it = free_list.insert(it, {off, bytes});
+        // merge with neighbours
+        size_t i = (size_t)(it - free_list.begin());
+        if (i + 1 < free_list.size() && free_list[i].first + free_list[i].second == free_list[i + 1].first) {
+            free_list[i].second += free_list[i + 1].second;
+            free_list.erase(free_list.begin() + (long)i + 1);
+        }
+        if (i > 0 && free_list[i - 1].first + free_list[i - 1].second == free_list[i].first) {
+            free_list[i - 1].second += free_list[i].second;
+            free_list.erase(free_list.begin() + (long)i);
+        }
+    }
+};
+
+struct Request {
+    uint64_t ticket;
+    double x0[13];
+    double t_now, t_arrival;
+};
+
+struct InFlight {
+    int drone;
+    uint64_t ticket;
+    double t_arrival, t_launch;
+    size_t ws_off;
+};
+
+struct Slot {
+    mppi_batch *batch = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    double *h_req = nullptr, *d_req = nullptr;   // n x 16
+    double *h_u0 = nullptr, *d_u0 = nullptr;     // n x 4
+    std::vector<InFlight> flight;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct mppi_server {
+    std::vector<mppi_ctx *> drones;
+    mppi_server_cfg cfg{};
+    std::vector<std::vector<Request>> queue;     // per drone, FIFO (front at index head[d])
+    std::vector<size_t> head;
+    std::vector<char> busy;
+    std::vector<Slot> slots;
+    char *arena_base = nullptr;
+    Arena arena;
+    std::vector<mppi_result> done;
+    size_t done_head = 0;
+    uint64_t next_ticket = 1;
+    mppi_server_stats st{};
+    std::string err;
+};
+
+static mppi_status sfail(mppi_server *s, mppi_status code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+static mppi_status sfail(mppi_server *s, mppi_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) s->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+static void release_server(mppi_server *s)
+{
+    if (!s) return;
+    for (auto &sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.batch) release_batch(sl.batch);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.h_req) (void)hipHostFree(sl.h_req);
+        if (sl.h_u0) (void)hipHostFree(sl.h_u0);
+        if (sl.d_req) (void)hipFree(sl.d_req);
+        if (sl.d_u0) (void)hipFree(sl.d_u0);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    if (s->arena_base) (void)hipFree(s->arena_base);
+    delete s;
+}
+
+// Retire finished launches of every busy slot (non-blocking unless wait).
+static mppi_status retire(mppi_server *s, double now, bool wait)
+{
+    for (auto &sl : s->slots) {
+        if (!sl.busy) continue;
+        hipError_t q = wait ? hipEventSynchronize(sl.done) : hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return sfail(s, MPPI_E_DEVICE, "launch failed: %s", hipGetErrorString(q));
+        for (size_t i = 0; i < sl.flight.size(); ++i) {
+            const InFlight &f = sl.flight[i];
+            mppi_result r{};
+            r.ticket = f.ticket;
+            r.drone = f.drone;
+            bool finite = true;
+            for (int c = 0; c < 4; ++c) {
+                r.u0[c] = sl.h_u0[4 * i + c];
+                finite = finite && isfinite(r.u0[c]);
+            }
+            r.status = finite ? MPPI_OK : MPPI_E_NONFINITE;
+            r.t_arrival = f.t_arrival;
+            r.t_launch = f.t_launch;
+            r.t_done = now;
+            s->done.push_back(r);
+            s->busy[f.drone] = 0;
+            s->arena.release(f.ws_off, s->drones[f.drone]->ws_bytes);
+            s->st.completed += 1;
+            s->st.rollout_steps += (double)s->drones[f.drone]->K * (double)s->drones[f.drone]->N;
+        }
+        s->st.in_flight -= (int64_t)sl.flight.size();
+        sl.flight.clear();
+        sl.busy = false;
+    }
+    return MPPI_OK;
+}
+
+// Admit queued heads into idle slots and launch them.
+static mppi_status admit(mppi_server *s, double now, int32_t *n_launched)
+{
+    const int nd = (int)s->drones.size();
+    for (auto &sl : s->slots) {
+        if (sl.busy) continue;
+        // ready drones, oldest head first
+        std::vector<int> ready;
+        for (int d = 0; d < nd; ++d)
+            if (!s->busy[d] && s->head[d] < s->queue[d].size()) ready.push_back(d);
+        if (ready.empty()) return MPPI_OK;
+        std::stable_sort(ready.begin(), ready.end(), [&](int x, int y) {
+            return s->queue[x][s->head[x]].t_arrival < s->queue[y][s->head[y]].t_arrival;
+        });
+        std::vector<int32_t> active;
+        std::vector<char *> ws;
+        for (int d : ready) {
+            if (s->cfg.max_batch > 0 && (int)active.size() >= s->cfg.max_batch) break;
+            size_t off = 0;
+            if (!s->arena.alloc(s->drones[d]->ws_bytes, &off)) continue;  // waits for memory
+            const Request &rq = s->queue[d][s->head[d]];
+            const int i = (int)active.size();
+            for (int c = 0; c < 13; ++c) sl.h_req[kReqDoubles * i + c] = rq.x0[c];
+            sl.h_req[kReqDoubles * i + 13] = rq.t_now;
+            active.push_back(d);
+            ws.push_back(s->arena_base + off);
+            sl.flight.push_back(InFlight{d, rq.ticket, rq.t_arrival, now, off});
+            s->busy[d] = 1;
+            s->head[d] += 1;
+            if (s->head[d] == s->queue[d].size()) { s->queue[d].clear(); s->head[d] = 0; }
+        }
+        if (active.empty()) return MPPI_OK;  // nothing fits the free memory now
+        const int n = (int)active.size();
+        if (s->arena.in_use > s->st.peak_bytes_in_flight) s->st.peak_bytes_in_flight = (double)s->arena.in_use;
+        if (hipMemcpyAsync(sl.d_req, sl.h_req, sizeof(double) * kReqDoubles * n, hipMemcpyHostToDevice, sl.stream) !=
+            hipSuccess)
+            return sfail(s, MPPI_E_DEVICE, "request copy failed");
+        mppi_status st = batch_solve(sl.batch, active.data(), n, sl.d_req, sl.d_u0, ws.data());
+        if (st != MPPI_OK) return sfail(s, st, "batch launch failed: %s", sl.batch->err.c_str());
+        if (hipMemcpyAsync(sl.h_u0, sl.d_u0, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
+            hipEventRecord(sl.done, sl.stream) != hipSuccess)
+            return sfail(s, MPPI_E_DEVICE, "result copy failed");
+        sl.busy = true;
+        s->st.launches += 1;
+        s->st.queued -= n;
+        s->st.in_flight += n;
+        if (n_launched) *n_launched += 1;
+    }
+    return MPPI_OK;
+}
+
+extern "C" {
+
+const char *mppi_server_last_error(const mppi_server *s) { return s ? s->err.c_str() : g_create_err.c_str(); }
+
+void mppi_server_destroy(mppi_server *s) { release_server(s); }
+
+mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_server_cfg *cfg, mppi_server **out)
+{
+    if (!out) return sfail(nullptr, MPPI_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!drones || n < 1 || !cfg) return sfail(nullptr, MPPI_E_INVAL, "drones and cfg are required");
+    if (!(cfg->budget_bytes > 0.0) || cfg->n_slots < 1 || cfg->n_slots > 16 || cfg->max_batch < 0)
+        return sfail(nullptr, MPPI_E_INVAL, "invalid server configuration");
+    for (int i = 0; i < n; ++i)
+        if (!drones[i] || !drones[i]->external_ws)
+            return sfail(nullptr, MPPI_E_INVAL, "drone %d: context must be created with MPPI_FLAG_EXTERNAL_WORKSPACE", i);
+    mppi_server *s = new (std::nothrow) mppi_server();
+    if (!s) return sfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
+    s->drones.assign(drones, drones + n);
+    s->cfg = *cfg;
+    s->queue.resize(n);
+    s->head.assign(n, 0);
+    s->busy.assign(n, 0);
+    const size_t arena = (size_t)cfg->budget_bytes;
+    if (hipMalloc((void **)&s->arena_base, arena) != hipSuccess) {
+        release_server(s);
+        return sfail(nullptr, MPPI_E_NOMEM, "arena of %zu bytes could not be allocated", arena);
+    }
+    s->arena.reset(arena);
+    s->st.arena_bytes = (double)arena;
+    s->slots.resize(cfg->n_slots);
+    for (auto &sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void **)&sl.h_req, sizeof(double) * kReqDoubles * n, 0) != hipSuccess ||
+            hipHostMalloc((void **)&sl.h_u0, sizeof(double) * 4 * n, 0) != hipSuccess ||
+            hipMalloc((void **)&sl.d_req, sizeof(double) * kReqDoubles * n) != hipSuccess ||
+            hipMalloc((void **)&sl.d_u0, sizeof(double) * 4 * n) != hipSuccess) {
+            release_server(s);
+            return sfail(nullptr, MPPI_E_NOMEM, "slot resources could not be allocated");
+        }
+        mppi_batch_cfg bc{0, 0, 0, cfg->use_graph ? 1 : 0};
+        mppi_status st = mppi_batch_create(drones, n, sl.stream, &bc, &sl.batch);
+        if (st != MPPI_OK) {
+            std::string e = g_create_err;
+            release_server(s);
+            return sfail(nullptr, st, "slot batch: %s", e.c_str());
+        }
+    }
+    *out = s;
+    return MPPI_OK;
+}
+
+mppi_status mppi_server_submit(mppi_server *s, int32_t drone, const double x0[13], double t_now, double t_arrival,
+                               uint64_t *ticket)
+{
+    if (!s || !x0) return sfail(s, MPPI_E_INVAL, "server and x0 are required");
+    if (drone < 0 || drone >= (int)s->drones.size()) return sfail(s, MPPI_E_INVAL, "drone %d out of range", drone);
+    if (!finite_all(x0, 13) || !isfinite(t_now)) return sfail(s, MPPI_E_INVAL, "x0 and t_now must be finite");
+    const double qn = x0[6] * x0[6] + x0[7] * x0[7] + x0[8] * x0[8] + x0[9] * x0[9];
+    if (!(qn > 0.0)) return sfail(s, MPPI_E_INVAL, "quaternion of x0 has zero norm");
+    if (align_up(s->drones[drone]->ws_bytes, 256) > s->arena.size)
+        return sfail(s, MPPI_E_NOMEM, "drone %d needs %zu workspace bytes, the arena has %zu", drone,
+                     s->drones[drone]->ws_bytes, s->arena.size);
+    Request r;
+    r.ticket = s->next_ticket++;
+    memcpy(r.x0, x0, sizeof r.x0);
+    r.t_now = t_now;
+    r.t_arrival = t_arrival;
+    s->queue[drone].push_back(r);
+    s->st.submitted += 1;
+    s->st.queued += 1;
+    if (ticket) *ticket = r.ticket;
+    return MPPI_OK;
+}
+
+mppi_status mppi_server_progress(mppi_server *s, double now, int32_t *n_launched)
+{
+    if (!s) return sfail(nullptr, MPPI_E_INVAL, "server is NULL");
+    if (n_launched) *n_launched = 0;
+    mppi_status st = retire(s, now, false);
+    if (st != MPPI_OK) return st;
+    return admit(s, now, n_launched);
+}
+
+mppi_status mppi_server_drain(mppi_server *s, double now)
+{
+    if (!s) return sfail(nullptr, MPPI_E_INVAL, "server is NULL");
+    for (;;) {
+        mppi_status st = mppi_server_progress(s, now, nullptr);
+        if (st != MPPI_OK) return st;
+        if (s->st.queued == 0 && s->st.in_flight == 0) return MPPI_OK;
+        if ((st = retire(s, now, true)) != MPPI_OK) return st;
+    }
+}
+
+mppi_status mppi_server_poll(mppi_server *s, mppi_result *out, int32_t max, int32_t *n_out)
+{
+    if (!s || !n_out || (max > 0 && !out)) return sfail(s, MPPI_E_INVAL, "invalid poll arguments");
+    int32_t k = 0;
+    while (k < max && s->done_head < s->done.size()) out[k++] = s->done[s->done_head++];
+    if (s->done_head == s->done.size()) { s->done.clear(); s->done_head = 0; }
+    *n_out = k;
+    return MPPI_OK;
+}
+
+mppi_status mppi_server_get_stats(const mppi_server *s, mppi_server_stats *out)
+{
+    if (!s || !out) return MPPI_E_INVAL;
+    *out = s->st;
     return MPPI_OK;
 }
 

@@ -25,7 +25,11 @@ FP32, FP64 = 0, 1
 
 EXPORTS = ["mppi_create", "mppi_destroy", "mppi_solve", "mppi_solve_device", "mppi_read_info",
            "mppi_read_samples", "mppi_get_warm", "mppi_set_warm", "mppi_last_error",
-           "mppi_status_string", "mppi_plant_step", "mppi_set_profiling", "mppi_read_profile"]
+           "mppi_status_string", "mppi_plant_step", "mppi_set_profiling", "mppi_read_profile",
+           "mppi_batch_create", "mppi_batch_solve_device", "mppi_batch_set_cfg", "mppi_batch_get_cfg",
+           "mppi_batch_autotune", "mppi_batch_destroy", "mppi_batch_last_error",
+           "mppi_server_create", "mppi_server_submit", "mppi_server_progress", "mppi_server_poll",
+           "mppi_server_drain", "mppi_server_get_stats", "mppi_server_destroy", "mppi_server_last_error"]
 
 
 class MppiError(RuntimeError):
@@ -48,7 +52,10 @@ class mppi_params(C.Structure):
                 ("Q", C.c_double * 13), ("QN", C.c_double * 13), ("R_dT", C.c_double * 4),
                 ("q_l", C.c_double), ("q_c", C.c_double), ("Q_w", C.c_double * 3),
                 ("r_dv", C.c_double), ("mu", C.c_double), ("v_max", C.c_double),
-                ("proj_window", C.c_int32), ("pad_", C.c_int32)]
+                ("proj_window", C.c_int32), ("flags", C.c_int32)]
+
+
+FLAG_EXTERNAL_WORKSPACE = 1
 
 
 class mppi_problem(C.Structure):
@@ -81,6 +88,34 @@ class mppi_warm(C.Structure):
                 ("N", C.c_int32), ("allow", C.c_uint32 * MASK_WORDS), ("t_prev", C.c_double),
                 ("x_prev", C.c_double * 13), ("theta0", C.c_double),
                 ("U", C.c_double * (N_MAX * 4)), ("V", C.c_double * N_MAX)]
+
+
+class mppi_batch_cfg(C.Structure):
+    _fields_ = [("rollout_waves", C.c_int32), ("rollout_groups", C.c_int32),
+                ("sample_groups", C.c_int32), ("use_graph", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class mppi_server_cfg(C.Structure):
+    _fields_ = [("budget_bytes", C.c_double), ("n_slots", C.c_int32), ("max_batch", C.c_int32),
+                ("use_graph", C.c_int32), ("pad_", C.c_int32)]
+
+
+class mppi_result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("drone", C.c_int32), ("status", C.c_int32),
+                ("u0", C.c_double * 4), ("t_arrival", C.c_double), ("t_launch", C.c_double),
+                ("t_done", C.c_double)]
+
+
+class mppi_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("launches", C.c_uint64),
+                ("queued", C.c_int64), ("in_flight", C.c_int64), ("arena_bytes", C.c_double),
+                ("peak_bytes_in_flight", C.c_double), ("rollout_steps", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _D = C.POINTER(C.c_double)
@@ -127,6 +162,39 @@ def _load():
     L.mppi_set_profiling.restype = C.c_int
     L.mppi_read_profile.argtypes = [_P, _D, C.POINTER(C.c_int32)]
     L.mppi_read_profile.restype = C.c_int
+    L.mppi_batch_create.argtypes = [C.POINTER(_P), C.c_int32, _P, C.POINTER(mppi_batch_cfg),
+                                    C.POINTER(_P)]
+    L.mppi_batch_create.restype = C.c_int
+    L.mppi_batch_solve_device.argtypes = [_P, C.POINTER(C.c_int32), C.c_int32, _P, _P]
+    L.mppi_batch_solve_device.restype = C.c_int
+    L.mppi_batch_set_cfg.argtypes = [_P, C.POINTER(mppi_batch_cfg)]
+    L.mppi_batch_set_cfg.restype = C.c_int
+    L.mppi_batch_get_cfg.argtypes = [_P, C.POINTER(mppi_batch_cfg)]
+    L.mppi_batch_get_cfg.restype = C.c_int
+    L.mppi_batch_autotune.argtypes = [_P, _P, _P, C.c_int32, C.POINTER(mppi_batch_cfg), _D]
+    L.mppi_batch_autotune.restype = C.c_int
+    L.mppi_batch_destroy.argtypes = [_P]
+    L.mppi_batch_destroy.restype = None
+    L.mppi_batch_last_error.argtypes = [_P]
+    L.mppi_batch_last_error.restype = C.c_char_p
+    L.mppi_server_create.argtypes = [C.POINTER(_P), C.c_int32, C.POINTER(mppi_server_cfg),
+                                     C.POINTER(_P)]
+    L.mppi_server_create.restype = C.c_int
+    L.mppi_server_submit.argtypes = [_P, C.c_int32, _D, C.c_double, C.c_double,
+                                     C.POINTER(C.c_uint64)]
+    L.mppi_server_submit.restype = C.c_int
+    L.mppi_server_progress.argtypes = [_P, C.c_double, C.POINTER(C.c_int32)]
+    L.mppi_server_progress.restype = C.c_int
+    L.mppi_server_poll.argtypes = [_P, C.POINTER(mppi_result), C.c_int32, C.POINTER(C.c_int32)]
+    L.mppi_server_poll.restype = C.c_int
+    L.mppi_server_drain.argtypes = [_P, C.c_double]
+    L.mppi_server_drain.restype = C.c_int
+    L.mppi_server_get_stats.argtypes = [_P, C.POINTER(mppi_server_stats)]
+    L.mppi_server_get_stats.restype = C.c_int
+    L.mppi_server_destroy.argtypes = [_P]
+    L.mppi_server_destroy.restype = None
+    L.mppi_server_last_error.argtypes = [_P]
+    L.mppi_server_last_error.restype = C.c_char_p
     return L
 
 
@@ -163,6 +231,7 @@ def make_params(p: dict, precision: int) -> mppi_params:
     s.q_l = p.get("q_l", 0.0); s.q_c = p.get("q_c", 0.0); s.Q_w[:] = list(p.get("Q_w", [0.0] * 3))
     s.r_dv = p.get("r_dv", 0.0); s.mu = p.get("mu", 0.0); s.v_max = p.get("v_max", 0.0)
     s.proj_window = p.get("proj_window", 64)
+    s.flags = p.get("flags", 0)
     return s
 
 
@@ -287,3 +356,122 @@ def plant_step(quad: dict, x, u, dt: float, substeps: int = 1):
     x = _f64(x, 13); u = _f64(u, 4); out = np.zeros(13)
     _check(lib.mppi_plant_step(C.byref(q), _dp(x), _dp(u), float(dt), int(substeps), _dp(out)))
     return out
+
+
+def _bcheck(st: int, b=None):
+    if st != OK:
+        raise MppiError(st, f"{lib.mppi_status_string(st).decode()}: {lib.mppi_batch_last_error(b).decode()}")
+
+
+class Batch:
+    """A batch of registered solvers stepped together (mppi_batch_*)."""
+
+    def __init__(self, solvers, stream=None, rollout_waves=0, rollout_groups=0, sample_groups=0,
+                 use_graph=True):
+        self.solvers = list(solvers)
+        arr = (_P * len(self.solvers))(*[sv.ctx.value if hasattr(sv.ctx, "value") else sv.ctx
+                                         for sv in self.solvers])
+        cfg = mppi_batch_cfg(rollout_waves, rollout_groups, sample_groups, 1 if use_graph else 0)
+        b = _P()
+        _bcheck(lib.mppi_batch_create(arr, len(self.solvers), _P(stream) if stream else None,
+                                      C.byref(cfg), C.byref(b)))
+        self.b = b
+
+    def solve_device(self, d_reqs: int, d_u0s: int, active=None):
+        n = len(self.solvers)
+        if active is None:
+            _bcheck(lib.mppi_batch_solve_device(self.b, None, n, _P(d_reqs), _P(d_u0s)), self.b)
+        else:
+            a = (C.c_int32 * len(active))(*[int(i) for i in active])
+            _bcheck(lib.mppi_batch_solve_device(self.b, a, len(active), _P(d_reqs), _P(d_u0s)), self.b)
+
+    def set_cfg(self, rollout_waves=0, rollout_groups=0, sample_groups=0, use_graph=True):
+        cfg = mppi_batch_cfg(rollout_waves, rollout_groups, sample_groups, 1 if use_graph else 0)
+        _bcheck(lib.mppi_batch_set_cfg(self.b, C.byref(cfg)), self.b)
+
+    def get_cfg(self) -> dict:
+        cfg = mppi_batch_cfg()
+        _bcheck(lib.mppi_batch_get_cfg(self.b, C.byref(cfg)), self.b)
+        return cfg.as_dict()
+
+    def autotune(self, d_reqs: int, d_u0s: int, reps: int = 3):
+        best = mppi_batch_cfg()
+        ms = C.c_double()
+        _bcheck(lib.mppi_batch_autotune(self.b, _P(d_reqs), _P(d_u0s), int(reps), C.byref(best),
+                                        C.byref(ms)), self.b)
+        return best.as_dict(), ms.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib.mppi_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scheck(st: int, srv=None):
+    if st != OK:
+        raise MppiError(st, f"{lib.mppi_status_string(st).decode()}: {lib.mppi_server_last_error(srv).decode()}")
+
+
+class Server:
+    """Continuous-batching server over drone contexts (mppi_server_*).  The
+    solvers must be created with params["flags"] = FLAG_EXTERNAL_WORKSPACE."""
+
+    def __init__(self, solvers, budget_bytes: float, n_slots: int = 2, max_batch: int = 0,
+                 use_graph: bool = True):
+        self.solvers = list(solvers)
+        arr = (_P * len(self.solvers))(*[sv.ctx.value if hasattr(sv.ctx, "value") else sv.ctx
+                                         for sv in self.solvers])
+        cfg = mppi_server_cfg(float(budget_bytes), int(n_slots), int(max_batch), 1 if use_graph else 0, 0)
+        s = _P()
+        _scheck(lib.mppi_server_create(arr, len(self.solvers), C.byref(cfg), C.byref(s)))
+        self.s = s
+        self._buf = (mppi_result * 4096)()
+
+    def submit(self, drone: int, x0, t_now: float, t_arrival: float) -> int:
+        x = _f64(x0, 13)
+        t = C.c_uint64()
+        _scheck(lib.mppi_server_submit(self.s, int(drone), _dp(x), float(t_now), float(t_arrival),
+                                       C.byref(t)), self.s)
+        return t.value
+
+    def progress(self, now: float) -> int:
+        n = C.c_int32()
+        _scheck(lib.mppi_server_progress(self.s, float(now), C.byref(n)), self.s)
+        return n.value
+
+    def drain(self, now: float):
+        _scheck(lib.mppi_server_drain(self.s, float(now)), self.s)
+
+    def poll(self):
+        out = []
+        while True:
+            n = C.c_int32()
+            _scheck(lib.mppi_server_poll(self.s, self._buf, len(self._buf), C.byref(n)), self.s)
+            for i in range(n.value):
+                r = self._buf[i]
+                out.append(dict(ticket=r.ticket, drone=r.drone, status=r.status, u0=list(r.u0),
+                                t_arrival=r.t_arrival, t_launch=r.t_launch, t_done=r.t_done))
+            if n.value < len(self._buf):
+                return out
+
+    def stats(self) -> dict:
+        st = mppi_server_stats()
+        _scheck(lib.mppi_server_get_stats(self.s, C.byref(st)), self.s)
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "s", None):
+            lib.mppi_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

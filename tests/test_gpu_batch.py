@@ -1,0 +1,140 @@
+"""Batched solves (one persistent launch sequence for many uneven contexts)
+against the same contexts solved alone, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_14726_amd import mppi as M
+from paper_2509_14726_amd import synth
+from tests.parity import build_pair, solve_and_compare, warm_to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def make_instances(n, seed, objectives=("gate",), precision=M.FP32):
+    rng = np.random.default_rng(seed)
+    inst = []
+    for i in range(n):
+        K = int(rng.choice([64, 200, 1024, 2048]))
+        N = int(rng.integers(5, 60))
+        obj = objectives[i % len(objectives)]
+        w = synth.single_solve_workload(K=K, N=N, objective=obj, seed=100 + i, track_seed=100 + i,
+                                        n_gates=int(rng.integers(5, 13)), **{"lambda": 30.0})
+        inst.append(w)
+    return inst
+
+
+def solver_for(w, precision):
+    return M.Solver(w["quad"], w["params"], gates=w["gates"], path=w.get("path"),
+                    path_len=w.get("path_len", 0.0), xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0),
+                    precision=precision)
+
+
+@pytest.mark.parametrize("precision", [M.FP32, M.FP64])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_equals_solo(precision, use_graph, monkeypatch):
+    import torch
+    say("batch vs solo", precision, "graph", use_graph)
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "2")
+    inst = make_instances(12, seed=1, objectives=("gate", "contour", "track"), precision=precision)
+    solo = [solver_for(w, precision) for w in inst]
+    bat = [solver_for(w, precision) for w in inst]
+    B = M.Batch(bat, rollout_waves=2, use_graph=use_graph)
+    n = len(inst)
+    reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    u0s = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    xs = [w["x0"].copy() for w in inst]
+    for step in range(4):
+        for i, w in enumerate(inst):
+            reqs[i, :13] = torch.from_numpy(xs[i])
+            reqs[i, 13] = step * w["params"]["dt"]
+        torch.cuda.synchronize()
+        B.solve_device(reqs.data_ptr(), u0s.data_ptr())
+        torch.cuda.synchronize()
+        got = u0s.cpu().numpy()
+        for i, w in enumerate(inst):
+            u0, U, info = solo[i].solve(xs[i], step * w["params"]["dt"])
+            st, info_b = bat[i].read_info()
+            assert st == M.OK
+            assert np.array_equal(got[i], u0), (step, i, got[i], u0)
+            assert info_b["J_min"] == info["J_min"] and info_b["g0"] == info["g0"]
+            Jb, _ = bat[i].read_samples()
+            Js, _ = solo[i].read_samples()
+            assert np.array_equal(Jb, Js)
+            xs[i] = M.plant_step(w["quad"], xs[i], u0, w["params"]["dt"], 2)
+    B.close()
+
+
+def test_batch_subsets_and_graph_replays():
+    """Replays of one captured graph with changing subsets: each replay
+    equals the eager (uncaptured) result for the same subset, and contexts
+    outside a subset keep their warm state."""
+    import torch
+    say("subsets")
+    inst = make_instances(10, seed=2)
+    A = [solver_for(w, M.FP32) for w in inst]
+    E = [solver_for(w, M.FP32) for w in inst]
+    BA = M.Batch(A, rollout_waves=1, use_graph=True)
+    BE = M.Batch(E, rollout_waves=1, use_graph=False)
+    n = len(inst)
+    reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    for i, w in enumerate(inst):
+        reqs[i, :13] = torch.from_numpy(w["x0"])
+    ua = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    ue = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    subsets = [list(range(n)), [3, 1, 7], [0], [9, 8, 7, 6, 5, 4], [2, 5]]
+    count = [0] * n
+    for r, sub in enumerate(subsets):
+        sub_reqs = reqs[sub].contiguous()
+        sub_reqs[:, 13] = 0.02 * (r + 1)
+        torch.cuda.synchronize()
+        BA.solve_device(sub_reqs.data_ptr(), ua.data_ptr(), active=sub)
+        BE.solve_device(sub_reqs.data_ptr(), ue.data_ptr(), active=sub)
+        torch.cuda.synchronize()
+        assert torch.equal(ua[:len(sub)], ue[:len(sub)]), r
+        for i in sub:
+            count[i] += 1
+        for i in range(n):
+            assert A[i].get_warm().solve_index == count[i] == E[i].get_warm().solve_index
+    BA.close()
+    BE.close()
+
+
+def test_batch_rejects_bad_arguments():
+    say("batch args")
+    inst = make_instances(2, seed=3)
+    S = [solver_for(w, M.FP32) for w in inst]
+    with pytest.raises(M.MppiError):
+        M.Batch([S[0], S[0]])
+    B = M.Batch(S)
+    with pytest.raises(M.MppiError):
+        B.solve_device(0, 0, active=[0])  # null requests
+    import torch
+    reqs = torch.zeros((2, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    with pytest.raises(M.MppiError):
+        B.solve_device(reqs.data_ptr(), 0, active=[0, 0])
+    with pytest.raises(M.MppiError):
+        B.solve_device(reqs.data_ptr(), 0, active=[5])
+    B.close()
+
+
+def test_autotuner_picks_a_valid_shape():
+    import torch
+    say("autotune")
+    inst = make_instances(8, seed=4)
+    S = [solver_for(w, M.FP32) for w in inst]
+    B = M.Batch(S)
+    reqs = torch.zeros((len(S), M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    for i, w in enumerate(inst):
+        reqs[i, :13] = torch.from_numpy(w["x0"])
+    u0s = torch.zeros((len(S), 4), dtype=torch.float64, device="cuda")
+    best, ms = B.autotune(reqs.data_ptr(), u0s.data_ptr(), reps=2)
+    say("  best", best, ms)
+    assert best["rollout_waves"] in (1, 2) and best["rollout_groups"] > 0 and ms > 0
+    assert B.get_cfg()["rollout_waves"] == best["rollout_waves"]
+    B.close()

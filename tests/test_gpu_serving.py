@@ -1,0 +1,95 @@
+"""Serving: continuous batching of solves from many drones.  Each result of
+the mix must equal the same drone's solve sequence run alone (same warm-start
+history), with the memory budget forcing admissions to wait."""
+import numpy as np
+import pytest
+
+from paper_2509_14726_amd import mppi as M
+from paper_2509_14726_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def drones(n, seed, external):
+    rng = np.random.default_rng(seed)
+    out = []
+    for d in range(n):
+        K = int(rng.choice([128, 512, 1024]))
+        N = int(rng.choice([20, 40]))
+        obj = "gate" if d % 2 == 0 else "contour"
+        w = synth.single_solve_workload(K=K, N=N, objective=obj, seed=400 + d, track_seed=400 + d,
+                                        **{"lambda": 30.0})
+        if external:
+            w["params"] = dict(w["params"], flags=M.FLAG_EXTERNAL_WORKSPACE)
+        out.append(w)
+    return out
+
+
+def solver(w, prec=M.FP32):
+    return M.Solver(w["quad"], w["params"], gates=w["gates"], path=w.get("path"),
+                    path_len=w.get("path_len", 0.0), precision=prec)
+
+
+@pytest.mark.parametrize("budget_mb,slots", [(512.0, 2), (2.0, 3)])
+def test_alone_vs_mix(budget_mb, slots, monkeypatch):
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "2")
+    say("alone vs mix", budget_mb, slots)
+    n = 10
+    ws = drones(n, 7, external=True)
+    wa = drones(n, 7, external=False)
+    served = [solver(w) for w in ws]
+    alone = [solver(w) for w in wa]
+    S = M.Server(served, budget_bytes=budget_mb * 2 ** 20, n_slots=slots, max_batch=4)
+    rng = np.random.default_rng(3)
+    steps = 4
+    # each drone: a fixed sequence of requests (states from its own plant)
+    xs = [w["x0"].copy() for w in wa]
+    expected = {}
+    reqs = []
+    for k in range(steps):
+        for d in range(n):
+            t = k * 0.02
+            u0, _, _ = alone[d].solve(xs[d], t)
+            expected[(d, k)] = u0
+            reqs.append((rng.uniform(0, 1) + k, d, xs[d].copy(), t, k))
+            xs[d] = M.plant_step(wa[d]["quad"], xs[d], u0, 0.02, 2)
+    reqs.sort(key=lambda r: r[0])
+    tick = {}
+    for i, (ta, d, x, t, k) in enumerate(reqs):
+        tick[S.submit(d, x, t, ta)] = (d, k)
+        if i % 5 == 0:
+            S.progress(float(i))
+    S.drain(1e9)
+    res = S.poll()
+    assert len(res) == n * steps
+    seen = set()
+    for r in res:
+        d, k = tick[r["ticket"]]
+        assert r["drone"] == d and r["status"] == M.OK
+        assert np.array_equal(np.array(r["u0"]), expected[(d, k)]), (d, k)
+        seen.add((d, k))
+    assert len(seen) == n * steps
+    st = S.stats()
+    say("  stats", st)
+    assert st["completed"] == n * steps and st["queued"] == 0 and st["in_flight"] == 0
+    assert st["peak_bytes_in_flight"] <= budget_mb * 2 ** 20
+    S.close()
+
+
+def test_server_rejects_oversized_and_plain_contexts():
+    say("server args")
+    ws = drones(2, 8, external=True)
+    served = [solver(w) for w in ws]
+    with pytest.raises(M.MppiError):
+        M.Server([solver(drones(1, 9, external=False)[0])], budget_bytes=1 << 20)
+    S = M.Server(served, budget_bytes=4096)
+    with pytest.raises(M.MppiError) as e:
+        S.submit(0, ws[0]["x0"], 0.0, 0.0)
+    assert e.value.status == M.E_NOMEM
+    S.close()
+    with pytest.raises(M.MppiError):
+        served[0].solve(ws[0]["x0"], 0.0)  # no workspace of its own
