@@ -51,6 +51,78 @@ def cpu_baseline(w, seconds: float = 12.0):
             "sample": f"{n} full solves of the benchmark workload (K={K}, N={N}) in {el:.1f} s, FP64"}
 
 
+def batched_bench(steps: int = 20, n: int = 256):
+    """256 uneven instances (K in {1024..16384}, N in [30, 150], 5-12 gates),
+    one persistent launch sequence per step under a captured HIP graph, launch
+    shape picked by the autotuner.  Returns rollout-steps/s over the batch."""
+    import torch
+    from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import synth
+    specs = synth.batch_instances(n)
+    ws = [synth.single_solve_workload(K=d["K"], N=d["N"], n_gates=d["n_gates"], track_seed=d["track_seed"],
+                                      seed=d["seed"]) for d in specs]
+    stream = torch.cuda.current_stream()
+    solvers = [M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32) for w in ws]
+    B = M.Batch(solvers, stream=stream.cuda_stream)
+    reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    for i, w in enumerate(ws):
+        reqs[i, :13] = torch.from_numpy(w["x0"])
+    u0s = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    best, tuned_ms = B.autotune(reqs.data_ptr(), u0s.data_ptr(), reps=3)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        B.solve_device(reqs.data_ptr(), u0s.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    work = sum(d["K"] * d["N"] for d in specs)
+    assert torch.isfinite(u0s).all().item()
+    B.close()
+    for sv in solvers:
+        sv.close()
+    return {"instances": n, "rollout_steps_per_batch": work, "ms_per_batch": ms,
+            "rollout_steps_per_s": work / (ms * 1e-3), "autotuned": best, "autotune_ms": tuned_ms,
+            "graph": True, "precision": "fp32"}
+
+
+def large_bench(steps: int = 5):
+    """K = 262144, N = 200, dt = 0.01 on a 12-gate track: the N x K x 4 sample
+    tensor (839 MB) streams through HBM; the final average accumulates in
+    binary64."""
+    import torch
+    from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import synth
+    w = synth.single_solve_workload(K=262144, N=200, dt=0.01, n_gates=12, track_seed=5, seed=5)
+    stream = torch.cuda.current_stream()
+    sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32, stream=stream.cuda_stream)
+    req = torch.zeros((steps + 1, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    req[:, :13] = torch.from_numpy(w["x0"]).cuda()
+    req[:, 13] = torch.arange(steps + 1, dtype=torch.float64, device="cuda") * 0.01
+    u0 = torch.zeros((steps + 1, 4), dtype=torch.float64, device="cuda")
+    sv.solve_device(req[0].data_ptr(), u0[0].data_ptr())
+    torch.cuda.synchronize()
+    sv.set_profiling(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(1, steps + 1):
+        sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kern, _ = sv.read_profile()
+    sv.close()
+    K, N = 262144, 200
+    avg_bytes = K * N * 16 + K * 4 * N  # sample tensor + costs re-read per step tile
+    return {"K": K, "N": N, "ms_per_solve": ms, "rollout_steps_per_s": K * N / (ms * 1e-3),
+            "kernels_ms": {"sample": float(kern[0]), "rollout": float(kern[1]), "average": float(kern[2])},
+            "average_GBps": avg_bytes / (float(kern[2]) * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +132,9 @@ def main():
     ap.add_argument("--N", type=int, default=100)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, large-solve and serving measurements")
+    ap.add_argument("--serving-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -135,6 +210,18 @@ def main():
                      "kernel": "k_rollout", "flops_per_launch": flops},
     }
     solver.close()
+    if not args.no_extras:
+        for name, fn in (("batched", batched_bench), ("large", large_bench)):
+            try:
+                out[name] = fn()
+            except Exception as e:  # reported, never silently dropped
+                out[name] = {"error": repr(e)}
+        try:
+            from paper_2509_14726_amd import serving
+            out["serving"] = serving.simulate(n_drones=512, seconds=args.serving_seconds, rate_hz=50.0,
+                                              budget_bytes=32 * 2 ** 30, n_slots=4)
+        except Exception as e:
+            out["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

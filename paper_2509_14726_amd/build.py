@@ -12,8 +12,11 @@ SOURCES = ["kernels.hip", "runtime.hip"]
 ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for every HIP source: the compiler
-# forms them on its own from scalar float code otherwise.
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
+# forms them on its own from scalar float code otherwise.  Multiply-adds are
+# contracted per source expression only (-ffp-contract=on), so every kernel
+# that inlines the same device code rounds the same way: a batched solve
+# reproduces the stand-alone solve bit for bit.
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]
 

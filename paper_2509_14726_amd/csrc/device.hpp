@@ -192,6 +192,11 @@ template <> struct KSum<double> {
     __device__ __forceinline__ double value() const { return s; }
 };
 
+// 1/sqrt(x): the hardware reciprocal square root in binary32 (about 1 ulp),
+// the accurate quotient in binary64.
+__device__ __forceinline__ float inv_sqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
 // Rounding of the warm-start shift and reference row: floor(x + 1/2).
 __device__ __forceinline__ int round_half_up(double x) { return (int)floor(x + 0.5); }
 

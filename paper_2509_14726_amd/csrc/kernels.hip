@@ -135,7 +135,6 @@ __device__ void solve_head(const KArgs &a)
         theta0 = wrap_len_d(s_th[0], L);
     }
 
-    for (int k = tid; k < a.N; k += blockDim.x) a.tickets[k] = 0u;
     if (tid == 0) {
         const double t_now = a.req[13];
         int g0 = w->g0;
@@ -159,7 +158,6 @@ __device__ void solve_head(const KArgs &a)
         c->warm = warm;
         c->s = w->s;
         c->ticket = 0u;
-        a.tickets[kNMax] = 0u;
         c->jmin32 = ordered_bits(INFINITY);
         c->jmin64 = ordered_bits((double)INFINITY);
         for (int j = 0; j < kMaskWords; ++j) c->allow[j] = allow[j];
@@ -345,7 +343,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(
                 const Real g1 = Real(1) - f;
                 const Real px = g1 * A[0] + f * B[0], py = g1 * A[1] + f * B[1], pz = g1 * A[2] + f * B[2];
                 Real tx = g1 * A[3] + f * B[3], ty = g1 * A[4] + f * B[4], tz = g1 * A[5] + f * B[5];
-                const Real tn = Real(1) / sqrt(tx * tx + ty * ty + tz * tz);
+                const Real tn = inv_sqrt(tx * tx + ty * ty + tz * tz);
                 tx *= tn; ty *= tn; tz *= tn;
                 const Real ex = (st.x[0] - px) + lo_of(st, 0);
                 const Real ey = (st.x[1] - py) + lo_of(st, 1);
@@ -535,12 +533,17 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
     const Real q_near = (Real)a.q_near, r_near2 = (Real)(a.r_near * a.r_near), half = (Real)a.gate_half;
 
     const int nch = (N + B - 1) / B;
+    // the control of the next step is always in flight while a step computes
+    R4 u_next = urow[0];
+    Real v_next = Real(0);
+    if (OBJ == OBJ_CONTOUR && wave == 1) v_next = vrow[0];
     for (int c = 0; c <= nch; ++c) {
         if (wave == 0 && c < nch) {
             const int kb = c * B, ke = min(N, kb + B);
             for (int k = kb; k < ke; ++k) {
                 R4 (*slot)[64] = s_q[c & 1][k - kb];
-                const R4 u = urow[(size_t)k * ustride];
+                const R4 u = u_next;
+                if (k + 1 < N) u_next = urow[(size_t)(k + 1) * ustride];
                 Real term = Real(0);
                 if (OBJ == OBJ_TRACK) {
                     int r = i0 + k;
@@ -624,7 +627,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                         q[i] = t;
                     }
                     const Real n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-                    const Real r = Real(1) / sqrt(n2);
+                    const Real r = inv_sqrt(n2);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const Real ph = q[i] * r;
@@ -654,7 +657,11 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
             const int kb = (c - 1) * B, ke = min(N, kb + B);
             for (int k = kb; k < ke; ++k) {
                 R4 (*slot)[64] = s_q[(c - 1) & 1][k - kb];
-                const R4 u = urow[(size_t)k * ustride];
+                const R4 u = u_next;
+                if (k + 1 < N) u_next = urow[(size_t)(k + 1) * ustride];
+                R4 qstage[4];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) qstage[st] = slot[st][lane];
                 const Real fm = ((u.x + u.y) + (u.z + u.w)) * M.inv_m;
                 Real term = Real(0);
                 Real ax = 0, ay = 0, az = 0;
@@ -691,7 +698,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                     const Real g1 = Real(1) - f;
                     const Real px = g1 * A[0] + f * Bp[0], py = g1 * A[1] + f * Bp[1], pz = g1 * A[2] + f * Bp[2];
                     Real tx = g1 * A[3] + f * Bp[3], ty = g1 * A[4] + f * Bp[4], tz = g1 * A[5] + f * Bp[5];
-                    const Real tn = Real(1) / sqrt(tx * tx + ty * ty + tz * tz);
+                    const Real tn = inv_sqrt(tx * tx + ty * ty + tz * tz);
                     tx *= tn; ty *= tn; tz *= tn;
                     const Real ex = (p[0] - px) + pl[0];
                     const Real ey = (p[1] - py) + pl[1];
@@ -701,7 +708,8 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                     const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
                     term += (Real)a.q_l * (lx * lx + ly * ly + lz * lz);
                     term += (Real)a.q_c * (cxe * cxe + cye * cye + cze * cze);
-                    const Real vk = vrow[(size_t)k * ustride];
+                    const Real vk = v_next;
+                    if (k + 1 < N) v_next = vrow[(size_t)(k + 1) * ustride];
                     const Real dv = vk - vp;
                     term += (Real)(a.r_dv / (a.dt * a.dt)) * dv * dv;
                     term -= (Real)a.mu * vk;
@@ -718,7 +726,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                 for (int i = 0; i < 3; ++i) vs[i] = v[i];
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
-                    const R4 qq = slot[st][lane];
+                    const R4 qq = qstage[st];
                     const Real r3x = Real(2) * (qq.y * qq.w + qq.x * qq.z);
                     const Real r3y = Real(2) * (qq.z * qq.w - qq.x * qq.y);
                     const Real r3z = Real(1) - Real(2) * (qq.y * qq.y + qq.z * qq.z);
@@ -862,11 +870,9 @@ template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
 
 // Block (mt, k) forms, for sample tile mt of step k,
 //   sum_m w~_m U^m_k  (C channels)   and, for k == 0,  sum_m w~_m, sum_m w~_m^2
-// with w~_m = exp(-(J_m - J_min)/lambda) (0 for non-finite J_m).  The last
-// block of step k to finish adds the tiles of that step in tile order; the
-// last step to be merged runs the tail: U = sums / S, first input, report and
-// warm-start hand-over.  Every sum has a fixed order, so results repeat bit
-// for bit.
+// with w~_m = exp(-(J_m - J_min)/lambda) (0 for non-finite J_m), and stores
+// them as partials.  No block waits for another: the tiles are merged by
+// the tail kernel that follows.
 template <typename Real, typename Acc, bool HAS_V>
 __device__ __forceinline__ void average_body(const KArgs &a, int mt, int k)
 {
@@ -874,7 +880,6 @@ __device__ __forceinline__ void average_body(const KArgs &a, int mt, int k)
     constexpr int NV = C + 2;
     typedef typename Vec4<Real>::T R4;
     __shared__ Acc s_red[4][NV];
-    __shared__ unsigned s_last;
 
     const int tid = threadIdx.x;
     const int K = a.K, N = a.N;
@@ -913,62 +918,52 @@ __device__ __forceinline__ void average_body(const KArgs &a, int mt, int k)
     __syncthreads();
     Acc *part = (Acc *)a.part;                          // [N][n_mt][C]
     Acc *part_den = part + (size_t)N * n_mt * C;        // [n_mt][2]
-    Acc *stage = part_den + 2 * (size_t)n_mt;           // [N][C] step sums, then [2] S, S2
     if (tid < NV) {
         const Acc r = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
         if (tid < C) part[((size_t)k * n_mt + mt) * C + tid] = r;
         else if (k == 0) part_den[2 * mt + (tid - C)] = r;
     }
-
-    // last tile of this step: merge the step
-    __threadfence();
     __syncthreads();
-    if (tid == 0) {
-        const unsigned t = __hip_atomic_fetch_add(&a.tickets[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == (unsigned)n_mt - 1) ? 1u : 0u;
+}
+
+// One block: adds the tiles of every step in tile order, forms U = sums / S,
+// writes the first input, the report and the warm-start hand-over, and
+// re-arms the running minimum for the next solve.
+template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(const KArgs &a)
+{
+    constexpr int C = HAS_V ? 5 : 4;
+    __shared__ Acc s_u[kNMax * C];
+    __shared__ Acc s_den[2];
+    const int tid = threadIdx.x;
+    const int N = a.N, n_mt = a.n_mt;
+    const Acc *part = (const Acc *)a.part;
+    const Acc *part_den = part + (size_t)N * n_mt * C;
+    DevCur *cur = a.cur;
+    const double jmin = a.real_bytes == 4 ? (double)from_ordered(cur->jmin32) : from_ordered(cur->jmin64);
+    if (tid < 2) {
+        Acc sden = 0;
+        for (int t = 0; t < n_mt; ++t) sden += part_den[2 * t + tid];
+        s_den[tid] = sden;
+    }
+    for (int idx = tid; idx < N * C; idx += blockDim.x) {
+        const int k = idx / C, ch = idx % C;
+        Acc sum = 0;
+        for (int t = 0; t < n_mt; ++t) sum += part[((size_t)k * n_mt + t) * C + ch];
+        s_u[idx] = sum;
     }
     __syncthreads();
-    const bool merge_step = s_last != 0u;
-    __syncthreads();
-    if (!merge_step) return;
-    __threadfence();
-    if (tid < C) {
-        Acc s = 0;
-        for (int t = 0; t < n_mt; ++t) s += part[((size_t)k * n_mt + t) * C + tid];
-        stage[(size_t)k * C + tid] = s;
-    } else if (k == 0 && tid < C + 2) {
-        Acc s = 0;
-        for (int t = 0; t < n_mt; ++t) s += part_den[2 * t + (tid - C)];
-        stage[(size_t)N * C + (tid - C)] = s;
-    }
-
-    // last merged step: the tail
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned t = __hip_atomic_fetch_add(&a.tickets[kNMax], 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == (unsigned)N - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    const bool run_tail = s_last != 0u;
-    __syncthreads();
-    if (!run_tail) return;
-    __threadfence();
-
-    const Acc den = stage[(size_t)N * C], den2 = stage[(size_t)N * C + 1];
-    const bool ok = isfinite((double)jmin) && den > Acc(0);
+    const Acc den = s_den[0], den2 = s_den[1];
+    const bool ok = isfinite(jmin) && den > Acc(0);
     DevWarm *w = a.warm;
-    const DevCur *cur = a.cur;
     if (ok) {
-        for (int idx = tid; idx < N * C; idx += 256) {
-            const int kk = idx / C, ch = idx % C;
-            const double u = (double)(stage[idx] / den);
-            if (ch < 4) a.wU[4 * kk + ch] = u;
-            else a.wV[kk] = u;
+        for (int idx = tid; idx < N * C; idx += blockDim.x) {
+            const int k = idx / C, ch = idx % C;
+            const double u = (double)(s_u[idx] / den);
+            if (ch < 4) a.wU[4 * k + ch] = u;
+            else a.wV[k] = u;
         }
         if (!HAS_V)
-            for (int kk = tid; kk < N; kk += 256) a.wV[kk] = 0.0;
+            for (int k = tid; k < N; k += blockDim.x) a.wV[k] = 0.0;
     }
     if (tid < kMaskWords && ok) {
         uint32_t word = 0u;
@@ -982,14 +977,15 @@ __device__ __forceinline__ void average_body(const KArgs &a, int mt, int k)
         }
         w->allow[tid] = word;
     }
+    __syncthreads();
     if (tid == 0) {
         DevResult *r = a.res;
         for (int i = 0; i < 4; ++i) {
-            const double u0 = ok ? (double)(stage[i] / den) : (double)NAN;
+            const double u0 = ok ? (double)(s_u[i] / den) : (double)NAN;
             r->u0[i] = u0;
             if (a.u0_out) a.u0_out[i] = u0;
         }
-        r->J_min = (double)jmin;
+        r->J_min = jmin;
         r->S = (double)den;
         r->S2 = (double)den2;
         r->ess = ok ? (double)den * (double)den / (double)den2 : 0.0;
@@ -1016,6 +1012,11 @@ template <typename Real, typename Acc, bool HAS_V>
 __global__ __launch_bounds__(256) void k_average(KArgs a)
 {
     average_body<Real, Acc, HAS_V>(a, blockIdx.x, blockIdx.y);
+}
+
+template <typename Acc, bool HAS_V> __global__ __launch_bounds__(256) void k_tail(KArgs a)
+{
+    tail_body<Acc, HAS_V>(a);
 }
 
 // ---------------------------------------------------------------- batched (persistent)
@@ -1100,6 +1101,19 @@ template <int OBJ, typename Real, int WAVES> __global__ __launch_bounds__(64 * W
     }
 }
 
+template <typename Acc, bool HAS_V> __global__ __launch_bounds__(256) void kb_tail(BArgs b)
+{
+    __shared__ KArgs s_a;
+    __shared__ int s_ctx;
+    if (threadIdx.x == 0) s_ctx = -1;
+    const int n = b.desc->n;
+    for (int item = blockIdx.x; item < n; item += gridDim.x) {
+        stage_args(s_a, s_ctx, b, item);
+        tail_body<Acc, HAS_V>(s_a);
+        __syncthreads();
+    }
+}
+
 template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(256) void kb_average(BArgs b)
 {
     __shared__ KArgs s_a;
@@ -1124,10 +1138,13 @@ static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(128), 0, st, b);
     else
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 1>), dim3(L.rollout_groups), dim3(64), 0, st, b);
-    if (L.acc64 || sizeof(Real) == 8)
+    if (L.acc64 || sizeof(Real) == 8) {
         hipLaunchKernelGGL((kb_average<Real, double, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
-    else
+        hipLaunchKernelGGL((kb_tail<double, HAS_V>), dim3(L.tail_groups), dim3(256), 0, st, b);
+    } else {
         hipLaunchKernelGGL((kb_average<Real, float, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((kb_tail<float, HAS_V>), dim3(L.tail_groups), dim3(256), 0, st, b);
+    }
     return hipGetLastError();
 }
 
@@ -1167,6 +1184,7 @@ template <typename Real, typename Acc, bool HAS_V>
 static hipError_t launch_average_t(const KArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL((k_average<Real, Acc, HAS_V>), dim3(a.n_mt, a.N), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_tail<Acc, HAS_V>), dim3(1), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ struct BatchLaunch {
     int rollout_waves;    // 1 or 2
     int rollout_groups;   // persistent rollout workgroups
     int sample_groups;    // grid-stride workgroups of the sample and average kernels
+    int tail_groups;      // workgroups of the merge-and-tail kernel (one item each)
 };
 
 // Enqueue one batched MPPI step over the items described in device memory.

@@ -45,9 +45,21 @@ template <typename Real> __device__ __forceinline__ Real unit_open(uint32_t w)
 
 template <typename Real> struct Normal4 { Real z0, z1, z2, z3; };
 
-__device__ __forceinline__ void sincos_2pi(float u, float *s, float *c) { sincospif(2.0f * u, s, c); }
+// binary32: the hardware transcendentals -- v_sin_f32 / v_cos_f32 take their
+// argument in revolutions, v_log_f32 is log2 -- each within a few ulps on
+// (0, 1), which bounds the error of a normal by about 1e-6.
+__device__ __forceinline__ void sincos_2pi(float u, float *s, float *c)
+{
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
+}
+__device__ __forceinline__ float radius(float u)
+{
+    // sqrt(-2 ln u) = sqrt(-2 ln(2) log2(u))
+    return __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));
+}
+// binary64: the accurate library functions
 __device__ __forceinline__ void sincos_2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
-__device__ __forceinline__ float radius(float u) { return sqrtf(-2.0f * logf(u)); }
 __device__ __forceinline__ double radius(double u) { return sqrt(-2.0 * log(u)); }
 
 template <typename Real>

@@ -123,7 +123,7 @@ template <typename Real> __device__ __forceinline__ void commit(State<Real> &s, 
         s.x[i] = t;
     }
     const Real n2 = s.x[6] * s.x[6] + s.x[7] * s.x[7] + s.x[8] * s.x[8] + s.x[9] * s.x[9];
-    const Real r = Real(1) / sqrtf(n2);
+    const Real r = inv_sqrt(n2);
 #pragma unroll
     for (int i = 6; i < 10; ++i) {
         const Real ph = s.x[i] * r;

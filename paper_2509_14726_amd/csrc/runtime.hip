@@ -683,6 +683,7 @@ static void resolve_cfg(mppi_batch *b)
         g.launch.rollout_waves = waves;
         g.launch.rollout_groups = rg;
         g.launch.sample_groups = sg;
+        g.launch.tail_groups = g.cap < 1 ? 1 : (g.cap > 4 * b->n_cu ? 4 * b->n_cu : g.cap);
     }
 }
 

@@ -105,34 +105,12 @@ def path_table(gates: np.ndarray, n_points: int = 2000, dense: int = 200000):
     return np.hstack([pos, tan]), L
 
 
-def _quat_from_matrix(R: np.ndarray) -> np.ndarray:
-    tr = R[0, 0] + R[1, 1] + R[2, 2]
-    if tr > 0:
-        s = 2.0 * math.sqrt(tr + 1.0)
-        q = np.array([0.25 * s, (R[2, 1] - R[1, 2]) / s, (R[0, 2] - R[2, 0]) / s,
-                      (R[1, 0] - R[0, 1]) / s])
-    elif R[0, 0] > R[1, 1] and R[0, 0] > R[2, 2]:
-        s = 2.0 * math.sqrt(1.0 + R[0, 0] - R[1, 1] - R[2, 2])
-        q = np.array([(R[2, 1] - R[1, 2]) / s, 0.25 * s, (R[0, 1] + R[1, 0]) / s,
-                      (R[0, 2] + R[2, 0]) / s])
-    elif R[1, 1] > R[2, 2]:
-        s = 2.0 * math.sqrt(1.0 + R[1, 1] - R[0, 0] - R[2, 2])
-        q = np.array([(R[0, 2] - R[2, 0]) / s, (R[0, 1] + R[1, 0]) / s, 0.25 * s,
-                      (R[1, 2] + R[2, 1]) / s])
-    else:
-        s = 2.0 * math.sqrt(1.0 + R[2, 2] - R[0, 0] - R[1, 1])
-        q = np.array([(R[1, 0] - R[0, 1]) / s, (R[0, 2] + R[2, 0]) / s,
-                      (R[1, 2] + R[2, 1]) / s, 0.25 * s])
-    if q[0] < 0:
-        q = -q
-    return q / np.linalg.norm(q)
-
-
 def reference_table(gates: np.ndarray, speed: float = 5.0, dt: float = 0.02, n_rows: int = 1101,
                     gravity: float = 9.81) -> np.ndarray:
     """Full-state reference sampled every dt along the spline at constant
     speed: p = path(speed t), v = speed * tangent, attitude from the thrust
     direction a + g e_z with yaw along the tangent, zero body rates."""
+    from scipy.spatial.transform import Rotation
     sp, umax = _periodic_spline(gates[:, :3])
     dense = 200000
     uu = np.linspace(0.0, umax, dense + 1)
@@ -140,29 +118,30 @@ def reference_table(gates: np.ndarray, speed: float = 5.0, dt: float = 0.02, n_r
     sp_len = np.linalg.norm(d1, axis=1)
     s = np.concatenate([[0.0], np.cumsum(0.5 * (sp_len[1:] + sp_len[:-1]) * np.diff(uu))])
     L = s[-1]
+    sr = (speed * np.arange(n_rows) * dt) % L
+    u = np.interp(sr, s, uu)
+    p = sp(u)
+    du = sp(u, 1)
+    ddu = sp(u, 2)
+    nd = np.linalg.norm(du, axis=1, keepdims=True)
+    t = du / nd
+    # d^2 p / ds^2 = (ddu - (t . ddu) t) / |du|^2
+    kappa = (ddu - np.sum(t * ddu, axis=1, keepdims=True) * t) / (nd * nd)
+    zb = speed * speed * kappa + np.array([0.0, 0.0, gravity])
+    zb /= np.linalg.norm(zb, axis=1, keepdims=True)
+    yaw = np.arctan2(t[:, 1], t[:, 0])
+    xc = np.column_stack([np.cos(yaw), np.sin(yaw), np.zeros(n_rows)])
+    yb = np.cross(zb, xc)
+    yb /= np.linalg.norm(yb, axis=1, keepdims=True)
+    xb = np.cross(yb, zb)
+    R = np.stack([xb, yb, zb], axis=2)            # columns are the body axes
+    qxyzw = Rotation.from_matrix(R).as_quat()      # (x, y, z, w)
+    q = np.column_stack([qxyzw[:, 3], qxyzw[:, 0], qxyzw[:, 1], qxyzw[:, 2]])
+    q *= np.where(q[:, :1] < 0.0, -1.0, 1.0)
     out = np.zeros((n_rows, 13))
-    for r in range(n_rows):
-        sr = (speed * r * dt) % L
-        u = float(np.interp(sr, s, uu))
-        p = sp(u)
-        du = sp(u, 1)
-        ddu = sp(u, 2)
-        nd = np.linalg.norm(du)
-        t = du / nd
-        # d^2 p / ds^2 = (ddu - (t . ddu) t) / |du|^2
-        kappa = (ddu - np.dot(t, ddu) * t) / (nd * nd)
-        a = speed * speed * kappa
-        zb = a + np.array([0.0, 0.0, gravity])
-        zb /= np.linalg.norm(zb)
-        yaw = math.atan2(t[1], t[0])
-        xc = np.array([math.cos(yaw), math.sin(yaw), 0.0])
-        yb = np.cross(zb, xc)
-        yb /= np.linalg.norm(yb)
-        xb = np.cross(yb, zb)
-        R = np.column_stack([xb, yb, zb])
-        out[r, 0:3] = p
-        out[r, 3:6] = speed * t
-        out[r, 6:10] = _quat_from_matrix(R)
+    out[:, 0:3] = p
+    out[:, 3:6] = speed * t
+    out[:, 6:10] = q
     return out
 
 
@@ -172,14 +151,16 @@ def reference_table(gates: np.ndarray, speed: float = 5.0, dt: float = 0.02, n_r
 def single_solve_workload(K: int = 1024, N: int = 50, seed: int = 1, track_seed: int = 1,
                           n_gates: int = 7, objective: str = "gate", dt: float = 0.02,
                           **over) -> dict:
-    """A single MPPI solve on a seeded track; all three objectives share the
-    track, the path table (2000 points) and the 5 m/s reference."""
+    """A single MPPI solve on a seeded track.  Contouring gets the 2000-point
+    arc-length table of the spline through the gate centres, tracking the 5 m/s
+    full-state reference on the same spline."""
     gates = random_track(track_seed, n_gates)
     prm = params(K, N, objective, seed, dt=dt, **over)
     w = dict(quad=dict(QUAD), params=prm, gates=gates, x0=start_state(gates))
-    if objective in ("contour", "track"):
+    if objective == "contour":
         path, L = path_table(gates)
         w.update(path=path, path_len=L)
+    if objective == "track":
         w.update(xref=reference_table(gates, dt=dt, n_rows=1000 + N + 1), ref_dt=dt)
     return w
 

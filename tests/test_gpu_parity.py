@@ -170,3 +170,22 @@ def test_rollout_layouts_agree(precision, monkeypatch):
     eps = 1e-13 if precision == M.FP64 else 1e-5
     np.testing.assert_allclose(out[0][0], out[1][0], rtol=eps, atol=eps)
     np.testing.assert_allclose(out[0][1], out[1][1], rtol=0, atol=1e-3 if precision == M.FP32 else 1e-12)
+
+
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+def test_sample_tensor_matches_oracle_samples(precision):
+    """The stored clipped samples U^m_k (Eq. (3)) against the oracle's, on the
+    same Philox words: binary64 to 1e-12 N, binary32 (hardware
+    transcendentals) to 2e-5 N at sigma = 1 N."""
+    say("sample tensor", precision)
+    w = _workload(700, 13, seed=21)
+    dev, orc = build_pair(w, precision)
+    dev.solve(w["x0"], 0.0)
+    _, Us = dev.read_samples(want_U=True)          # N x K x 4
+    hover = synth.hover_thrust()
+    N, K = 13, 700
+    ref = np.array([orc.sample(np.full(4 * N, hover), np.zeros(N), m, 0)[0] for m in range(K)])
+    err = np.abs(Us.transpose(1, 0, 2) - ref).max()
+    say("  max |dU|", err)
+    assert err <= (1e-12 if precision == M.FP64 else 2e-5)
+    dev.close()
