@@ -224,8 +224,10 @@ mppi_status mppi_read_profile(mppi_ctx *ctx, double mean_ms[3], int32_t *n_solve
 typedef struct mppi_batch mppi_batch;
 
 typedef struct {
-    int32_t rollout_waves;     /* 1 or 2 waves per 64-sample tile; 0: 2 when the
-                                  batch has fewer tiles than SIMDs, else 1       */
+    int32_t rollout_waves;     /* waves per 64-sample tile: 1 (separate sampling
+                                  kernel), 2 (attitude / translation split) or 3
+                                  (sampling joins the rollout); 0: 3 when the
+                                  batch has fewer tiles than four per CU, else 1 */
     int32_t rollout_groups;    /* persistent rollout workgroups; 0: automatic    */
     int32_t sample_groups;     /* workgroups of the sample and reduction kernels;
                                   0: automatic                                   */

@@ -79,17 +79,26 @@ __device__ double wrap_len_d(double th, double L)
     return r;
 }
 
-// Decides, once per solve, everything inherited from the previous solve:
-// warm-start shift, current gate and pass mask, start arc length, reference
-// row, last applied input.  Run by all threads of one block.
-__device__ void solve_head(const KArgs &a)
+// What one solve inherits from the previous one, decided from the request and
+// the warm-start state: warm-start shift, current gate and pass mask, start
+// arc length, reference row, last applied input.
+struct HeadVals {
+    int32_t g0, i0, shift, warm;
+    uint32_t s;
+    uint32_t allow[kMaskWords];
+    double theta0, t_now, v_prev;
+    double u_prev[4];
+    double x0[13];
+};
+
+// Run by all threads of one block (any size up to 256); h is in LDS.
+__device__ void compute_head(const KArgs &a, HeadVals &h)
 {
     __shared__ double s_d2[256];
     __shared__ double s_th[256];
     __shared__ int s_j[256];
     const int tid = threadIdx.x;
     const DevWarm *w = a.warm;
-    DevCur *c = a.cur;
     const int warm = w->warm;
 
     double theta0 = 0.0;
@@ -122,8 +131,9 @@ __device__ void solve_head(const KArgs &a)
         }
         s_d2[tid] = best; s_th[tid] = best_th; s_j[tid] = best_j;
         __syncthreads();
-        for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-            if (tid < st) {
+        // smallest distance, ties to the first candidate in search order
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st && tid + st < (int)blockDim.x) {
                 const double d_o = s_d2[tid + st];
                 const int j_o = s_j[tid + st];
                 if (d_o < s_d2[tid] || (d_o == s_d2[tid] && j_o < s_j[tid])) {
@@ -152,21 +162,49 @@ __device__ void solve_head(const KArgs &a)
             if (r > (double)(a.R - 1)) r = (double)(a.R - 1);
             i0 = (int)r;
         }
-        c->g0 = g0;
-        c->i0 = i0;
-        c->shift = solve_shift(warm, t_now, w->t_prev, a.dt);
-        c->warm = warm;
-        c->s = w->s;
+        h.g0 = g0;
+        h.i0 = i0;
+        h.shift = solve_shift(warm, t_now, w->t_prev, a.dt);
+        h.warm = warm;
+        h.s = w->s;
+        for (int j = 0; j < kMaskWords; ++j) h.allow[j] = allow[j];
+        h.theta0 = theta0;
+        h.t_now = t_now;
+        for (int i = 0; i < 4; ++i) h.u_prev[i] = warm ? a.wU[i] : a.hover;
+        h.v_prev = warm ? a.wV[0] : 0.0;
+        for (int i = 0; i < 13; ++i) h.x0[i] = a.req[i];
+    }
+    __syncthreads();
+}
+
+// Publish the head for the kernels that follow (thread 0 of one block).
+__device__ void publish_head(const KArgs &a, const HeadVals &h)
+{
+    DevCur *c = a.cur;
+    c->g0 = h.g0;
+    c->i0 = h.i0;
+    c->shift = h.shift;
+    c->warm = h.warm;
+    c->s = h.s;
+    for (int j = 0; j < kMaskWords; ++j) c->allow[j] = h.allow[j];
+    c->theta0 = h.theta0;
+    c->t_now = h.t_now;
+    for (int i = 0; i < 4; ++i) c->u_prev[i] = h.u_prev[i];
+    c->v_prev = h.v_prev;
+    for (int i = 0; i < 13; ++i) c->x0[i] = h.x0[i];
+}
+
+__device__ void solve_head(const KArgs &a)
+{
+    __shared__ HeadVals h;
+    compute_head(a, h);
+    if (threadIdx.x == 0) {
+        publish_head(a, h);
+        DevCur *c = a.cur;
         c->ticket = 0u;
         c->jmin32 = ordered_bits(INFINITY);
         c->jmin64 = ordered_bits((double)INFINITY);
-        for (int j = 0; j < kMaskWords; ++j) c->allow[j] = allow[j];
-        c->theta0 = theta0;
-        c->t_now = t_now;
-        for (int i = 0; i < 4; ++i) c->u_prev[i] = warm ? a.wU[i] : a.hover;
-        c->v_prev = warm ? a.wV[0] : 0.0;
         c->J_nom = 0.0;
-        for (int i = 0; i < 13; ++i) c->x0[i] = a.req[i];
     }
 }
 
@@ -860,6 +898,456 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(128) void k_rollo
     rollout2_body<OBJ, Real>(a, blockIdx.x);
 }
 
+// ---------------------------------------------------------------- rollout, three waves
+
+// Sampling joins the rollout: per 64-sample tile, wave 0 draws the noise and
+// the clipped controls of every step (Eq. (3)), stores them in the sample
+// tensor for the weighted average and hands the step's collective thrust over
+// mass and torques over inertia to the other waves through an LDS ring;
+// wave 1 integrates (q, omega) and hands on the RK4 stage quaternions; wave 2
+// integrates (p, v) and evaluates the position costs.  Each wave accumulates
+// the cost terms of what it computes (wave 0: control-rate and progress-speed
+// terms; wave 1: attitude and body-rate terms; wave 2: position terms); the
+// three partial costs are added at the end.  Every workgroup derives the
+// per-solve head itself; workgroup 0 publishes it for the tail.
+template <typename Real> struct Ring3;
+template <> struct Ring3<float> { static constexpr int B = 8; };
+template <> struct Ring3<double> { static constexpr int B = 4; };
+
+template <int OBJ, typename Real>
+__device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const HeadVals &h)
+{
+    typedef typename Vec4<Real>::T R4;
+    constexpr int B = Ring3<Real>::B;
+    constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
+    __shared__ R4 s_in[3][B][64];                  // (F/m, tau_x/J_x, tau_y/J_y, tau_z/J_z)
+    __shared__ Real s_v[HAS_V ? 3 : 1][B][64];     // progress speed
+    __shared__ R4 s_q[2][B][4][64];                // stage quaternions
+    __shared__ Real s_jp[2][64];                   // partial costs of waves 0 and 1
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = blk * 64 + lane;
+    const int K = a.K, N = a.N;
+    const bool active = m <= K;
+    const bool nominal = m == K;
+    const bool sampled = m < K;
+    const Model<Real> M(a);
+    const Real dt = (Real)a.dt;
+    const Real h2 = Real(0.5) * dt;
+    const Real dt6 = dt / Real(6);
+    const Real w_max = (Real)a.w_max, w_lim = (Real)a.w_lim;
+    const Real *xref = (const Real *)a.xref_r;
+    const int i0 = h.i0;
+    Real rdt[4];
+    for (int i = 0; i < 4; ++i) rdt[i] = (Real)(a.R_dT[i] / (a.dt * a.dt));
+    const Real r_dv = (Real)(a.r_dv / (a.dt * a.dt));
+
+    KSum<Real> J;
+    // wave 0: sampling
+    Real up[4], vp = (Real)h.v_prev;
+    for (int i = 0; i < 4; ++i) up[i] = (Real)h.u_prev[i];
+    // wave 1: attitude and body rates; wave 2: position and velocity
+    Real q[4], ql[4], w[3], wl[3], p[3], pl[3], v[3], vl[3];
+    for (int i = 0; i < 4; ++i) {
+        q[i] = (Real)h.x0[6 + i];
+        ql[i] = sizeof(Real) == 4 ? (Real)(h.x0[6 + i] - (double)q[i]) : Real(0);
+    }
+    for (int i = 0; i < 3; ++i) {
+        w[i] = (Real)h.x0[10 + i];
+        wl[i] = sizeof(Real) == 4 ? (Real)(h.x0[10 + i] - (double)w[i]) : Real(0);
+        p[i] = (Real)h.x0[i];
+        pl[i] = sizeof(Real) == 4 ? (Real)(h.x0[i] - (double)p[i]) : Real(0);
+        v[i] = (Real)h.x0[3 + i];
+        vl[i] = sizeof(Real) == 4 ? (Real)(h.x0[3 + i] - (double)v[i]) : Real(0);
+    }
+    GateRegs<Real> gt, g0r;
+    int g = 0, passes = 0;
+    const Real *gtab = (const Real *)a.gates_r;
+    const Real *path = (const Real *)a.path_r;
+    Real th_hi = 0, th_lo = 0, ds = 0, inv_ds = 0, L = 0;
+    if (OBJ == OBJ_GATE) {
+        g = h.g0;
+        gt.load(gtab, g);
+        g0r = gt;
+    }
+    if (OBJ == OBJ_CONTOUR) {
+        th_hi = (Real)h.theta0;
+        if (sizeof(Real) == 4) th_lo = (Real)(h.theta0 - (double)th_hi);
+        L = (Real)a.path_len;
+        ds = (Real)(a.path_len / (double)a.P);
+        inv_ds = (Real)((double)a.P / a.path_len);
+    }
+    const Real q_near = (Real)a.q_near, r_near2 = (Real)(a.r_near * a.r_near), half = (Real)a.gate_half;
+    const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max, vmax = (Real)a.v_max;
+    const Real sig0 = (Real)a.sigma[0], sig1 = (Real)a.sigma[1], sig2 = (Real)a.sigma[2], sig3 = (Real)a.sigma[3];
+    const Real sigv = (Real)a.sigma_v, hover = (Real)a.hover;
+    typedef typename Vec4<Real>::T R4g;
+    R4g *ctrl = (R4g *)a.ctrl;
+    Real *vctrl = (Real *)a.vctrl;
+
+    const int nch = (N + B - 1) / B;
+    for (int c = 0; c <= nch + 1; ++c) {
+        if (wave == 0 && c < nch) {
+            const int kb = c * B, ke = min(N, kb + B);
+            for (int k = kb; k < ke; ++k) {
+                const int j = k - kb;
+                int src = k + h.shift;
+                if (src > N - 1) src = N - 1;
+                Real us[4];
+                for (int i = 0; i < 4; ++i) us[i] = h.warm ? (Real)a.wU[4 * src + i] : hover;
+                const Real vs = h.warm ? (Real)a.wV[src] : Real(0);
+                R4 u;
+                Real V = Real(0);
+                if (sampled) {
+                    const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, h.s, 0u, a.seed_lo, a.seed_hi);
+                    u.x = clampT(us[0] + sig0 * z.z0, tmin, tmax);
+                    u.y = clampT(us[1] + sig1 * z.z1, tmin, tmax);
+                    u.z = clampT(us[2] + sig2 * z.z2, tmin, tmax);
+                    u.w = clampT(us[3] + sig3 * z.z3, tmin, tmax);
+                    const size_t idx = (size_t)k * (size_t)K + (size_t)m;
+                    ctrl[idx] = u;
+                    if (HAS_V) {
+                        const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, h.s, 1u, a.seed_lo, a.seed_hi);
+                        V = clampT(vs + sigv * zv, Real(0), vmax);
+                        vctrl[idx] = V;
+                    }
+                } else {  // the noise-free nominal (and idle lanes past it)
+                    u.x = clampT(us[0], tmin, tmax);
+                    u.y = clampT(us[1], tmin, tmax);
+                    u.z = clampT(us[2], tmin, tmax);
+                    u.w = clampT(us[3], tmin, tmax);
+                    if (HAS_V) V = clampT(vs, Real(0), vmax);
+                }
+                Real term = Real(0);
+                if (OBJ != OBJ_GATE) {
+                    const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
+                    term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                }
+                if (HAS_V) {
+                    const Real dv = V - vp;
+                    term += r_dv * dv * dv;
+                    term -= (Real)a.mu * V;
+                    vp = V;
+                    s_v[c % 3][j][lane] = V;
+                }
+                if (OBJ != OBJ_GATE) J.add(term);
+                up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
+                const StepInput<Real> in = step_input(M, u.x, u.y, u.z, u.w);
+                R4 o;
+                o.x = in.fm; o.y = in.tx; o.z = in.ty; o.w = in.tz;
+                s_in[c % 3][j][lane] = o;
+            }
+        } else if (wave == 1 && c >= 1 && c <= nch) {
+            const int kb = (c - 1) * B, ke = min(N, kb + B);
+            for (int k = kb; k < ke; ++k) {
+                const int j = k - kb;
+                const R4 in = s_in[(c - 1) % 3][j][lane];
+                R4 (*slot)[64] = s_q[(c - 1) & 1][j];
+                Real term = Real(0);
+                if (OBJ == OBJ_TRACK) {
+                    int r = i0 + k;
+                    if (r > a.R - 1) r = a.R - 1;
+                    const Real *xr = xref + 16 * r;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real e = (q[i] - xr[6 + i]) + ql[i];
+                        term += (Real)a.Q[6 + i] * e * e;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (w[i] - xr[10 + i]) + wl[i];
+                        term += (Real)a.Q[10 + i] * e * e;
+                    }
+                }
+                if (OBJ == OBJ_CONTOUR)
+                    term += (Real)a.Q_w[0] * w[0] * w[0] + (Real)a.Q_w[1] * w[1] * w[1] +
+                            (Real)a.Q_w[2] * w[2] * w[2];
+                Real ws[3], qs[4], kw[3], kq[4], dw[3], dq[4];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) ws[i] = w[i];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) qs[i] = q[i];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    R4 o;
+                    o.x = qs[0]; o.y = qs[1]; o.z = qs[2]; o.w = qs[3];
+                    slot[st][lane] = o;
+                    kw[0] = in.y - M.gx * ws[1] * ws[2];
+                    kw[1] = in.z - M.gy * ws[2] * ws[0];
+                    kw[2] = in.w - M.gz * ws[0] * ws[1];
+                    kq[0] = Real(0.5) * (-qs[1] * ws[0] - qs[2] * ws[1] - qs[3] * ws[2]);
+                    kq[1] = Real(0.5) * (qs[0] * ws[0] + qs[2] * ws[2] - qs[3] * ws[1]);
+                    kq[2] = Real(0.5) * (qs[0] * ws[1] - qs[1] * ws[2] + qs[3] * ws[0]);
+                    kq[3] = Real(0.5) * (qs[0] * ws[2] + qs[1] * ws[1] - qs[2] * ws[0]);
+                    if (st == 0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] = kw[i];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] = kq[i];
+                    } else if (st < 3) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] += Real(2) * kw[i];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] += Real(2) * kq[i];
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] = dt6 * (dw[i] + kw[i]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] = dt6 * (dq[i] + kq[i]);
+                    }
+                    if (st < 3) {
+                        const Real hh = st < 2 ? h2 : dt;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) ws[i] = w[i] + hh * kw[i];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) qs[i] = q[i] + hh * kq[i];
+                    }
+                }
+                if (sizeof(Real) == 4) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real y = dw[i] + wl[i];
+                        const Real t = w[i] + y;
+                        wl[i] = y - (t - w[i]);
+                        w[i] = t;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real y = dq[i] + ql[i];
+                        const Real t = q[i] + y;
+                        ql[i] = y - (t - q[i]);
+                        q[i] = t;
+                    }
+                    const Real n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+                    const Real r = inv_sqrt(n2);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real ph = q[i] * r;
+                        const Real pl2 = fma(q[i], r, -ph) + ql[i] * r;
+                        const Real hs = ph + pl2;
+                        ql[i] = pl2 - (hs - ph);
+                        q[i] = hs;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) w[i] += dw[i];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) q[i] += dq[i];
+                    const Real nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) q[i] /= nq;
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const Real e = fmax(fabs(w[i]) - w_max, Real(0));
+                    term += w_lim * e * e;
+                }
+                J.add(term);
+            }
+        } else if (wave == 2 && c >= 2) {
+            const int kb = (c - 2) * B, ke = min(N, kb + B);
+            for (int k = kb; k < ke; ++k) {
+                const int j = k - kb;
+                const R4 in = s_in[(c - 2) % 3][j][lane];
+                R4 qstage[4];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) qstage[st] = s_q[(c - 2) & 1][j][st][lane];
+                const Real fm = in.x;
+                Real term = Real(0);
+                Real ax = 0, ay = 0, az = 0;
+                if (OBJ == OBJ_GATE) {
+                    ax = (p[0] - gt.cx) + pl[0];
+                    ay = (p[1] - gt.cy) + pl[1];
+                    az = (p[2] - gt.cz) + pl[2];
+                    const Real bx = (p[0] - g0r.cx) + pl[0];
+                    const Real by = (p[1] - g0r.cy) + pl[1];
+                    const Real bz = (p[2] - g0r.cz) + pl[2];
+                    const Real d2 = bx * bx + by * by + bz * bz;
+                    if (d2 < r_near2) term += q_near * d2;
+                    if (nominal) a.front8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+                } else if (OBJ == OBJ_TRACK) {
+                    int r = i0 + k;
+                    if (r > a.R - 1) r = a.R - 1;
+                    const Real *xr = xref + 16 * r;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (p[i] - xr[i]) + pl[i];
+                        term += (Real)a.Q[i] * e * e;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (v[i] - xr[3 + i]) + vl[i];
+                        term += (Real)a.Q[3 + i] * e * e;
+                    }
+                } else {
+                    const Real vk = s_v[(c - 2) % 3][j][lane];
+                    const Real fl = floor(th_hi * inv_ds);
+                    const Real f = ((th_hi - fl * ds) + th_lo) * inv_ds;
+                    const int i = (fl >= Real(0) && fl < Real(1 << 30)) ? ((int)fl % a.P) : 0;
+                    const int i1 = (i + 1 == a.P) ? 0 : i + 1;
+                    const Real *A = path + 8 * i, *Bp = path + 8 * i1;
+                    const Real g1 = Real(1) - f;
+                    const Real px = g1 * A[0] + f * Bp[0], py = g1 * A[1] + f * Bp[1], pz = g1 * A[2] + f * Bp[2];
+                    Real tx = g1 * A[3] + f * Bp[3], ty = g1 * A[4] + f * Bp[4], tz = g1 * A[5] + f * Bp[5];
+                    const Real tn = inv_sqrt(tx * tx + ty * ty + tz * tz);
+                    tx *= tn; ty *= tn; tz *= tn;
+                    const Real ex = (p[0] - px) + pl[0];
+                    const Real ey = (p[1] - py) + pl[1];
+                    const Real ez = (p[2] - pz) + pl[2];
+                    const Real et = ex * tx + ey * ty + ez * tz;
+                    const Real lx = et * tx, ly = et * ty, lz = et * tz;
+                    const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
+                    term += (Real)a.q_l * (lx * lx + ly * ly + lz * lz);
+                    term += (Real)a.q_c * (cxe * cxe + cye * cye + cze * cze);
+                    const Real y = vk * dt + th_lo;
+                    const Real t = th_hi + y;
+                    th_lo = (sizeof(Real) == 4) ? y - (t - th_hi) : Real(0);
+                    th_hi = t;
+                    if (th_hi >= L) th_hi -= L;
+                }
+                Real vs[3], kv[3], dpv[3], dvv[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) vs[i] = v[i];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const R4 qq = qstage[st];
+                    const Real r3x = Real(2) * (qq.y * qq.w + qq.x * qq.z);
+                    const Real r3y = Real(2) * (qq.z * qq.w - qq.x * qq.y);
+                    const Real r3z = Real(1) - Real(2) * (qq.y * qq.y + qq.z * qq.z);
+                    kv[0] = fm * r3x;
+                    kv[1] = fm * r3y;
+                    kv[2] = fm * r3z - M.g;
+                    if (M.drag) {
+                        const Real qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
+                        const Real r11 = Real(1) - Real(2) * (qy * qy + qz * qz), r12 = Real(2) * (qx * qy - qw * qz);
+                        const Real r21 = Real(2) * (qx * qy + qw * qz), r22 = Real(1) - Real(2) * (qx * qx + qz * qz);
+                        const Real r31 = Real(2) * (qx * qz - qw * qy), r32 = Real(2) * (qy * qz + qw * qx);
+                        const Real b0 = M.d0 * (r11 * vs[0] + r21 * vs[1] + r31 * vs[2]);
+                        const Real b1 = M.d1 * (r12 * vs[0] + r22 * vs[1] + r32 * vs[2]);
+                        const Real b2 = M.d2 * (r3x * vs[0] + r3y * vs[1] + r3z * vs[2]);
+                        kv[0] -= r11 * b0 + r12 * b1 + r3x * b2;
+                        kv[1] -= r21 * b0 + r22 * b1 + r3y * b2;
+                        kv[2] -= r31 * b0 + r32 * b1 + r3z * b2;
+                    }
+                    if (st == 0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] = vs[i]; dvv[i] = kv[i]; }
+                    } else if (st < 3) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] += Real(2) * vs[i]; dvv[i] += Real(2) * kv[i]; }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] = dt6 * (dpv[i] + vs[i]); dvv[i] = dt6 * (dvv[i] + kv[i]); }
+                    }
+                    if (st < 3) {
+                        const Real hh = st < 2 ? h2 : dt;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) vs[i] = v[i] + hh * kv[i];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (sizeof(Real) == 4) {
+                        Real y = dpv[i] + pl[i];
+                        Real t = p[i] + y;
+                        pl[i] = y - (t - p[i]);
+                        p[i] = t;
+                        y = dvv[i] + vl[i];
+                        t = v[i] + y;
+                        vl[i] = y - (t - v[i]);
+                        v[i] = t;
+                    } else {
+                        p[i] += dpv[i];
+                        v[i] += dvv[i];
+                    }
+                }
+                if (OBJ == OBJ_GATE) {
+                    term += dpv[0] * (Real(2) * ax + dpv[0]) + dpv[1] * (Real(2) * ay + dpv[1]) +
+                            dpv[2] * (Real(2) * az + dpv[2]);
+                    const Real sa = ax * gt.nx + ay * gt.ny;
+                    const Real sb = (ax + dpv[0]) * gt.nx + (ay + dpv[1]) * gt.ny;
+                    if (sa < Real(0) && sb >= Real(0)) {
+                        const Real t = sa / (sa - sb);
+                        const Real yx = ax + t * dpv[0], yy = ay + t * dpv[1], yz = az + t * dpv[2];
+                        const Real lat = yx * gt.hx + yy * gt.hy;
+                        const bool inside = fabs(lat) <= half && fabs(yz) <= half;
+                        const int jj = k + 1;
+                        const bool allowed = passes > 0 || ((h.allow[jj >> 5] >> (jj & 31)) & 1u);
+                        if (inside && allowed) {
+                            g = (g + 1 == a.G) ? 0 : g + 1;
+                            ++passes;
+                            gt.load(gtab, g);
+                        }
+                    }
+                }
+                J.add(term);
+            }
+        }
+        __syncthreads();
+    }
+
+    if (OBJ == OBJ_TRACK && wave > 0) {
+        int r = i0 + N;
+        if (r > a.R - 1) r = a.R - 1;
+        const Real *xr = xref + 16 * r;
+        Real term = 0;
+        if (wave == 1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const Real e = (q[i] - xr[6 + i]) + ql[i];
+                term += (Real)a.QN[6 + i] * e * e;
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const Real e = (w[i] - xr[10 + i]) + wl[i];
+                term += (Real)a.QN[10 + i] * e * e;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const Real e = (p[i] - xr[i]) + pl[i];
+                term += (Real)a.QN[i] * e * e;
+                const Real f = (v[i] - xr[3 + i]) + vl[i];
+                term += (Real)a.QN[3 + i] * f * f;
+            }
+        }
+        J.add(term);
+    }
+    if (wave < 2) s_jp[wave][lane] = J.value();
+    __syncthreads();
+    if (wave == 2) {
+        Real Jfinal = Real(0);
+        if (active) {
+            Jfinal = (s_jp[0][lane] + s_jp[1][lane]) + J.value();
+            if (OBJ == OBJ_GATE && nominal) {
+                const Real bx = (p[0] - g0r.cx) + pl[0];
+                const Real by = (p[1] - g0r.cy) + pl[1];
+                a.front8[N] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+            }
+            if (nominal) a.cur->J_nom = (double)Jfinal;
+            else ((Real *)a.J)[m] = Jfinal;
+        }
+        const bool use = active && !nominal && isfinite(Jfinal);
+        if (sizeof(Real) == 4) {
+            const uint32_t vb = use ? ordered_bits((float)Jfinal) : ordered_bits(INFINITY);
+            wave_min_atomic(vb, &a.cur->jmin32);
+        } else {
+            const unsigned long long vb = use ? ordered_bits((double)Jfinal) : ordered_bits((double)INFINITY);
+            wave_min_atomic(vb, &a.cur->jmin64);
+        }
+    }
+    __syncthreads();
+}
+
+template <int OBJ, typename Real> __global__ __launch_bounds__(192) void k_rollout3(KArgs a)
+{
+    __shared__ HeadVals h;
+    compute_head(a, h);
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_head(a, h);
+    rollout3_body<OBJ, Real>(a, blockIdx.x, h);
+}
+
 // ---------------------------------------------------------------- average
 
 template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
@@ -996,6 +1484,9 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
         r->i0 = cur->i0;
         r->shift = cur->shift;
         r->s = cur->s;
+        // the next solve's rollouts start their running minimum from +inf
+        cur->jmin32 = ordered_bits(INFINITY);
+        cur->jmin64 = ordered_bits((double)INFINITY);
         if (ok) {
             w->warm = 1;
             w->g0 = cur->g0;
@@ -1101,6 +1592,28 @@ template <int OBJ, typename Real, int WAVES> __global__ __launch_bounds__(64 * W
     }
 }
 
+template <int OBJ, typename Real> __global__ __launch_bounds__(192) void kb_rollout3(BArgs b)
+{
+    __shared__ KArgs s_a;
+    __shared__ HeadVals h;
+    __shared__ int s_ctx, s_unit;
+    if (threadIdx.x == 0) s_ctx = -1;
+    const int n = b.desc->n, total = b.desc->n_tiles;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_unit = (int)atomicAdd(&b.desc->queue, 1u);
+        __syncthreads();
+        const int u = s_unit;
+        if (u >= total) break;
+        const int item = find_item(b.tile_prefix, n, u);
+        stage_args(s_a, s_ctx, b, item);
+        const int blk = u - b.tile_prefix[item];
+        compute_head(s_a, h);
+        if (blk == 0 && threadIdx.x == 0) publish_head(s_a, h);
+        rollout3_body<OBJ, Real>(s_a, blk, h);
+    }
+}
+
 template <typename Acc, bool HAS_V> __global__ __launch_bounds__(256) void kb_tail(BArgs b)
 {
     __shared__ KArgs s_a;
@@ -1133,8 +1646,11 @@ template <typename Real, int OBJ>
 static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream_t st)
 {
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
-    hipLaunchKernelGGL((kb_sample<Real, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
-    if (L.rollout_waves == 2)
+    if (L.rollout_waves != 3)
+        hipLaunchKernelGGL((kb_sample<Real, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
+    if (L.rollout_waves == 3)
+        hipLaunchKernelGGL((kb_rollout3<OBJ, Real>), dim3(L.rollout_groups), dim3(192), 0, st, b);
+    else if (L.rollout_waves == 2)
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(128), 0, st, b);
     else
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 1>), dim3(L.rollout_groups), dim3(64), 0, st, b);
@@ -1194,9 +1710,11 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
     const dim3 gs((a.K + 1 + 255) / 256, a.N);
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
+    if (a.rollout_waves != 3) hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);
-    if (a.rollout_waves == 2)
+    if (a.rollout_waves == 3)
+        hipLaunchKernelGGL((k_rollout3<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(192), 0, st, a);
+    else if (a.rollout_waves == 2)
         hipLaunchKernelGGL((k_rollout_split<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(128), 0, st, a);
     else
         hipLaunchKernelGGL((k_rollout<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(64), 0, st, a);

@@ -189,10 +189,9 @@ static void plan_average(mppi_ctx *c)
     // one wave per 64 samples issues fewer instructions in total.  The
     // environment variable MPPI_ROLLOUT_WAVES (1 or 2) overrides the choice.
     const int waves = (K + 1 + 63) / 64;
-    a.rollout_waves = waves < 1024 ? 2 : 1;
+    a.rollout_waves = waves < 1024 ? 3 : 1;
     if (const char *e = getenv("MPPI_ROLLOUT_WAVES")) {
-        if (e[0] == '1') a.rollout_waves = 1;
-        if (e[0] == '2') a.rollout_waves = 2;
+        if (e[0] >= '1' && e[0] <= '3') a.rollout_waves = e[0] - '0';
     }
 }
 
@@ -358,6 +357,11 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     if (e == hipSuccess) e = hipMemsetAsync(wU, 0, sizeof(double) * kNMax * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(wV, 0, sizeof(double) * kNMax, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(res, 0, sizeof(DevResult), c->stream);
+    DevCur c0;
+    memset(&c0, 0, sizeof c0);
+    c0.jmin32 = 0xff800000u;                 // ordered bits of +inf (binary32)
+    c0.jmin64 = 0xfff0000000000000ull;       // ordered bits of +inf (binary64)
+    if (e == hipSuccess) e = hipMemcpyAsync(cur, &c0, sizeof c0, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_setup(a, c->fp64, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -673,8 +677,8 @@ static void resolve_cfg(mppi_batch *b)
 {
     mppi_batch_cfg &c = b->cfg;
     int waves = c.rollout_waves;
-    if (waves != 1 && waves != 2) waves = b->total_tiles < 4 * b->n_cu ? 2 : 1;
-    int rg = c.rollout_groups > 0 ? c.rollout_groups : (waves == 2 ? 2 * b->n_cu : 8 * b->n_cu);
+    if (waves < 1 || waves > 3) waves = b->total_tiles < 4 * b->n_cu ? 3 : 1;
+    int rg = c.rollout_groups > 0 ? c.rollout_groups : (waves >= 2 ? b->n_cu : 8 * b->n_cu);
     int sg = c.sample_groups > 0 ? c.sample_groups : 4 * b->n_cu;
     for (auto &g : b->groups) {
         g.launch.objective = g.objective;
@@ -797,7 +801,7 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
 mppi_status mppi_batch_set_cfg(mppi_batch *b, const mppi_batch_cfg *cfg)
 {
     if (!b || !cfg) return bfail(b, MPPI_E_INVAL, "batch and cfg are required");
-    if (cfg->rollout_waves < 0 || cfg->rollout_waves > 2 || cfg->rollout_groups < 0 || cfg->sample_groups < 0)
+    if (cfg->rollout_waves < 0 || cfg->rollout_waves > 3 || cfg->rollout_groups < 0 || cfg->sample_groups < 0)
         return bfail(b, MPPI_E_INVAL, "invalid launch shape");
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     drop_graph(b);
@@ -927,10 +931,10 @@ mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u
     const mppi_batch_cfg saved = b->cfg;
     std::vector<mppi_batch_cfg> cand;
     const int cu = b->n_cu;
-    for (int waves = 1; waves <= 2; ++waves) {
+    for (int waves = 1; waves <= 3; ++waves) {
         const int rg_mult[] = {1, 2, 4, 8};
         for (int rm : rg_mult) {
-            if (waves == 2 && rm > 2) continue;  // two 64 KB LDS rings fit one CU
+            if (waves >= 2 && rm > 2) continue;  // one or two LDS rings fit one CU
             for (int sm : {1, 4}) cand.push_back(mppi_batch_cfg{waves, rm * cu, sm * cu, 1});
         }
     }

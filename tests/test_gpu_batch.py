@@ -36,15 +36,15 @@ def solver_for(w, precision):
 
 
 @pytest.mark.parametrize("precision", [M.FP32, M.FP64])
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_equals_solo(precision, use_graph, monkeypatch):
+@pytest.mark.parametrize("use_graph,waves", [(True, 3), (False, 2), (True, 1)])
+def test_batch_equals_solo(precision, use_graph, waves, monkeypatch):
     import torch
-    say("batch vs solo", precision, "graph", use_graph)
-    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "2")
+    say("batch vs solo", precision, "graph", use_graph, "waves", waves)
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", str(waves))
     inst = make_instances(12, seed=1, objectives=("gate", "contour", "track"), precision=precision)
     solo = [solver_for(w, precision) for w in inst]
     bat = [solver_for(w, precision) for w in inst]
-    B = M.Batch(bat, rollout_waves=2, use_graph=use_graph)
+    B = M.Batch(bat, rollout_waves=waves, use_graph=use_graph)
     n = len(inst)
     reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
     u0s = torch.zeros((n, 4), dtype=torch.float64, device="cuda")

@@ -38,7 +38,7 @@ def test_single_solve_gate(precision, seed, lam):
     dev.close()
 
 
-@pytest.fixture(params=["1", "2"], ids=["one-wave", "two-wave"])
+@pytest.fixture(params=["1", "2", "3"], ids=["one-wave", "two-wave", "three-wave"])
 def rollout_waves(request, monkeypatch):
     """Both rollout layouts (read by mppi_create)."""
     monkeypatch.setenv("MPPI_ROLLOUT_WAVES", request.param)
@@ -160,7 +160,7 @@ def test_rollout_layouts_agree(precision, monkeypatch):
     say("layouts agree", precision)
     w = _workload(4096, 80, seed=12, **{"lambda": 40.0})
     out = []
-    for waves in ("1", "2"):
+    for waves in ("1", "2", "3"):
         monkeypatch.setenv("MPPI_ROLLOUT_WAVES", waves)
         dev, _ = build_pair(w, precision)
         u0, U, info = dev.solve(w["x0"], 0.0)
@@ -168,8 +168,9 @@ def test_rollout_layouts_agree(precision, monkeypatch):
         out.append((J, U))
         dev.close()
     eps = 1e-13 if precision == M.FP64 else 1e-5
-    np.testing.assert_allclose(out[0][0], out[1][0], rtol=eps, atol=eps)
-    np.testing.assert_allclose(out[0][1], out[1][1], rtol=0, atol=1e-3 if precision == M.FP32 else 1e-12)
+    for other in out[1:]:
+        np.testing.assert_allclose(out[0][0], other[0], rtol=eps, atol=eps)
+        np.testing.assert_allclose(out[0][1], other[1], rtol=0, atol=1e-3 if precision == M.FP32 else 1e-12)
 
 
 @pytest.mark.parametrize("precision", [M.FP64, M.FP32])
