@@ -19,6 +19,7 @@ namespace mppi {
 constexpr int kNMax = 256;
 constexpr int kMaskWords = 9;   // (kNMax + 1) bits
 constexpr int kReqDoubles = 16;
+constexpr int kMaxTiles = 32;   // sample tiles per step of the weighted-average reduction
 
 enum Objective { OBJ_GATE = 0, OBJ_CONTOUR = 1, OBJ_TRACK = 2 };
 enum Status { ST_OK = 0, ST_INVAL = -1, ST_NOMEM = -2, ST_DEVICE = -3, ST_NONFINITE = -4 };

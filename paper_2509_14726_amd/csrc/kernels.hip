@@ -1428,15 +1428,25 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
     const Acc *part_den = part + (size_t)N * n_mt * C;
     DevCur *cur = a.cur;
     const double jmin = a.real_bytes == 4 ? (double)from_ordered(cur->jmin32) : from_ordered(cur->jmin64);
+    // every tile partial of an output is loaded before any is added (the
+    // loads overlap), then they are added in tile order
     if (tid < 2) {
+        Acc vals[kMaxTiles];
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t) vals[t] = t < n_mt ? part_den[2 * t + tid] : Acc(0);
         Acc sden = 0;
-        for (int t = 0; t < n_mt; ++t) sden += part_den[2 * t + tid];
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t) sden += vals[t];
         s_den[tid] = sden;
     }
     for (int idx = tid; idx < N * C; idx += blockDim.x) {
         const int k = idx / C, ch = idx % C;
+        Acc vals[kMaxTiles];
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t) vals[t] = t < n_mt ? part[((size_t)k * n_mt + t) * C + ch] : Acc(0);
         Acc sum = 0;
-        for (int t = 0; t < n_mt; ++t) sum += part[((size_t)k * n_mt + t) * C + ch];
+#pragma unroll
+        for (int t = 0; t < kMaxTiles; ++t) sum += vals[t];
         s_u[idx] = sum;
     }
     __syncthreads();

@@ -169,14 +169,14 @@ static mppi_status validate(const mppi_params *p, const mppi_quad *q, const mppi
     return MPPI_OK;
 }
 
-// Reduction tiling: one step per block, sample tiles of a multiple of 256
-// samples, about two thousand blocks in all and at most 32 tiles per step.
+// Reduction tiling: one step per block, sample tiles of at least 4096
+// samples (a multiple of 256), at most kMaxTiles tiles per step.
 static void plan_average(mppi_ctx *c)
 {
     KArgs &a = c->args;
-    const int K = c->K, N = c->N;
-    int n_mt = (2048 + N - 1) / N;
-    if (n_mt > 32) n_mt = 32;
+    const int K = c->K;
+    int n_mt = (K + 4095) / 4096;
+    if (n_mt > kMaxTiles) n_mt = kMaxTiles;
     const int max_mt = (K + 255) / 256;
     if (n_mt > max_mt) n_mt = max_mt;
     if (n_mt < 1) n_mt = 1;

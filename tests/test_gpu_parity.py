@@ -190,3 +190,17 @@ def test_sample_tensor_matches_oracle_samples(precision):
     say("  max |dU|", err)
     assert err <= (1e-12 if precision == M.FP64 else 2e-5)
     dev.close()
+
+
+@pytest.mark.parametrize("lam", [1.0, 1e5])
+def test_large_solve_fp32_with_fp64_average(lam):
+    """K = 262144, N = 200, dt = 0.01 on a 12-gate track: binary32 rollouts,
+    binary64 weighted average (K >= 65536), every cost and the update against
+    the oracle.  lambda = 1e5 spreads the weights over many samples, so the
+    average really sums a quarter million terms."""
+    say("large solve K=262144 N=200 lambda", lam)
+    w = _workload(262144, 200, seed=5, track_seed=5, n_gates=12, dt=0.01, **{"lambda": lam})
+    dev, orc = build_pair(w, M.FP32, n_threads=16)
+    st = solve_and_compare(dev, orc, w["x0"], 0.0, M.FP32)
+    say("  err_J", st["err_J"], "err_U", st["err_U"], "e2e", st["err_U_e2e"], "ambiguous", st["n_amb"])
+    dev.close()
