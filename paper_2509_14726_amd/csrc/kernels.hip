@@ -516,6 +516,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
     const Real dt = (Real)a.dt;
     const Real h2 = Real(0.5) * dt;
     const Real dt6 = dt / Real(6);
+    const Real h4 = Real(0.5) * h2, dt12 = Real(0.5) * dt6;
     const Real w_max = (Real)a.w_max, w_lim = (Real)a.w_lim;
     const bool use_nom = m >= K;  // lanes past K read the nominal row, results unused
     const R4 *urow = use_nom ? (const R4 *)a.nomU : (const R4 *)a.ctrl + m;
@@ -620,10 +621,12 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                     kw[0] = in.tx - M.gx * ws[1] * ws[2];
                     kw[1] = in.ty - M.gy * ws[2] * ws[0];
                     kw[2] = in.tz - M.gz * ws[0] * ws[1];
-                    kq[0] = Real(0.5) * (-qs[1] * ws[0] - qs[2] * ws[1] - qs[3] * ws[2]);
-                    kq[1] = Real(0.5) * (qs[0] * ws[0] + qs[2] * ws[2] - qs[3] * ws[1]);
-                    kq[2] = Real(0.5) * (qs[0] * ws[1] - qs[1] * ws[2] + qs[3] * ws[0]);
-                    kq[3] = Real(0.5) * (qs[0] * ws[2] + qs[1] * ws[1] - qs[2] * ws[0]);
+                    // kq is twice the quaternion rate; the factor 1/2 is
+                    // carried by the step sizes (exact: a power of two)
+                    kq[0] = -qs[1] * ws[0] - qs[2] * ws[1] - qs[3] * ws[2];
+                    kq[1] = qs[0] * ws[0] + qs[2] * ws[2] - qs[3] * ws[1];
+                    kq[2] = qs[0] * ws[1] - qs[1] * ws[2] + qs[3] * ws[0];
+                    kq[3] = qs[0] * ws[2] + qs[1] * ws[1] - qs[2] * ws[0];
                     if (st == 0) {
 #pragma unroll
                         for (int i = 0; i < 3; ++i) dw[i] = kw[i];
@@ -638,14 +641,15 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
 #pragma unroll
                         for (int i = 0; i < 3; ++i) dw[i] = dt6 * (dw[i] + kw[i]);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) dq[i] = dt6 * (dq[i] + kq[i]);
+                        for (int i = 0; i < 4; ++i) dq[i] = dt12 * (dq[i] + kq[i]);
                     }
                     if (st < 3) {
                         const Real hh = st < 2 ? h2 : dt;
+                        const Real hq = st < 2 ? h4 : h2;
 #pragma unroll
                         for (int i = 0; i < 3; ++i) ws[i] = w[i] + hh * kw[i];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) qs[i] = q[i] + hh * kq[i];
+                        for (int i = 0; i < 4; ++i) qs[i] = q[i] + hq * kq[i];
                     }
                 }
                 // commit the step (compensated in binary32), unit quaternion
@@ -914,16 +918,25 @@ template <typename Real> struct Ring3;
 template <> struct Ring3<float> { static constexpr int B = 8; };
 template <> struct Ring3<double> { static constexpr int B = 4; };
 
-template <int OBJ, typename Real>
+//
+// With NW = 2 a fourth wave shares the sampling: waves 0 and 3 take the even
+// and the odd steps of each chunk, and the control-rate and progress-speed
+// cost terms, which need the previous step's input, are added by wave 0 one
+// chunk later from an LDS ring of the clipped inputs (same terms, same order).
+template <int OBJ, typename Real, int NW>
 __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const HeadVals &h)
 {
     typedef typename Vec4<Real>::T R4;
     constexpr int B = Ring3<Real>::B;
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
+    constexpr bool DEFER_RATE = NW == 2 && OBJ != OBJ_GATE;
     __shared__ R4 s_in[3][B][64];                  // (F/m, tau_x/J_x, tau_y/J_y, tau_z/J_z)
     __shared__ Real s_v[HAS_V ? 3 : 1][B][64];     // progress speed
     __shared__ R4 s_q[2][B][4][64];                // stage quaternions
     __shared__ Real s_jp[2][64];                   // partial costs of waves 0 and 1
+    __shared__ R4 s_us[kNMax];                     // shifted warm-start thrusts per step
+    __shared__ R4 s_u[DEFER_RATE ? 3 : 1][B][64];  // clipped inputs, for the deferred rate terms
+    __shared__ Real s_vs[HAS_V ? kNMax : 1];       // shifted warm-start progress speed
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -936,6 +949,7 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     const Real dt = (Real)a.dt;
     const Real h2 = Real(0.5) * dt;
     const Real dt6 = dt / Real(6);
+    const Real h4 = Real(0.5) * h2, dt12 = Real(0.5) * dt6;
     const Real w_max = (Real)a.w_max, w_lim = (Real)a.w_lim;
     const Real *xref = (const Real *)a.xref_r;
     const int i0 = h.i0;
@@ -986,17 +1000,51 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     R4g *ctrl = (R4g *)a.ctrl;
     Real *vctrl = (Real *)a.vctrl;
 
+    // the shifted warm start (Alg. 1, warm start) of every step, staged once
+    // so that the sampling wave reads it from LDS instead of waiting on a
+    // dependent global load per step
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        int src = k + h.shift;
+        if (src > N - 1) src = N - 1;
+        R4 o;
+        o.x = h.warm ? (Real)a.wU[4 * src + 0] : hover;
+        o.y = h.warm ? (Real)a.wU[4 * src + 1] : hover;
+        o.z = h.warm ? (Real)a.wU[4 * src + 2] : hover;
+        o.w = h.warm ? (Real)a.wU[4 * src + 3] : hover;
+        s_us[k] = o;
+        if (HAS_V) s_vs[k] = h.warm ? (Real)a.wV[src] : Real(0);
+    }
+    __syncthreads();
+
     const int nch = (N + B - 1) / B;
+    const bool noise_wave = wave == 0 || (NW == 2 && wave == 3);
+    const int k_first = (NW == 2 && wave == 3) ? 1 : 0;
     for (int c = 0; c <= nch + 1; ++c) {
-        if (wave == 0 && c < nch) {
-            const int kb = c * B, ke = min(N, kb + B);
+        if (DEFER_RATE && wave == 0 && c >= 1 && c <= nch) {
+            // rate terms of the previous chunk, in step order
+            const int kb = (c - 1) * B, ke = min(N, kb + B);
             for (int k = kb; k < ke; ++k) {
                 const int j = k - kb;
-                int src = k + h.shift;
-                if (src > N - 1) src = N - 1;
-                Real us[4];
-                for (int i = 0; i < 4; ++i) us[i] = h.warm ? (Real)a.wU[4 * src + i] : hover;
-                const Real vs = h.warm ? (Real)a.wV[src] : Real(0);
+                const R4 u = s_u[(c - 1) % 3][j][lane];
+                const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
+                Real term = rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                if (HAS_V) {
+                    const Real V = s_v[(c - 1) % 3][j][lane];
+                    const Real dv = V - vp;
+                    term += r_dv * dv * dv;
+                    term -= (Real)a.mu * V;
+                    vp = V;
+                }
+                J.add(term);
+                up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
+            }
+        }
+        if (noise_wave && c < nch) {
+            const int kb = c * B, ke = min(N, kb + B);
+            auto noise_step = [&](const int k, const int j) {
+                const R4 w4 = s_us[k];
+                const Real us[4] = {w4.x, w4.y, w4.z, w4.w};
+                const Real vs = HAS_V ? s_vs[k] : Real(0);
                 R4 u;
                 Real V = Real(0);
                 if (sampled) {
@@ -1019,29 +1067,35 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     u.w = clampT(us[3], tmin, tmax);
                     if (HAS_V) V = clampT(vs, Real(0), vmax);
                 }
-                Real term = Real(0);
-                if (OBJ != OBJ_GATE) {
+                if (HAS_V) s_v[c % 3][j][lane] = V;
+                if (DEFER_RATE) {
+                    s_u[c % 3][j][lane] = u;
+                } else if (OBJ != OBJ_GATE) {
                     const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
-                    term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                    Real term = rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                    if (HAS_V) {
+                        const Real dv = V - vp;
+                        term += r_dv * dv * dv;
+                        term -= (Real)a.mu * V;
+                        vp = V;
+                    }
+                    J.add(term);
+                    up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
                 }
-                if (HAS_V) {
-                    const Real dv = V - vp;
-                    term += r_dv * dv * dv;
-                    term -= (Real)a.mu * V;
-                    vp = V;
-                    s_v[c % 3][j][lane] = V;
-                }
-                if (OBJ != OBJ_GATE) J.add(term);
-                up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
                 const StepInput<Real> in = step_input(M, u.x, u.y, u.z, u.w);
                 R4 o;
                 o.x = in.fm; o.y = in.tx; o.z = in.ty; o.w = in.tz;
                 s_in[c % 3][j][lane] = o;
+            };
+            if (ke - kb == B) {
+#pragma unroll
+                for (int j = 0; j < B; j += NW) noise_step(kb + j + k_first, j + k_first);
+            } else {
+                for (int k = kb + k_first; k < ke; k += NW) noise_step(k, k - kb);
             }
         } else if (wave == 1 && c >= 1 && c <= nch) {
             const int kb = (c - 1) * B, ke = min(N, kb + B);
-            for (int k = kb; k < ke; ++k) {
-                const int j = k - kb;
+            auto rot_step = [&](const int k, const int j) {
                 const R4 in = s_in[(c - 1) % 3][j][lane];
                 R4 (*slot)[64] = s_q[(c - 1) & 1][j];
                 Real term = Real(0);
@@ -1076,10 +1130,12 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     kw[0] = in.y - M.gx * ws[1] * ws[2];
                     kw[1] = in.z - M.gy * ws[2] * ws[0];
                     kw[2] = in.w - M.gz * ws[0] * ws[1];
-                    kq[0] = Real(0.5) * (-qs[1] * ws[0] - qs[2] * ws[1] - qs[3] * ws[2]);
-                    kq[1] = Real(0.5) * (qs[0] * ws[0] + qs[2] * ws[2] - qs[3] * ws[1]);
-                    kq[2] = Real(0.5) * (qs[0] * ws[1] - qs[1] * ws[2] + qs[3] * ws[0]);
-                    kq[3] = Real(0.5) * (qs[0] * ws[2] + qs[1] * ws[1] - qs[2] * ws[0]);
+                    // kq is twice the quaternion rate; the factor 1/2 is
+                    // carried by the step sizes (exact: a power of two)
+                    kq[0] = -qs[1] * ws[0] - qs[2] * ws[1] - qs[3] * ws[2];
+                    kq[1] = qs[0] * ws[0] + qs[2] * ws[2] - qs[3] * ws[1];
+                    kq[2] = qs[0] * ws[1] - qs[1] * ws[2] + qs[3] * ws[0];
+                    kq[3] = qs[0] * ws[2] + qs[1] * ws[1] - qs[2] * ws[0];
                     if (st == 0) {
 #pragma unroll
                         for (int i = 0; i < 3; ++i) dw[i] = kw[i];
@@ -1094,14 +1150,15 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
 #pragma unroll
                         for (int i = 0; i < 3; ++i) dw[i] = dt6 * (dw[i] + kw[i]);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) dq[i] = dt6 * (dq[i] + kq[i]);
+                        for (int i = 0; i < 4; ++i) dq[i] = dt12 * (dq[i] + kq[i]);
                     }
                     if (st < 3) {
                         const Real hh = st < 2 ? h2 : dt;
+                        const Real hq = st < 2 ? h4 : h2;
 #pragma unroll
                         for (int i = 0; i < 3; ++i) ws[i] = w[i] + hh * kw[i];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) qs[i] = q[i] + hh * kq[i];
+                        for (int i = 0; i < 4; ++i) qs[i] = q[i] + hq * kq[i];
                     }
                 }
                 if (sizeof(Real) == 4) {
@@ -1144,11 +1201,16 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     term += w_lim * e * e;
                 }
                 J.add(term);
+            };
+            if (ke - kb == B) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) rot_step(kb + j, j);
+            } else {
+                for (int k = kb; k < ke; ++k) rot_step(k, k - kb);
             }
         } else if (wave == 2 && c >= 2) {
             const int kb = (c - 2) * B, ke = min(N, kb + B);
-            for (int k = kb; k < ke; ++k) {
-                const int j = k - kb;
+            auto trans_step = [&](const int k, const int j) {
                 const R4 in = s_in[(c - 2) % 3][j][lane];
                 R4 qstage[4];
 #pragma unroll
@@ -1282,6 +1344,12 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     }
                 }
                 J.add(term);
+            };
+            if (ke - kb == B) {
+#pragma unroll
+                for (int j = 0; j < B; ++j) trans_step(kb + j, j);
+            } else {
+                for (int k = kb; k < ke; ++k) trans_step(k, k - kb);
             }
         }
         __syncthreads();
@@ -1340,12 +1408,12 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     __syncthreads();
 }
 
-template <int OBJ, typename Real> __global__ __launch_bounds__(192) void k_rollout3(KArgs a)
+template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 + NW)) void k_rollout3(KArgs a)
 {
     __shared__ HeadVals h;
     compute_head(a, h);
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_head(a, h);
-    rollout3_body<OBJ, Real>(a, blockIdx.x, h);
+    rollout3_body<OBJ, Real, NW>(a, blockIdx.x, h);
 }
 
 // ---------------------------------------------------------------- average
@@ -1384,18 +1452,35 @@ __device__ __forceinline__ void average_body(const KArgs &a, int mt, int k)
     Acc v[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = Acc(0);
-    for (int m = m_lo + tid; m < m_hi; m += 256) {
-        const Real Jm = J[m];
-        const Real wr = isfinite(Jm) ? exp(-(Jm - jmin) * inv_lambda) : Real(0);
-        const Acc w = (Acc)wr;
-        const R4 u = ctrl[m];
-        v[0] += w * (Acc)u.x;
-        v[1] += w * (Acc)u.y;
-        v[2] += w * (Acc)u.z;
-        v[3] += w * (Acc)u.w;
-        if (HAS_V) v[4] += w * (Acc)vctrl[m];
-        v[C] += w;
-        v[C + 1] += w * w;
+    // four samples per thread and round: their loads are issued together,
+    // then they are accumulated in sample order
+    constexpr int UR = 4;
+    for (int m0 = m_lo + tid; m0 < m_hi; m0 += 256 * UR) {
+        Real Jm[UR], vm[UR];
+        R4 u[UR];
+#pragma unroll
+        for (int i = 0; i < UR; ++i) {
+            const int m = m0 + 256 * i;
+            if (m < m_hi) {
+                Jm[i] = J[m];
+                u[i] = ctrl[m];
+                if (HAS_V) vm[i] = vctrl[m];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < UR; ++i) {
+            if (m0 + 256 * i < m_hi) {
+                const Real wr = isfinite(Jm[i]) ? exp(-(Jm[i] - jmin) * inv_lambda) : Real(0);
+                const Acc w = (Acc)wr;
+                v[0] += w * (Acc)u[i].x;
+                v[1] += w * (Acc)u[i].y;
+                v[2] += w * (Acc)u[i].z;
+                v[3] += w * (Acc)u[i].w;
+                if (HAS_V) v[4] += w * (Acc)vm[i];
+                v[C] += w;
+                v[C + 1] += w * w;
+            }
+        }
     }
     const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
@@ -1416,7 +1501,10 @@ __device__ __forceinline__ void average_body(const KArgs &a, int mt, int k)
 
 // One block: adds the tiles of every step in tile order, forms U = sums / S,
 // writes the first input, the report and the warm-start hand-over, and
-// re-arms the running minimum for the next solve.
+// re-arms the running minimum for the next solve.  Every global load (the
+// running minimum, the tile partials, the nominal's front flags, the head
+// values) is issued before the first of them is used, so the block waits on
+// memory about once.
 template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(const KArgs &a)
 {
     constexpr int C = HAS_V ? 5 : 4;
@@ -1427,9 +1515,27 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
     const Acc *part = (const Acc *)a.part;
     const Acc *part_den = part + (size_t)N * n_mt * C;
     DevCur *cur = a.cur;
+    DevWarm *w = a.warm;
+    const bool gate = a.objective == OBJ_GATE;
+
     const double jmin = a.real_bytes == 4 ? (double)from_ordered(cur->jmin32) : from_ordered(cur->jmin64);
-    // every tile partial of an output is loaded before any is added (the
-    // loads overlap), then they are added in tile order
+    // front flag of the nominal at step j = tid (and j = 256 for N = 256)
+    const bool fr = gate && tid <= N && a.front8[tid] != 0;
+    const bool fr_last = gate && tid == 0 && N >= 256 && a.front8[256] != 0;
+    double rep_Jnom = 0.0, rep_theta0 = 0.0, rep_t = 0.0, rep_x0[13];
+    int32_t rep_g0 = 0, rep_i0 = 0, rep_shift = 0;
+    uint32_t rep_s = 0;
+    if (tid == 0) {
+        rep_Jnom = cur->J_nom;
+        rep_theta0 = cur->theta0;
+        rep_t = cur->t_now;
+        rep_g0 = cur->g0;
+        rep_i0 = cur->i0;
+        rep_shift = cur->shift;
+        rep_s = cur->s;
+        for (int i = 0; i < 13; ++i) rep_x0[i] = cur->x0[i];
+    }
+    // tile partials: all loads of an output first, then the sum in tile order
     if (tid < 2) {
         Acc vals[kMaxTiles];
 #pragma unroll
@@ -1452,7 +1558,6 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
     __syncthreads();
     const Acc den = s_den[0], den2 = s_den[1];
     const bool ok = isfinite(jmin) && den > Acc(0);
-    DevWarm *w = a.warm;
     if (ok) {
         for (int idx = tid; idx < N * C; idx += blockDim.x) {
             const int k = idx / C, ch = idx % C;
@@ -1463,19 +1568,18 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
         if (!HAS_V)
             for (int k = tid; k < N; k += blockDim.x) a.wV[k] = 0.0;
     }
-    if (tid < kMaskWords && ok) {
-        uint32_t word = 0u;
-        if (a.objective == OBJ_GATE) {
-            for (int b = 0; b < 32; ++b) {
-                const int j = tid * 32 + b;
-                if (j <= N && a.front8[j]) word |= 1u << b;
-            }
-        } else {
-            word = 0xffffffffu;
+    // pass mask of the next solve: bit j = front flag of the nominal at step
+    // j, gathered by wave ballots (blocks of 256 threads)
+    if (gate) {
+        const unsigned long long bal = __ballot(fr);
+        if ((tid & 63) == 0 && ok) {
+            w->allow[tid >> 5] = (uint32_t)bal;
+            w->allow[(tid >> 5) + 1] = (uint32_t)(bal >> 32);
         }
-        w->allow[tid] = word;
+        if (tid == 0 && ok) w->allow[8] = fr_last ? 1u : 0u;
+    } else if (tid < kMaskWords && ok) {
+        w->allow[tid] = 0xffffffffu;
     }
-    __syncthreads();
     if (tid == 0) {
         DevResult *r = a.res;
         for (int i = 0; i < 4; ++i) {
@@ -1487,24 +1591,24 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
         r->S = (double)den;
         r->S2 = (double)den2;
         r->ess = ok ? (double)den * (double)den / (double)den2 : 0.0;
-        r->J_nom = cur->J_nom;
-        r->theta0 = cur->theta0;
+        r->J_nom = rep_Jnom;
+        r->theta0 = rep_theta0;
         r->status = ok ? ST_OK : ST_NONFINITE;
-        r->g0 = cur->g0;
-        r->i0 = cur->i0;
-        r->shift = cur->shift;
-        r->s = cur->s;
+        r->g0 = rep_g0;
+        r->i0 = rep_i0;
+        r->shift = rep_shift;
+        r->s = rep_s;
         // the next solve's rollouts start their running minimum from +inf
         cur->jmin32 = ordered_bits(INFINITY);
         cur->jmin64 = ordered_bits((double)INFINITY);
         if (ok) {
             w->warm = 1;
-            w->g0 = cur->g0;
-            w->s = cur->s + 1u;
+            w->g0 = rep_g0;
+            w->s = rep_s + 1u;
             w->N = N;
-            w->t_prev = cur->t_now;
-            w->theta0 = cur->theta0;
-            for (int i = 0; i < 13; ++i) w->x_prev[i] = cur->x0[i];
+            w->t_prev = rep_t;
+            w->theta0 = rep_theta0;
+            for (int i = 0; i < 13; ++i) w->x_prev[i] = rep_x0[i];
         }
     }
 }
@@ -1602,7 +1706,7 @@ template <int OBJ, typename Real, int WAVES> __global__ __launch_bounds__(64 * W
     }
 }
 
-template <int OBJ, typename Real> __global__ __launch_bounds__(192) void kb_rollout3(BArgs b)
+template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 + NW)) void kb_rollout3(BArgs b)
 {
     __shared__ KArgs s_a;
     __shared__ HeadVals h;
@@ -1620,7 +1724,7 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(192) void kb_roll
         const int blk = u - b.tile_prefix[item];
         compute_head(s_a, h);
         if (blk == 0 && threadIdx.x == 0) publish_head(s_a, h);
-        rollout3_body<OBJ, Real>(s_a, blk, h);
+        rollout3_body<OBJ, Real, NW>(s_a, blk, h);
     }
 }
 
@@ -1656,10 +1760,12 @@ template <typename Real, int OBJ>
 static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream_t st)
 {
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
-    if (L.rollout_waves != 3)
+    if (L.rollout_waves < 3)
         hipLaunchKernelGGL((kb_sample<Real, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
-    if (L.rollout_waves == 3)
-        hipLaunchKernelGGL((kb_rollout3<OBJ, Real>), dim3(L.rollout_groups), dim3(192), 0, st, b);
+    if (L.rollout_waves == 4)
+        hipLaunchKernelGGL((kb_rollout3<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(256), 0, st, b);
+    else if (L.rollout_waves == 3)
+        hipLaunchKernelGGL((kb_rollout3<OBJ, Real, 1>), dim3(L.rollout_groups), dim3(192), 0, st, b);
     else if (L.rollout_waves == 2)
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(128), 0, st, b);
     else
@@ -1720,10 +1826,12 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
     const dim3 gs((a.K + 1 + 255) / 256, a.N);
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (a.rollout_waves != 3) hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
+    if (a.rollout_waves < 3) hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);
-    if (a.rollout_waves == 3)
-        hipLaunchKernelGGL((k_rollout3<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(192), 0, st, a);
+    if (a.rollout_waves == 4)
+        hipLaunchKernelGGL((k_rollout3<OBJ, Real, 2>), dim3((a.K + 1 + 63) / 64), dim3(256), 0, st, a);
+    else if (a.rollout_waves == 3)
+        hipLaunchKernelGGL((k_rollout3<OBJ, Real, 1>), dim3((a.K + 1 + 63) / 64), dim3(192), 0, st, a);
     else if (a.rollout_waves == 2)
         hipLaunchKernelGGL((k_rollout_split<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(128), 0, st, a);
     else

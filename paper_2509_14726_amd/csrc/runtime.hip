@@ -169,13 +169,14 @@ static mppi_status validate(const mppi_params *p, const mppi_quad *q, const mppi
     return MPPI_OK;
 }
 
-// Reduction tiling: one step per block, sample tiles of at least 4096
-// samples (a multiple of 256), at most kMaxTiles tiles per step.
+// Reduction tiling: one step per block, sample tiles of a multiple of 256
+// samples, about two thousand blocks in all (enough loads in flight to
+// stream the sample tensor) and at most kMaxTiles tiles per step.
 static void plan_average(mppi_ctx *c)
 {
     KArgs &a = c->args;
-    const int K = c->K;
-    int n_mt = (K + 4095) / 4096;
+    const int K = c->K, N = c->N;
+    int n_mt = (2048 + N - 1) / N;
     if (n_mt > kMaxTiles) n_mt = kMaxTiles;
     const int max_mt = (K + 255) / 256;
     if (n_mt > max_mt) n_mt = max_mt;
@@ -184,14 +185,15 @@ static void plan_average(mppi_ctx *c)
     mt = (mt + 255) / 256 * 256;
     a.mt_size = mt;
     a.n_mt = (K + mt - 1) / mt;
-    // Rollout layout: with fewer waves than SIMDs (1024 on MI355X) the chip
-    // is latency bound and the two-wave split shortens each step; with more,
+    // Rollout layout: with fewer 64-sample tiles than SIMDs (1024 on MI355X)
+    // the chip is latency bound and splitting each tile's work over several
+    // waves (sampling, attitude, translation) shortens each step; with more,
     // one wave per 64 samples issues fewer instructions in total.  The
-    // environment variable MPPI_ROLLOUT_WAVES (1 or 2) overrides the choice.
+    // environment variable MPPI_ROLLOUT_WAVES (1..4) overrides the choice.
     const int waves = (K + 1 + 63) / 64;
     a.rollout_waves = waves < 1024 ? 3 : 1;
     if (const char *e = getenv("MPPI_ROLLOUT_WAVES")) {
-        if (e[0] >= '1' && e[0] <= '3') a.rollout_waves = e[0] - '0';
+        if (e[0] >= '1' && e[0] <= '4') a.rollout_waves = e[0] - '0';
     }
 }
 
@@ -677,7 +679,7 @@ static void resolve_cfg(mppi_batch *b)
 {
     mppi_batch_cfg &c = b->cfg;
     int waves = c.rollout_waves;
-    if (waves < 1 || waves > 3) waves = b->total_tiles < 4 * b->n_cu ? 3 : 1;
+    if (waves < 1 || waves > 4) waves = b->total_tiles < 4 * b->n_cu ? 3 : 1;
     int rg = c.rollout_groups > 0 ? c.rollout_groups : (waves >= 2 ? b->n_cu : 8 * b->n_cu);
     int sg = c.sample_groups > 0 ? c.sample_groups : 4 * b->n_cu;
     for (auto &g : b->groups) {
@@ -801,7 +803,7 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
 mppi_status mppi_batch_set_cfg(mppi_batch *b, const mppi_batch_cfg *cfg)
 {
     if (!b || !cfg) return bfail(b, MPPI_E_INVAL, "batch and cfg are required");
-    if (cfg->rollout_waves < 0 || cfg->rollout_waves > 3 || cfg->rollout_groups < 0 || cfg->sample_groups < 0)
+    if (cfg->rollout_waves < 0 || cfg->rollout_waves > 4 || cfg->rollout_groups < 0 || cfg->sample_groups < 0)
         return bfail(b, MPPI_E_INVAL, "invalid launch shape");
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     drop_graph(b);
@@ -931,7 +933,7 @@ mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u
     const mppi_batch_cfg saved = b->cfg;
     std::vector<mppi_batch_cfg> cand;
     const int cu = b->n_cu;
-    for (int waves = 1; waves <= 3; ++waves) {
+    for (int waves = 1; waves <= 4; ++waves) {
         const int rg_mult[] = {1, 2, 4, 8};
         for (int rm : rg_mult) {
             if (waves >= 2 && rm > 2) continue;  // one or two LDS rings fit one CU

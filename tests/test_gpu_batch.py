@@ -36,7 +36,7 @@ def solver_for(w, precision):
 
 
 @pytest.mark.parametrize("precision", [M.FP32, M.FP64])
-@pytest.mark.parametrize("use_graph,waves", [(True, 3), (False, 2), (True, 1)])
+@pytest.mark.parametrize("use_graph,waves", [(True, 4), (True, 3), (False, 2), (True, 1)])
 def test_batch_equals_solo(precision, use_graph, waves, monkeypatch):
     import torch
     say("batch vs solo", precision, "graph", use_graph, "waves", waves)
@@ -135,6 +135,6 @@ def test_autotuner_picks_a_valid_shape():
     u0s = torch.zeros((len(S), 4), dtype=torch.float64, device="cuda")
     best, ms = B.autotune(reqs.data_ptr(), u0s.data_ptr(), reps=2)
     say("  best", best, ms)
-    assert best["rollout_waves"] in (1, 2) and best["rollout_groups"] > 0 and ms > 0
+    assert best["rollout_waves"] in (1, 2, 3, 4) and best["rollout_groups"] > 0 and ms > 0
     assert B.get_cfg()["rollout_waves"] == best["rollout_waves"]
     B.close()

@@ -38,9 +38,9 @@ def test_single_solve_gate(precision, seed, lam):
     dev.close()
 
 
-@pytest.fixture(params=["1", "2", "3"], ids=["one-wave", "two-wave", "three-wave"])
+@pytest.fixture(params=["1", "2", "3", "4"], ids=["one-wave", "two-wave", "three-wave", "four-wave"])
 def rollout_waves(request, monkeypatch):
-    """Both rollout layouts (read by mppi_create)."""
+    """Every rollout layout (read by mppi_create)."""
     monkeypatch.setenv("MPPI_ROLLOUT_WAVES", request.param)
     return request.param
 
@@ -153,20 +153,24 @@ def test_device_entry_point_matches_host_entry_point():
     b.close()
 
 
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
 @pytest.mark.parametrize("precision", [M.FP64, M.FP32])
-def test_rollout_layouts_agree(precision, monkeypatch):
-    """The one-wave and two-wave rollouts compute the same per-component
-    arithmetic: costs agree to a few ulps, the update to rounding."""
-    say("layouts agree", precision)
-    w = _workload(4096, 80, seed=12, **{"lambda": 40.0})
+def test_rollout_layouts_agree(precision, objective, monkeypatch):
+    """The rollout layouts compute the same per-component arithmetic: costs
+    agree to a few ulps, the update to rounding.  The three- and four-wave
+    layouts differ only in which wave draws a step's noise and when the rate
+    terms are added (same terms, same order), so they agree bit for bit."""
+    say("layouts agree", precision, objective)
+    w = _workload(4096, 80, objective=objective, seed=12, **{"lambda": 40.0})
     out = []
-    for waves in ("1", "2", "3"):
+    for waves in ("1", "2", "3", "4"):
         monkeypatch.setenv("MPPI_ROLLOUT_WAVES", waves)
         dev, _ = build_pair(w, precision)
         u0, U, info = dev.solve(w["x0"], 0.0)
         J, _ = dev.read_samples()
         out.append((J, U))
         dev.close()
+    assert np.array_equal(out[2][0], out[3][0]) and np.array_equal(out[2][1], out[3][1])
     eps = 1e-13 if precision == M.FP64 else 1e-5
     for other in out[1:]:
         np.testing.assert_allclose(out[0][0], other[0], rtol=eps, atol=eps)
