@@ -91,7 +91,7 @@ typedef struct {
 } mppi_params;
 
 /* The context allocates no per-solve workspace (sample tensor, costs,
- * reduction partials); a server lends one to each admitted solve.  Such a
+ * per-tile cost minima); a server lends one to each admitted solve.  Such a
  * context is solved only through a server (mppi_solve, mppi_solve_device and
  * mppi_read_samples return MPPI_E_INVAL). */
 #define MPPI_FLAG_EXTERNAL_WORKSPACE 1
@@ -154,8 +154,8 @@ typedef struct {
  * objective and the data it needs: G >= 1 gates, P >= 2 path points, R >= 1
  * reference rows), copies the problem data to the device and allocates all
  * device buffers: the N x K x 4 sample tensor (step-major: sample m of step k
- * at element (k*K + m)*4), K costs, the reduction partials and the warm-start
- * state.  stream is a hipStream_t (NULL: the library creates a non-blocking
+ * at element (k*K + m)*4), K costs, the per-tile cost minima and the
+ * warm-start state.  stream is a hipStream_t (NULL: the library creates a non-blocking
  * stream of default priority that it owns).  The context starts cold with
  * target gate 0.  On failure *out is NULL. */
 mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad,
@@ -215,7 +215,8 @@ mppi_status mppi_read_profile(mppi_ctx *ctx, double mean_ms[3], int32_t *n_solve
  * differ).  Each mppi_batch_solve_device call runs one MPPI step for a chosen
  * subset of them in a single launch sequence: a grid-stride sample kernel, a
  * persistent rollout kernel that pulls 64-sample tiles from a device queue in
- * order of decreasing horizon, and a grid-stride reduction kernel, per group
+ * order of decreasing horizon, and a grid-stride weighted-average kernel
+ * (one unit per context and horizon step), per group
  * of contexts sharing an objective and accumulation type.  Grids are fixed
  * and the work description lives in device memory, so the sequence is
  * captured once in a HIP graph (cfg.use_graph) and replayed for any subset.
@@ -275,7 +276,7 @@ const char *mppi_batch_last_error(const mppi_batch *b);
  * state.  mppi_server_progress retires finished launches and then, for every
  * idle launch slot (a stream with its own batch and graph), admits queued
  * heads in arrival order as long as their workspace (sample tensor, costs,
- * partials) fits in the free part of a device arena of budget_bytes, and
+ * tile minima) fits in the free part of a device arena of budget_bytes, and
  * launches them as one batch.  Requests that arrive while others run are
  * admitted as slots and memory free up; the slots' work overlaps on the
  * device.  A solve's result is the same as that of the context stepped alone. */

@@ -6,7 +6,7 @@
 //   vctrl  N x K Real      contouring progress-speed samples, same order
 //   nomU   N x 4 Real      clipped nominal sequence (the noise-free sample, lane K)
 //   J      K Real          sample costs
-//   part   partial weighted sums of the reduction over samples (per tile, per step)
+//   tmin   ceil((K+1)/64) Real  smallest finite cost of each 64-sample rollout tile
 //   warm   DevWarm + wU (N x 4 double) + wV (N double): what the next solve inherits
 //   cur    DevCur: per-solve values decided once by the head and read by every kernel
 #pragma once
@@ -19,7 +19,7 @@ namespace mppi {
 constexpr int kNMax = 256;
 constexpr int kMaskWords = 9;   // (kNMax + 1) bits
 constexpr int kReqDoubles = 16;
-constexpr int kMaxTiles = 32;   // sample tiles per step of the weighted-average reduction
+constexpr int kFinalThreads = 1024;  // threads of a block of the weighted-average kernel
 
 enum Objective { OBJ_GATE = 0, OBJ_CONTOUR = 1, OBJ_TRACK = 2 };
 enum Status { ST_OK = 0, ST_INVAL = -1, ST_NOMEM = -2, ST_DEVICE = -3, ST_NONFINITE = -4 };
@@ -37,8 +37,7 @@ struct DevWarm {
 
 struct DevCur {
     int32_t g0, i0, shift, warm;
-    uint32_t s, ticket, jmin32, pad0;
-    unsigned long long jmin64;
+    uint32_t s, pad0[3];
     uint32_t allow[kMaskWords];
     int32_t pad1;
     double theta0, t_now;
@@ -61,7 +60,7 @@ struct DevResult {
 struct KArgs {
     int32_t K, N, G, P, R, objective;
     int32_t C, real_bytes, acc_bytes, pad2;   // channels (4, 5 contouring), sizes for ws_layout
-    int32_t mt_size, n_mt;      // reduction tiles: samples per tile, tiles per step
+    int32_t n_tiles, pad3;      // 64-sample rollout tiles: ceil((K + 1) / 64)
     int32_t proj_window, has_drag;
     int32_t rollout_waves, pad_;  // 1: one wave per 64 samples; 2: attitude and translation on two waves
     uint32_t seed_lo, seed_hi;
@@ -89,8 +88,7 @@ struct KArgs {
     DevCur *cur;
     DevResult *res;
     void *ctrl, *vctrl, *nomU, *nomV, *J;
-    void *part;                 // Acc: [N][n_mt][C] tile sums, [n_mt][2] weight sums, [N][C] + 2 step sums
-    uint32_t *tickets;          // kNMax + 1 completion counters of the reduction
+    void *tmin;                 // n_tiles Real: smallest finite sample cost per rollout tile
     uint8_t *front8;            // N + 1 bytes written by the nominal lane
     // per-call
     const double *req;          // x0[13], t_now
@@ -98,13 +96,13 @@ struct KArgs {
 };
 
 // Per-solve scratch of one context, carved out of one block: the sample
-// tensor, costs, reduction partials and counters.  Offsets are multiples of
-// 256 bytes.  rs / as: bytes of Real and of the accumulation type.
+// tensor, costs, tile minima and the nominal's front flags.  Offsets are
+// multiples of 256 bytes.  rs: bytes of Real.
 struct WsLayout {
-    size_t ctrl, vctrl, nomU, nomV, J, part, tickets, front8, total;
+    size_t ctrl, vctrl, nomU, nomV, J, tmin, front8, total;
 };
 
-__host__ __device__ inline WsLayout ws_layout(int K, int N, int C, int n_mt, int rs, int as)
+__host__ __device__ inline WsLayout ws_layout(int K, int N, int C, int rs)
 {
     WsLayout l;
     size_t o = 0;
@@ -114,8 +112,7 @@ __host__ __device__ inline WsLayout ws_layout(int K, int N, int C, int n_mt, int
     l.nomU = o; o += (rs * 4 * n + 255) / 256 * 256;
     l.nomV = o; o += (rs * n + 255) / 256 * 256;
     l.J = o; o += (rs * k + 255) / 256 * 256;
-    l.part = o; o += (as * ((size_t)n_mt * n * C + 2 * (size_t)n_mt + n * C + 2) + 255) / 256 * 256;
-    l.tickets = o; o += (sizeof(uint32_t) * (kNMax + 1) + 255) / 256 * 256;
+    l.tmin = o; o += (rs * ((k + 1 + 63) / 64) + 255) / 256 * 256;
     l.front8 = o; o += (n + 1 + 255) / 256 * 256;
     l.total = o;
     return l;
@@ -138,7 +135,7 @@ struct BatchDesc {
     int32_t n;                  // items
     int32_t n_sample_units;     // sum over items of ceil((K+1)/256) * N
     int32_t n_tiles;            // sum over items of ceil((K+1)/64)
-    int32_t n_avg_units;        // sum over items of n_mt * N
+    int32_t n_steps;            // sum over items of N (units of the weighted-average kernel)
     uint32_t queue;             // rollout tile counter, reset by the sample kernel
     uint32_t pad[3];
 };
@@ -147,32 +144,12 @@ struct BArgs {
     const KArgs *table;         // kernel arguments of every registered context
     BatchDesc *desc;
     const BatchItem *items;     // n entries
-    const int32_t *sample_prefix, *tile_prefix, *avg_prefix;  // n + 1 entries each
+    const int32_t *sample_prefix, *tile_prefix, *step_prefix;  // n + 1 entries each
 };
 
 template <typename T> __device__ __forceinline__ T clampT(T v, T lo, T hi)
 {
     return v < lo ? lo : (v > hi ? hi : v);
-}
-
-// Order-preserving maps of finite floats to unsigned integers (for atomicMin).
-__device__ __forceinline__ uint32_t ordered_bits(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float from_ordered(uint32_t u)
-{
-    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
-__device__ __forceinline__ unsigned long long ordered_bits(double f)
-{
-    unsigned long long u = (unsigned long long)__double_as_longlong(f);
-    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double from_ordered(unsigned long long u)
-{
-    return __longlong_as_double((long long)((u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u));
 }
 
 // Compensated (Kahan) running sum.  For double the compensation is dropped.

@@ -200,11 +200,7 @@ __device__ void solve_head(const KArgs &a)
     compute_head(a, h);
     if (threadIdx.x == 0) {
         publish_head(a, h);
-        DevCur *c = a.cur;
-        c->ticket = 0u;
-        c->jmin32 = ordered_bits(INFINITY);
-        c->jmin64 = ordered_bits((double)INFINITY);
-        c->J_nom = 0.0;
+        a.cur->J_nom = 0.0;
     }
 }
 
@@ -260,21 +256,17 @@ template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_sa
 
 // ---------------------------------------------------------------- rollout
 
-__device__ __forceinline__ void wave_min_atomic(uint32_t v, uint32_t *dst)
+// Smallest finite sample cost of a 64-sample tile (+inf when there is none),
+// stored by lane 0 of the wave that holds the tile's costs.  The weighted
+// average takes J_min as the minimum over tiles: no atomics, nothing to reset.
+template <typename Real> __device__ __forceinline__ void store_tile_min(Real v, bool use, void *tmin, int tile)
 {
+    v = use ? v : Real(INFINITY);
     for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t o = __shfl_xor(v, off, 64);
+        const Real o = __shfl_xor(v, off, 64);
         v = o < v ? o : v;
     }
-    if ((threadIdx.x & 63) == 0) atomicMin(dst, v);
-}
-__device__ __forceinline__ void wave_min_atomic(unsigned long long v, unsigned long long *dst)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(v, off, 64);
-        v = o < v ? o : v;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMin(dst, v);
+    if ((threadIdx.x & 63) == 0) ((Real *)tmin)[tile] = v;
 }
 
 template <typename Real> struct GateRegs {
@@ -467,15 +459,8 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(
         if (nominal) a.cur->J_nom = (double)Jfinal;
         else ((Real *)a.J)[m] = Jfinal;
     }
-    // running minimum over the finite sample costs
-    const bool use = active && !nominal && isfinite(Jfinal);
-    if (sizeof(Real) == 4) {
-        const uint32_t v = use ? ordered_bits((float)Jfinal) : ordered_bits(INFINITY);
-        wave_min_atomic(v, &a.cur->jmin32);
-    } else {
-        const unsigned long long v = use ? ordered_bits((double)Jfinal) : ordered_bits((double)INFINITY);
-        wave_min_atomic(v, &a.cur->jmin64);
-    }
+    // smallest finite sample cost of the tile
+    store_tile_min(Jfinal, active && !nominal && isfinite(Jfinal), a.tmin, blk);
 }
 
 template <int OBJ, typename Real> __global__ __launch_bounds__(64) void k_rollout(KArgs a)
@@ -886,14 +871,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
             if (nominal) a.cur->J_nom = (double)Jfinal;
             else ((Real *)a.J)[m] = Jfinal;
         }
-        const bool use = active && !nominal && isfinite(Jfinal);
-        if (sizeof(Real) == 4) {
-            const uint32_t vb = use ? ordered_bits((float)Jfinal) : ordered_bits(INFINITY);
-            wave_min_atomic(vb, &a.cur->jmin32);
-        } else {
-            const unsigned long long vb = use ? ordered_bits((double)Jfinal) : ordered_bits((double)INFINITY);
-            wave_min_atomic(vb, &a.cur->jmin64);
-        }
+        store_tile_min(Jfinal, active && !nominal && isfinite(Jfinal), a.tmin, blk);
     }
 }
 
@@ -1396,14 +1374,7 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
             if (nominal) a.cur->J_nom = (double)Jfinal;
             else ((Real *)a.J)[m] = Jfinal;
         }
-        const bool use = active && !nominal && isfinite(Jfinal);
-        if (sizeof(Real) == 4) {
-            const uint32_t vb = use ? ordered_bits((float)Jfinal) : ordered_bits(INFINITY);
-            wave_min_atomic(vb, &a.cur->jmin32);
-        } else {
-            const unsigned long long vb = use ? ordered_bits((double)Jfinal) : ordered_bits((double)INFINITY);
-            wave_min_atomic(vb, &a.cur->jmin64);
-        }
+        store_tile_min(Jfinal, active && !nominal && isfinite(Jfinal), a.tmin, blk);
     }
     __syncthreads();
 }
@@ -1416,7 +1387,7 @@ template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 +
     rollout3_body<OBJ, Real, NW>(a, blockIdx.x, h);
 }
 
-// ---------------------------------------------------------------- average
+// ---------------------------------------------------------------- weighted average
 
 template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
 {
@@ -1424,108 +1395,62 @@ template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
     return v;
 }
 
-// Block (mt, k) forms, for sample tile mt of step k,
-//   sum_m w~_m U^m_k  (C channels)   and, for k == 0,  sum_m w~_m, sum_m w~_m^2
-// with w~_m = exp(-(J_m - J_min)/lambda) (0 for non-finite J_m), and stores
-// them as partials.  No block waits for another: the tiles are merged by
-// the tail kernel that follows.
+// Eq. (4)-(5) for step k in one block of kFinalThreads threads:
+//   J_min = min over the tile minima,  w~_m = exp(-(J_m - J_min)/lambda)
+//   (0 for non-finite J_m),  S = sum_m w~_m,  U_k = sum_m w~_m U^m_k / S.
+// Thread t adds the samples t, t + kFinalThreads, ... in that order, the
+// waves are added by a fixed tree and the wave totals in wave order.  S and
+// sum_m w~_m^2 come out of the same loop in every block, bit for bit, so no
+// block waits for another.  The block of step 0 also writes the first input,
+// the report, the nominal's pass mask for the next solve and the warm-start
+// hand-over.  Every load the block needs (tile minima, its first samples,
+// head values) is issued before the first of them is used.
 template <typename Real, typename Acc, bool HAS_V>
-__device__ __forceinline__ void average_body(const KArgs &a, int mt, int k)
+__device__ __forceinline__ void final_body(const KArgs &a, int k)
 {
     constexpr int C = HAS_V ? 5 : 4;
     constexpr int NV = C + 2;
+    constexpr int NT = kFinalThreads, NWV = NT / 64, UR = 4;
     typedef typename Vec4<Real>::T R4;
-    __shared__ Acc s_red[4][NV];
+    __shared__ Real s_min[NWV];
+    __shared__ Acc s_red[NWV][NV];
+    __shared__ Acc s_tot[NV];
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int K = a.K, N = a.N;
-    const int n_mt = a.n_mt;
-    const int m_lo = mt * a.mt_size;
-    const int m_hi = min(K, m_lo + a.mt_size);
-    const Real jmin = sizeof(Real) == 4 ? (Real)from_ordered(a.cur->jmin32)
-                                        : (Real)from_ordered(a.cur->jmin64);
-    const Real inv_lambda = (Real)(1.0 / a.lambda);
     const Real *J = (const Real *)a.J;
     const R4 *ctrl = (const R4 *)a.ctrl + (size_t)k * (size_t)K;
     const Real *vctrl = HAS_V ? (const Real *)a.vctrl + (size_t)k * (size_t)K : nullptr;
-
-    Acc v[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = Acc(0);
-    // four samples per thread and round: their loads are issued together,
-    // then they are accumulated in sample order
-    constexpr int UR = 4;
-    for (int m0 = m_lo + tid; m0 < m_hi; m0 += 256 * UR) {
-        Real Jm[UR], vm[UR];
-        R4 u[UR];
-#pragma unroll
-        for (int i = 0; i < UR; ++i) {
-            const int m = m0 + 256 * i;
-            if (m < m_hi) {
-                Jm[i] = J[m];
-                u[i] = ctrl[m];
-                if (HAS_V) vm[i] = vctrl[m];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < UR; ++i) {
-            if (m0 + 256 * i < m_hi) {
-                const Real wr = isfinite(Jm[i]) ? exp(-(Jm[i] - jmin) * inv_lambda) : Real(0);
-                const Acc w = (Acc)wr;
-                v[0] += w * (Acc)u[i].x;
-                v[1] += w * (Acc)u[i].y;
-                v[2] += w * (Acc)u[i].z;
-                v[3] += w * (Acc)u[i].w;
-                if (HAS_V) v[4] += w * (Acc)vm[i];
-                v[C] += w;
-                v[C + 1] += w * w;
-            }
-        }
-    }
-    const int lane = tid & 63, wv = tid >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const Acc r = wave_sum(v[i]);
-        if (lane == 0) s_red[wv][i] = r;
-    }
-    __syncthreads();
-    Acc *part = (Acc *)a.part;                          // [N][n_mt][C]
-    Acc *part_den = part + (size_t)N * n_mt * C;        // [n_mt][2]
-    if (tid < NV) {
-        const Acc r = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
-        if (tid < C) part[((size_t)k * n_mt + mt) * C + tid] = r;
-        else if (k == 0) part_den[2 * mt + (tid - C)] = r;
-    }
-    __syncthreads();
-}
-
-// One block: adds the tiles of every step in tile order, forms U = sums / S,
-// writes the first input, the report and the warm-start hand-over, and
-// re-arms the running minimum for the next solve.  Every global load (the
-// running minimum, the tile partials, the nominal's front flags, the head
-// values) is issued before the first of them is used, so the block waits on
-// memory about once.
-template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(const KArgs &a)
-{
-    constexpr int C = HAS_V ? 5 : 4;
-    __shared__ Acc s_u[kNMax * C];
-    __shared__ Acc s_den[2];
-    const int tid = threadIdx.x;
-    const int N = a.N, n_mt = a.n_mt;
-    const Acc *part = (const Acc *)a.part;
-    const Acc *part_den = part + (size_t)N * n_mt * C;
+    const Real inv_lambda = (Real)(1.0 / a.lambda);
     DevCur *cur = a.cur;
     DevWarm *w = a.warm;
+    const bool head = k == 0;
     const bool gate = a.objective == OBJ_GATE;
 
-    const double jmin = a.real_bytes == 4 ? (double)from_ordered(cur->jmin32) : from_ordered(cur->jmin64);
-    // front flag of the nominal at step j = tid (and j = 256 for N = 256)
-    const bool fr = gate && tid <= N && a.front8[tid] != 0;
-    const bool fr_last = gate && tid == 0 && N >= 256 && a.front8[256] != 0;
+    // loads: tile minima, the first UR samples of this thread
+    Real mn = Real(INFINITY);
+    for (int t = tid; t < a.n_tiles; t += NT) {
+        const Real v = ((const Real *)a.tmin)[t];
+        mn = v < mn ? v : mn;
+    }
+    Real Jm[UR], vm[UR];
+    R4 u[UR];
+#pragma unroll
+    for (int i = 0; i < UR; ++i) {
+        const int m = tid + NT * i;
+        if (m < K) {
+            Jm[i] = J[m];
+            u[i] = ctrl[m];
+            if (HAS_V) vm[i] = vctrl[m];
+        }
+    }
+    // head values for the report and the hand-over (block of step 0)
+    const bool fr = head && gate && tid <= N && tid < 256 && a.front8[tid] != 0;
+    const bool fr_last = head && gate && tid == 0 && N >= 256 && a.front8[256] != 0;
     double rep_Jnom = 0.0, rep_theta0 = 0.0, rep_t = 0.0, rep_x0[13];
     int32_t rep_g0 = 0, rep_i0 = 0, rep_shift = 0;
     uint32_t rep_s = 0;
-    if (tid == 0) {
+    if (head && tid == 0) {
         rep_Jnom = cur->J_nom;
         rep_theta0 = cur->theta0;
         rep_t = cur->t_now;
@@ -1535,46 +1460,79 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
         rep_s = cur->s;
         for (int i = 0; i < 13; ++i) rep_x0[i] = cur->x0[i];
     }
-    // tile partials: all loads of an output first, then the sum in tile order
-    if (tid < 2) {
-        Acc vals[kMaxTiles];
-#pragma unroll
-        for (int t = 0; t < kMaxTiles; ++t) vals[t] = t < n_mt ? part_den[2 * t + tid] : Acc(0);
-        Acc sden = 0;
-#pragma unroll
-        for (int t = 0; t < kMaxTiles; ++t) sden += vals[t];
-        s_den[tid] = sden;
+    // J_min
+    for (int off = 32; off > 0; off >>= 1) {
+        const Real o = __shfl_xor(mn, off, 64);
+        mn = o < mn ? o : mn;
     }
-    for (int idx = tid; idx < N * C; idx += blockDim.x) {
-        const int k = idx / C, ch = idx % C;
-        Acc vals[kMaxTiles];
+    if (lane == 0) s_min[wv] = mn;
+    __syncthreads();
+    Real jmin = s_min[0];
 #pragma unroll
-        for (int t = 0; t < kMaxTiles; ++t) vals[t] = t < n_mt ? part[((size_t)k * n_mt + t) * C + ch] : Acc(0);
-        Acc sum = 0;
+    for (int i = 1; i < NWV; ++i) jmin = s_min[i] < jmin ? s_min[i] : jmin;
+
+    // weighted sums, UR samples per round in sample order
+    Acc v[NV];
 #pragma unroll
-        for (int t = 0; t < kMaxTiles; ++t) sum += vals[t];
-        s_u[idx] = sum;
+    for (int i = 0; i < NV; ++i) v[i] = Acc(0);
+    for (int m0 = tid; m0 < K; m0 += NT * UR) {
+        if (m0 != tid) {
+#pragma unroll
+            for (int i = 0; i < UR; ++i) {
+                const int m = m0 + NT * i;
+                if (m < K) {
+                    Jm[i] = J[m];
+                    u[i] = ctrl[m];
+                    if (HAS_V) vm[i] = vctrl[m];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < UR; ++i) {
+            if (m0 + NT * i < K) {
+                const Real wr = isfinite(Jm[i]) ? exp(-(Jm[i] - jmin) * inv_lambda) : Real(0);
+                const Acc wa = (Acc)wr;
+                v[0] += wa * (Acc)u[i].x;
+                v[1] += wa * (Acc)u[i].y;
+                v[2] += wa * (Acc)u[i].z;
+                v[3] += wa * (Acc)u[i].w;
+                if (HAS_V) v[4] += wa * (Acc)vm[i];
+                v[C] += wa;
+                v[C + 1] += wa * wa;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const Acc r = wave_sum(v[i]);
+        if (lane == 0) s_red[wv][i] = r;
     }
     __syncthreads();
-    const Acc den = s_den[0], den2 = s_den[1];
-    const bool ok = isfinite(jmin) && den > Acc(0);
-    if (ok) {
-        for (int idx = tid; idx < N * C; idx += blockDim.x) {
-            const int k = idx / C, ch = idx % C;
-            const double u = (double)(s_u[idx] / den);
-            if (ch < 4) a.wU[4 * k + ch] = u;
-            else a.wV[k] = u;
-        }
-        if (!HAS_V)
-            for (int k = tid; k < N; k += blockDim.x) a.wV[k] = 0.0;
+    if (tid < NV) {
+        Acc t = s_red[0][tid];
+#pragma unroll
+        for (int i = 1; i < NWV; ++i) t += s_red[i][tid];
+        s_tot[tid] = t;
     }
-    // pass mask of the next solve: bit j = front flag of the nominal at step
-    // j, gathered by wave ballots (blocks of 256 threads)
+    __syncthreads();
+    const Acc den = s_tot[C], den2 = s_tot[C + 1];
+    const bool ok = isfinite(jmin) && den > Acc(0);
+    if (ok && tid < C) {
+        const double uk = (double)(s_tot[tid] / den);
+        if (tid < 4) a.wU[4 * k + tid] = uk;
+        else a.wV[k] = uk;
+    }
+    if (!HAS_V && ok && tid == 0) a.wV[k] = 0.0;
+    if (!head) return;
+
+    // pass mask of the next solve: bit j = front flag of the nominal at step j
     if (gate) {
-        const unsigned long long bal = __ballot(fr);
-        if ((tid & 63) == 0 && ok) {
-            w->allow[tid >> 5] = (uint32_t)bal;
-            w->allow[(tid >> 5) + 1] = (uint32_t)(bal >> 32);
+        if (tid < 256) {
+            const unsigned long long bal = __ballot(fr);
+            if ((tid & 63) == 0 && ok) {
+                w->allow[tid >> 5] = (uint32_t)bal;
+                w->allow[(tid >> 5) + 1] = (uint32_t)(bal >> 32);
+            }
         }
         if (tid == 0 && ok) w->allow[8] = fr_last ? 1u : 0u;
     } else if (tid < kMaskWords && ok) {
@@ -1583,11 +1541,11 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
     if (tid == 0) {
         DevResult *r = a.res;
         for (int i = 0; i < 4; ++i) {
-            const double u0 = ok ? (double)(s_u[i] / den) : (double)NAN;
+            const double u0 = ok ? (double)(s_tot[i] / den) : (double)NAN;
             r->u0[i] = u0;
             if (a.u0_out) a.u0_out[i] = u0;
         }
-        r->J_min = jmin;
+        r->J_min = (double)jmin;
         r->S = (double)den;
         r->S2 = (double)den2;
         r->ess = ok ? (double)den * (double)den / (double)den2 : 0.0;
@@ -1598,9 +1556,6 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
         r->i0 = rep_i0;
         r->shift = rep_shift;
         r->s = rep_s;
-        // the next solve's rollouts start their running minimum from +inf
-        cur->jmin32 = ordered_bits(INFINITY);
-        cur->jmin64 = ordered_bits((double)INFINITY);
         if (ok) {
             w->warm = 1;
             w->g0 = rep_g0;
@@ -1614,14 +1569,9 @@ template <typename Acc, bool HAS_V> __device__ __forceinline__ void tail_body(co
 }
 
 template <typename Real, typename Acc, bool HAS_V>
-__global__ __launch_bounds__(256) void k_average(KArgs a)
+__global__ __launch_bounds__(kFinalThreads) void k_final(KArgs a)
 {
-    average_body<Real, Acc, HAS_V>(a, blockIdx.x, blockIdx.y);
-}
-
-template <typename Acc, bool HAS_V> __global__ __launch_bounds__(256) void k_tail(KArgs a)
-{
-    tail_body<Acc, HAS_V>(a);
+    final_body<Real, Acc, HAS_V>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- batched (persistent)
@@ -1653,14 +1603,13 @@ __device__ __forceinline__ void stage_args(KArgs &s_a, int &s_ctx, const BArgs &
         s_a.req = it.req;
         s_a.u0_out = it.u0_out;
         if (it.ws) {
-            const WsLayout l = ws_layout(s_a.K, s_a.N, s_a.C, s_a.n_mt, s_a.real_bytes, s_a.acc_bytes);
+            const WsLayout l = ws_layout(s_a.K, s_a.N, s_a.C, s_a.real_bytes);
             s_a.ctrl = it.ws + l.ctrl;
             s_a.vctrl = s_a.C == 5 ? it.ws + l.vctrl : nullptr;
             s_a.nomU = it.ws + l.nomU;
             s_a.nomV = it.ws + l.nomV;
             s_a.J = it.ws + l.J;
-            s_a.part = it.ws + l.part;
-            s_a.tickets = (uint32_t *)(it.ws + l.tickets);
+            s_a.tmin = it.ws + l.tmin;
             s_a.front8 = (uint8_t *)(it.ws + l.front8);
         }
         // a workspace is bound per item: restage the next item in any case
@@ -1728,30 +1677,17 @@ template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 +
     }
 }
 
-template <typename Acc, bool HAS_V> __global__ __launch_bounds__(256) void kb_tail(BArgs b)
+// One unit per (item, step) of the weighted average.
+template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(kFinalThreads) void kb_final(BArgs b)
 {
     __shared__ KArgs s_a;
     __shared__ int s_ctx;
     if (threadIdx.x == 0) s_ctx = -1;
-    const int n = b.desc->n;
-    for (int item = blockIdx.x; item < n; item += gridDim.x) {
-        stage_args(s_a, s_ctx, b, item);
-        tail_body<Acc, HAS_V>(s_a);
-        __syncthreads();
-    }
-}
-
-template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(256) void kb_average(BArgs b)
-{
-    __shared__ KArgs s_a;
-    __shared__ int s_ctx;
-    if (threadIdx.x == 0) s_ctx = -1;
-    const int n = b.desc->n, total = b.desc->n_avg_units;
+    const int n = b.desc->n, total = b.desc->n_steps;
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
-        const int item = find_item(b.avg_prefix, n, u);
+        const int item = find_item(b.step_prefix, n, u);
         stage_args(s_a, s_ctx, b, item);
-        const int local = u - b.avg_prefix[item];
-        average_body<Real, Acc, HAS_V>(s_a, local % s_a.n_mt, local / s_a.n_mt);
+        final_body<Real, Acc, HAS_V>(s_a, u - b.step_prefix[item]);
         __syncthreads();
     }
 }
@@ -1770,13 +1706,10 @@ static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(128), 0, st, b);
     else
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 1>), dim3(L.rollout_groups), dim3(64), 0, st, b);
-    if (L.acc64 || sizeof(Real) == 8) {
-        hipLaunchKernelGGL((kb_average<Real, double, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
-        hipLaunchKernelGGL((kb_tail<double, HAS_V>), dim3(L.tail_groups), dim3(256), 0, st, b);
-    } else {
-        hipLaunchKernelGGL((kb_average<Real, float, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
-        hipLaunchKernelGGL((kb_tail<float, HAS_V>), dim3(L.tail_groups), dim3(256), 0, st, b);
-    }
+    if (L.acc64 || sizeof(Real) == 8)
+        hipLaunchKernelGGL((kb_final<Real, double, HAS_V>), dim3(L.final_groups), dim3(kFinalThreads), 0, st, b);
+    else
+        hipLaunchKernelGGL((kb_final<Real, float, HAS_V>), dim3(L.final_groups), dim3(kFinalThreads), 0, st, b);
     return hipGetLastError();
 }
 
@@ -1815,8 +1748,7 @@ hipError_t launch_setup(const KArgs &a, bool fp64, hipStream_t st)
 template <typename Real, typename Acc, bool HAS_V>
 static hipError_t launch_average_t(const KArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_average<Real, Acc, HAS_V>), dim3(a.n_mt, a.N), dim3(256), 0, st, a);
-    hipLaunchKernelGGL((k_tail<Acc, HAS_V>), dim3(1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_final<Real, Acc, HAS_V>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
     return hipGetLastError();
 }
 

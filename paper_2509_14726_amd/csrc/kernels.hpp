@@ -20,10 +20,10 @@ hipError_t launch_solve(const KArgs &a, bool fp64, bool acc64, hipStream_t st, h
 struct BatchLaunch {
     int objective;
     bool fp64, acc64;
-    int rollout_waves;    // 1 or 2
+    int rollout_waves;    // 1..4 (see mppi_batch_cfg)
     int rollout_groups;   // persistent rollout workgroups
-    int sample_groups;    // grid-stride workgroups of the sample and average kernels
-    int tail_groups;      // workgroups of the merge-and-tail kernel (one item each)
+    int sample_groups;    // grid-stride workgroups of the sample kernel
+    int final_groups;     // grid-stride workgroups of the weighted-average kernel
 };
 
 // Enqueue one batched MPPI step over the items described in device memory.

@@ -169,22 +169,12 @@ static mppi_status validate(const mppi_params *p, const mppi_quad *q, const mppi
     return MPPI_OK;
 }
 
-// Reduction tiling: one step per block, sample tiles of a multiple of 256
-// samples, about two thousand blocks in all (enough loads in flight to
-// stream the sample tensor) and at most kMaxTiles tiles per step.
-static void plan_average(mppi_ctx *c)
+// Rollout tiles of 64 samples (the nominal is sample K) and the layout.
+static void plan_layout(mppi_ctx *c)
 {
     KArgs &a = c->args;
-    const int K = c->K, N = c->N;
-    int n_mt = (2048 + N - 1) / N;
-    if (n_mt > kMaxTiles) n_mt = kMaxTiles;
-    const int max_mt = (K + 255) / 256;
-    if (n_mt > max_mt) n_mt = max_mt;
-    if (n_mt < 1) n_mt = 1;
-    int mt = (K + n_mt - 1) / n_mt;
-    mt = (mt + 255) / 256 * 256;
-    a.mt_size = mt;
-    a.n_mt = (K + mt - 1) / mt;
+    const int K = c->K;
+    a.n_tiles = (K + 1 + 63) / 64;
     // Rollout layout: with fewer 64-sample tiles than SIMDs (1024 on MI355X)
     // the chip is latency bound and splitting each tile's work over several
     // waves (sampling, attitude, translation) shortens each step; with more,
@@ -280,7 +270,7 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.r_dv = p.r_dv; a.mu = p.mu; a.v_max = p.v_max;
     a.path_len = problem->path_len;
     a.ref_dt = problem->ref_dt;
-    plan_average(c);
+    plan_layout(c);
 
     const size_t rs = c->fp64 ? sizeof(double) : sizeof(float);
     const size_t as = c->acc64 ? sizeof(double) : sizeof(float);
@@ -292,7 +282,7 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     void *gates_d = nullptr, *gates_r = nullptr, *path_d = nullptr, *path_r = nullptr, *xref_r = nullptr;
     void *warm = nullptr, *wU = nullptr, *wV = nullptr, *cur = nullptr, *res = nullptr, *req = nullptr;
     void *ws = nullptr;
-    const WsLayout wl = ws_layout(c->K, c->N, c->C, a.n_mt, (int)rs, (int)as);
+    const WsLayout wl = ws_layout(c->K, c->N, c->C, (int)rs);
     c->ws_bytes = wl.total;
     Want wants[] = {
         {&warm, sizeof(DevWarm)}, {&wU, sizeof(double) * kNMax * 4}, {&wV, sizeof(double) * kNMax},
@@ -338,8 +328,7 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
         a.nomU = w + wl.nomU;
         a.nomV = w + wl.nomV;
         a.J = w + wl.J;
-        a.part = w + wl.part;
-        a.tickets = (uint32_t *)(w + wl.tickets);
+        a.tmin = w + wl.tmin;
         a.front8 = (uint8_t *)(w + wl.front8);
     }
     c->warm = (DevWarm *)warm; c->res = (DevResult *)res; c->req = (double *)req;
@@ -361,8 +350,6 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     if (e == hipSuccess) e = hipMemsetAsync(res, 0, sizeof(DevResult), c->stream);
     DevCur c0;
     memset(&c0, 0, sizeof c0);
-    c0.jmin32 = 0xff800000u;                 // ordered bits of +inf (binary32)
-    c0.jmin64 = 0xfff0000000000000ull;       // ordered bits of +inf (binary64)
     if (e == hipSuccess) e = hipMemcpyAsync(cur, &c0, sizeof c0, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_setup(a, c->fp64, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -689,7 +676,8 @@ static void resolve_cfg(mppi_batch *b)
         g.launch.rollout_waves = waves;
         g.launch.rollout_groups = rg;
         g.launch.sample_groups = sg;
-        g.launch.tail_groups = g.cap < 1 ? 1 : (g.cap > 4 * b->n_cu ? 4 * b->n_cu : g.cap);
+        // kFinalThreads-thread workgroups, two per CU
+        g.launch.final_groups = 2 * b->n_cu;
     }
 }
 
@@ -793,7 +781,7 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
         g.bargs.items = (const BatchItem *)(d + o_items);
         g.bargs.sample_prefix = (const int32_t *)(d + o_sp);
         g.bargs.tile_prefix = (const int32_t *)(d + o_tp);
-        g.bargs.avg_prefix = (const int32_t *)(d + o_ap);
+        g.bargs.step_prefix = (const int32_t *)(d + o_ap);
     }
     resolve_cfg(b);
     *out = b;
@@ -872,7 +860,7 @@ static mppi_status batch_solve(mppi_batch *b, const int32_t *active, int32_t n_a
         BatchItem *items = (BatchItem *)(h + ((const char *)g.bargs.items - d));
         int32_t *sp = (int32_t *)(h + ((const char *)g.bargs.sample_prefix - d));
         int32_t *tp = (int32_t *)(h + ((const char *)g.bargs.tile_prefix - d));
-        int32_t *ap = (int32_t *)(h + ((const char *)g.bargs.avg_prefix - d));
+        int32_t *ap = (int32_t *)(h + ((const char *)g.bargs.step_prefix - d));
         int64_t s_units = 0, t_units = 0, a_units = 0;
         sp[0] = tp[0] = ap[0] = 0;
         for (size_t j = 0; j < lst.size(); ++j) {
@@ -884,7 +872,7 @@ static mppi_status batch_solve(mppi_batch *b, const int32_t *active, int32_t n_a
             items[j].ws = ws ? ws[lst[j].second] : nullptr;
             s_units += (int64_t)((c->K + 1 + 255) / 256) * c->N;
             t_units += (c->K + 1 + 63) / 64;
-            a_units += (int64_t)c->args.n_mt * c->N;
+            a_units += c->N;
             if (s_units > INT32_MAX || a_units > INT32_MAX) return bfail(b, MPPI_E_INVAL, "batch too large");
             sp[j + 1] = (int32_t)s_units;
             tp[j + 1] = (int32_t)t_units;
@@ -893,7 +881,7 @@ static mppi_status batch_solve(mppi_batch *b, const int32_t *active, int32_t n_a
         desc->n = (int32_t)lst.size();
         desc->n_sample_units = (int32_t)s_units;
         desc->n_tiles = (int32_t)t_units;
-        desc->n_avg_units = (int32_t)a_units;
+        desc->n_steps = (int32_t)a_units;
         desc->queue = 0u;
         g.active = (int)lst.size();
         BHIP_TRY(b, hipMemcpyAsync(g.d_block, g.h_block, g.bytes, hipMemcpyHostToDevice, b->stream));
