@@ -28,6 +28,37 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_ROLLOUT_STEP = 495
 # Peak FP32 vector throughput of MI355X (256 CUs, 2.4 GHz, packed FMA)
 PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBPS = 8000.0
+
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a run
+# of its own, WRITE_SIZE (KiB per dispatch, mean of 12 dispatches of the
+# benchmark workload), scaled by what the same counters read for a plain
+# 256 MiB device copy (FETCH_SIZE 131085.1 KiB -> x 2.0, WRITE_SIZE
+# 262144.0 KiB -> x 1.0); see profiles/k_rollout3_gate_k8192_n100_traffic.md.
+# They hold only for the device sources they were taken on (sha256 of
+# kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order); for any
+# other source the traffic is reported as null.
+TRAFFIC_SOURCES = "7b83c08d6f375d8a9316990d1ff22f5555b8cc45ec7686485b5076ee75e778d0"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.1, 262144.0 / 262144.0
+TRAFFIC_KIB = {"k_rollout3": (389.7, 12836.5), "k_final": (6578.5, 6.6)}
+
+
+def device_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.hpp", "rollout.hpp", "noise.hpp"):
+        with open(os.path.join(ROOT, "paper_2509_14726_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel: str):
+    """Measured HBM bytes per launch of a kernel (fetch + write), or None when
+    the device sources differ from the ones the counters were taken on."""
+    if device_sources_hash() != TRAFFIC_SOURCES:
+        return None
+    f, w = TRAFFIC_KIB[kernel]
+    return (f * FETCH_SCALE + w * WRITE_SCALE) * 1024.0
 
 
 def cpu_baseline(w, seconds: float = 12.0):
@@ -89,6 +120,74 @@ def batched_bench(steps: int = 20, n: int = 256):
             "graph": True, "precision": "fp32"}
 
 
+def closed_loop_race(steps: int = 1000):
+    """The closed-loop race workload: K = 8192, N = 100, dt = 0.02 on the
+    seeded 7-gate track, 1000 control steps with warm-started controls for
+    each objective (gate progress; contouring on the 2000-point arc-length
+    path; tracking of the 5 m/s reference).  Between solves the FP64 host
+    plant (RK4, 4 substeps) advances with the first input of each solve, so
+    every solve goes through the host entry point (upload, solve, download).
+    Reports the host-observed solve latency and what the flight achieved.
+
+    The race samples with sigma = 0.15 N and lambda = 10: with thrust as the
+    sampled input, i.i.d. noise of 1 N per rotor and 20 ms step spins this
+    airframe (J = 1e-3 kg m^2) past the 10 rad/s rate limit within a few
+    steps in nearly every sample, the rate term then dominates every cost
+    and the loop tumbles; the single-solve workload keeps sigma = 1 N."""
+    import numpy as np
+    from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import synth
+    out = {}
+    for obj in ("gate", "contour", "track"):
+        w = synth.single_solve_workload(K=8192, N=100, objective=obj, seed=1, sigma=(0.15,) * 4,
+                                        **{"lambda": 10.0})
+        sv = M.Solver(w["quad"], w["params"], gates=w["gates"], path=w.get("path"),
+                      path_len=w.get("path_len", 0.0), xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0),
+                      precision=M.FP32)
+        dt = w["params"]["dt"]
+        x = w["x0"].copy()
+        lat, gates, theta_adv, err = [], 0, 0.0, []
+        g_prev, th_prev = None, None
+        status = "ok"
+        try:
+            for i in range(steps):
+                t0 = time.perf_counter()
+                u0, _, info = sv.solve(x, i * dt)
+                lat.append(time.perf_counter() - t0)
+                if obj == "gate":
+                    if g_prev is not None and info["g0"] != g_prev:
+                        gates += 1
+                    g_prev = info["g0"]
+                if obj == "contour":
+                    th = info["theta0"]
+                    if th_prev is not None:
+                        d = th - th_prev
+                        if d < -0.5 * w["path_len"]:
+                            d += w["path_len"]
+                        theta_adv += d
+                    th_prev = th
+                if obj == "track":
+                    r = min(int(round(i * dt / w["ref_dt"])), len(w["xref"]) - 1)
+                    err.append(float(np.linalg.norm(x[:3] - w["xref"][r, :3])))
+                x = M.plant_step(w["quad"], x, u0, dt, 4)
+        except M.MppiError as e:
+            status = f"stopped at step {len(lat)}: {e}"
+        sv.close()
+        lat = np.array(lat)
+        rec = {"steps": int(lat.size), "status": status, "sigma_N": 0.15, "lambda": 10.0,
+               "solve_ms_mean": float(lat.mean() * 1e3),
+               "solve_ms_p99": float(np.percentile(lat, 99) * 1e3),
+               "rollout_steps_per_s": 8192 * 100 / float(lat.mean())}
+        if obj == "gate":
+            rec["gates_passed"] = gates
+        if obj == "contour":
+            rec["arc_length_m"] = theta_adv
+        if obj == "track":
+            rec["pos_err_m_mean"] = float(np.mean(err)) if err else None
+        out[obj] = rec
+    return out
+
+
 def large_bench(steps: int = 5):
     """K = 262144, N = 200, dt = 0.01 on a 12-gate track: the N x K x 4 sample
     tensor (839 MB) streams through HBM; the final average accumulates in
@@ -134,7 +233,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, large-solve and serving measurements")
-    ap.add_argument("--serving-seconds", type=float, default=10.0)
+    ap.add_argument("--serving-seconds", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -191,6 +290,10 @@ def main():
     ms_per_step = ms_total / args.steps
     value = K * N / (ms_per_step * 1e-3)
     roll_ms = float(kern_ms[1])
+    avg_ms = float(kern_ms[2])
+    # algorithmic bytes of the weighted average: the sample tensor and the
+    # costs (read once per step block), the tile minima
+    avg_bytes = K * N * 16 + K * 4 * N + ((K + 64) // 64) * 4 * N
     flops = FLOPS_PER_ROLLOUT_STEP * K * N
     achieved = flops / (roll_ms * 1e-3) / 1e12
     out = {
@@ -212,12 +315,17 @@ def main():
         "kernels_ms": {"sample": float(kern_ms[0]), "rollout": roll_ms, "average": float(kern_ms[2]),
                        "solves_timed": n_prof},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_rollout", "flops_per_launch": flops},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes("k_rollout3"),
+                     "kernel": "k_rollout3", "flops_per_launch": flops},
+        # the weighted average streams the sample tensor once: HBM-bound
+        "average_kernel": {"bound": "hbm", "kernel": "k_final", "bytes_per_launch": avg_bytes,
+                           "achieved": avg_bytes / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
+                           "unit": "GB/s", "frac": avg_bytes / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+                           "traffic": traffic_bytes("k_final")},
     }
     solver.close()
     if not args.no_extras:
-        for name, fn in (("batched", batched_bench), ("large", large_bench)):
+        for name, fn in (("batched", batched_bench), ("large", large_bench), ("closed_loop", closed_loop_race)):
             try:
                 out[name] = fn()
             except Exception as e:  # reported, never silently dropped

@@ -381,7 +381,10 @@ mppi_status mppi_set_profiling(mppi_ctx *ctx, int32_t enable)
     if (!ctx) return fail(nullptr, MPPI_E_INVAL, "ctx is NULL");
     if (enable && ctx->events.empty()) {
         ctx->events.resize(4 * (size_t)kProfSlots, nullptr);
-        for (auto &e : ctx->events) HIP_TRY(ctx, hipEventCreate(&e));
+        // timing-only events: no system-scope fence (cache write-back) when
+        // they are recorded, so they do not stretch the kernels they bracket;
+        // mppi_read_profile synchronizes the stream before reading them
+        for (auto &e : ctx->events) HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     ctx->profiling = enable != 0;
     ctx->prof_count = 0;

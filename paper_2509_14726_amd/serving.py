@@ -5,8 +5,12 @@ batches them as launch slots and device memory free up.
 Each drone has its own seeded track, K in {2048, 8192}, N in {50, 100} and a
 gate-progress or contouring objective (50/50), fixed for the drone (its warm
 start needs a stable shape).  Between two of its requests a drone's FP64 host
-plant advances with the last control it received.  Arrivals are paced in wall
-clock; latency = time the result is retired - arrival time.
+plant advances with the last control it received (RK4, substeps of at most
+5 ms).  A drone whose state leaves a sane envelope (non-finite, more than
+1 km from the origin, or spinning faster than 1000 rad/s) is counted as a
+crash and respawned at its start (its solver keeps the warm state and
+re-converges from it).  Arrivals are paced
+in wall clock; latency = time the result is retired - arrival time.
 """
 from __future__ import annotations
 
@@ -46,6 +50,15 @@ def arrivals(n_drones: int, seconds: float, rate_hz: float, seed: int = 4):
     return t[o], i[o]
 
 
+def _plant(quad, x, u, elapsed):
+    n = max(2, int(np.ceil(elapsed / 0.005)))
+    return M.plant_step(quad, x, u, elapsed, n)
+
+
+def _sane(x) -> bool:
+    return bool(np.all(np.isfinite(x)) and np.linalg.norm(x[0:3]) < 1e3 and np.linalg.norm(x[10:13]) < 1e3)
+
+
 def simulate(n_drones: int = 512, seconds: float = 60.0, rate_hz: float = 50.0,
              budget_bytes: float = 32 * 2 ** 30, n_slots: int = 4, max_batch: int = 0,
              precision: int = M.FP32, seed: int = 4, log=None):
@@ -57,6 +70,7 @@ def simulate(n_drones: int = 512, seconds: float = 60.0, rate_hz: float = 50.0,
     x = [w["x0"].copy() for w in ws]
     u = [np.full(4, synth.hover_thrust(w["quad"])) for w in ws]
     t_state = np.zeros(n_drones)
+    crashes = 0
     lat = []
     steps = 0.0
     idx, n_total = 0, t_arr.size
@@ -68,8 +82,12 @@ def simulate(n_drones: int = 512, seconds: float = 60.0, rate_hz: float = 50.0,
             d = int(d_arr[idx])
             ta = float(t_arr[idx])
             if ta > t_state[d]:
-                x[d] = M.plant_step(ws[d]["quad"], x[d], u[d], ta - t_state[d], 2)
+                x[d] = _plant(ws[d]["quad"], x[d], u[d], ta - t_state[d])
                 t_state[d] = ta
+            if not _sane(x[d]):
+                crashes += 1
+                x[d] = ws[d]["x0"].copy()
+                u[d] = np.full(4, synth.hover_thrust(ws[d]["quad"]))
             server.submit(d, x[d], ta, ta)
             idx += 1
         server.progress(now)
@@ -101,5 +119,5 @@ def simulate(n_drones: int = 512, seconds: float = 60.0, rate_hz: float = 50.0,
         "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
         "mean_batch": st["completed"] / max(st["launches"], 1),
         "peak_bytes_in_flight": st["peak_bytes_in_flight"], "budget_bytes": budget_bytes,
-        "n_slots": n_slots, "max_batch": max_batch,
+        "n_slots": n_slots, "max_batch": max_batch, "crashes": crashes,
     }
