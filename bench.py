@@ -41,6 +41,16 @@ PEAK_HBM_GBPS = 8000.0
 TRAFFIC_SOURCES = "7b83c08d6f375d8a9316990d1ff22f5555b8cc45ec7686485b5076ee75e778d0"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.1, 262144.0 / 262144.0
 TRAFFIC_KIB = {"k_rollout3": (389.7, 12836.5), "k_final": (6578.5, 6.6)}
+ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
+
+
+def rollout_kernel(K: int) -> str:
+    """The rollout kernel the library launches for K samples (its layout rule,
+    or the MPPI_ROLLOUT_WAVES override)."""
+    tiles = (K + 1 + 63) // 64
+    env = os.environ.get("MPPI_ROLLOUT_WAVES", "")
+    waves = int(env) if env in ("1", "2", "3", "4") else (4 if tiles < 1024 else 1)
+    return ROLLOUT_KERNELS[waves]
 
 
 def device_sources_hash() -> str:
@@ -55,7 +65,7 @@ def device_sources_hash() -> str:
 def traffic_bytes(kernel: str):
     """Measured HBM bytes per launch of a kernel (fetch + write), or None when
     the device sources differ from the ones the counters were taken on."""
-    if device_sources_hash() != TRAFFIC_SOURCES:
+    if device_sources_hash() != TRAFFIC_SOURCES or kernel not in TRAFFIC_KIB:
         return None
     f, w = TRAFFIC_KIB[kernel]
     return (f * FETCH_SCALE + w * WRITE_SCALE) * 1024.0
@@ -315,8 +325,8 @@ def main():
         "kernels_ms": {"sample": float(kern_ms[0]), "rollout": roll_ms, "average": float(kern_ms[2]),
                        "solves_timed": n_prof},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes("k_rollout3"),
-                     "kernel": "k_rollout3", "flops_per_launch": flops},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(rollout_kernel(K)),
+                     "kernel": rollout_kernel(K), "flops_per_launch": flops},
         # the weighted average streams the sample tensor once: HBM-bound
         "average_kernel": {"bound": "hbm", "kernel": "k_final", "bytes_per_launch": avg_bytes,
                            "achieved": avg_bytes / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,

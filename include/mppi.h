@@ -227,9 +227,11 @@ typedef struct mppi_batch mppi_batch;
 typedef struct {
     int32_t rollout_waves;     /* waves per 64-sample tile: 1 (separate sampling
                                   kernel), 2 (attitude / translation split), 3
-                                  (sampling joins the rollout) or 4 (sampling
-                                  shared by two waves); 0: automatic (3 when the
-                                  batch has fewer tiles than four per CU, else 1) */
+                                  (sampling joins the rollout) or 4 (four-stage
+                                  pipeline: sampling with body rates, attitude,
+                                  translation, sampling with position costs);
+                                  0: automatic (4 when the batch has fewer tiles
+                                  than four per CU, else 1) */
     int32_t rollout_groups;    /* persistent rollout workgroups; 0: automatic    */
     int32_t sample_groups;     /* workgroups of the sample and reduction kernels;
                                   0: automatic                                   */

@@ -1379,6 +1379,601 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     __syncthreads();
 }
 
+// ---------------------------------------------------------------- rollout, four-wave pipeline
+
+// The step of Eq. (2) split into four pipeline stages over four waves (one
+// per SIMD), a 64-sample tile per workgroup, chunks of B steps between
+// workgroup barriers.  At chunk iteration c:
+//   wave 0  draws the noise of the even steps of chunk c (Eq. (3)) and
+//           integrates the body rates over chunk c-1 (they depend on the
+//           torques only), with the rate-limit and body-rate cost terms;
+//   wave 3  draws the noise of the odd steps of chunk c and adds the
+//           position cost terms of chunk c-4 (gate progress, near-gate
+//           term, crossing and switch; contouring) and the input-rate terms;
+//   wave 1  integrates the attitude over chunk c-2 from the stage body rates;
+//   wave 2  integrates position and velocity over chunk c-3 from the stage
+//           attitudes, with the tracking terms of position and velocity.
+// Each stage hands its stage values on through LDS rings; every quantity is
+// computed with the same operations as in the three-wave layout.
+template <typename Real> struct Ring4;
+template <> struct Ring4<float> { static constexpr int B = 4; };
+template <> struct Ring4<double> { static constexpr int B = 2; };
+
+template <int OBJ, typename Real>
+__device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const HeadVals &h)
+{
+    typedef typename Vec4<Real>::T R4;
+    constexpr int B = Ring4<Real>::B;
+    constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
+    constexpr bool RATE = OBJ != OBJ_GATE;
+    constexpr bool POS = OBJ != OBJ_TRACK;        // position costs in wave 3
+    __shared__ R4 s_in[4][B][64];                  // (F/m, tau_x/J_x, tau_y/J_y, tau_z/J_z), chunk c at c % 4
+    __shared__ R4 s_w[2][B][4][64];                // stage body rates, chunk c at c % 2
+    __shared__ R4 s_q[2][B][4][64];                // stage quaternions, chunk c at c % 2
+    __shared__ R4 s_p[POS ? 2 : 1][B][3][64];      // p_k hi, p_k lo, increment; chunk c at c % 2
+    __shared__ R4 s_u[RATE ? 5 : 1][B][64];        // clipped inputs, chunk c at c % 5
+    __shared__ Real s_v[HAS_V ? 5 : 1][B][64];     // progress speed, chunk c at c % 5
+    __shared__ R4 s_us[kNMax];                     // shifted warm-start thrusts per step
+    __shared__ Real s_vs[HAS_V ? kNMax : 1];       // shifted warm-start progress speed
+    __shared__ Real s_jp[3][64];                   // partial costs of waves 0, 1, 2
+    __shared__ R4 s_pN[2][64];                     // p_N hi and lo (front flag of the nominal)
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = blk * 64 + lane;
+    const int K = a.K, N = a.N;
+    const bool active = m <= K;
+    const bool nominal = m == K;
+    const bool sampled = m < K;
+    const Model<Real> M(a);
+    const Real dt = (Real)a.dt;
+    const Real h2 = Real(0.5) * dt;
+    const Real dt6 = dt / Real(6);
+    const Real h4 = Real(0.5) * h2, dt12 = Real(0.5) * dt6;
+    const Real w_max = (Real)a.w_max, w_lim = (Real)a.w_lim;
+    const Real *xref = (const Real *)a.xref_r;
+    const int i0 = h.i0;
+    Real rdt[4];
+    for (int i = 0; i < 4; ++i) rdt[i] = (Real)(a.R_dT[i] / (a.dt * a.dt));
+    const Real r_dv = (Real)(a.r_dv / (a.dt * a.dt));
+
+    KSum<Real> J;
+    Real up[4], vp = (Real)h.v_prev;
+    for (int i = 0; i < 4; ++i) up[i] = (Real)h.u_prev[i];
+    Real q[4], ql[4], w[3], wl[3], p[3], pl[3], v[3], vl[3];
+    for (int i = 0; i < 4; ++i) {
+        q[i] = (Real)h.x0[6 + i];
+        ql[i] = sizeof(Real) == 4 ? (Real)(h.x0[6 + i] - (double)q[i]) : Real(0);
+    }
+    for (int i = 0; i < 3; ++i) {
+        w[i] = (Real)h.x0[10 + i];
+        wl[i] = sizeof(Real) == 4 ? (Real)(h.x0[10 + i] - (double)w[i]) : Real(0);
+        p[i] = (Real)h.x0[i];
+        pl[i] = sizeof(Real) == 4 ? (Real)(h.x0[i] - (double)p[i]) : Real(0);
+        v[i] = (Real)h.x0[3 + i];
+        vl[i] = sizeof(Real) == 4 ? (Real)(h.x0[3 + i] - (double)v[i]) : Real(0);
+    }
+    GateRegs<Real> gt, g0r;
+    int g = 0, passes = 0;
+    const Real *gtab = (const Real *)a.gates_r;
+    const Real *path = (const Real *)a.path_r;
+    Real th_hi = 0, th_lo = 0, ds = 0, inv_ds = 0, L = 0;
+    if (OBJ == OBJ_GATE) {
+        g = h.g0;
+        gt.load(gtab, g);
+        g0r = gt;
+    }
+    if (OBJ == OBJ_CONTOUR) {
+        th_hi = (Real)h.theta0;
+        if (sizeof(Real) == 4) th_lo = (Real)(h.theta0 - (double)th_hi);
+        L = (Real)a.path_len;
+        ds = (Real)(a.path_len / (double)a.P);
+        inv_ds = (Real)((double)a.P / a.path_len);
+    }
+    const Real q_near = (Real)a.q_near, r_near2 = (Real)(a.r_near * a.r_near), half = (Real)a.gate_half;
+    const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max, vmax = (Real)a.v_max;
+    const Real sig0 = (Real)a.sigma[0], sig1 = (Real)a.sigma[1], sig2 = (Real)a.sigma[2], sig3 = (Real)a.sigma[3];
+    const Real sigv = (Real)a.sigma_v, hover = (Real)a.hover;
+    typedef typename Vec4<Real>::T R4g;
+    R4g *ctrl = (R4g *)a.ctrl;
+    Real *vctrl = (Real *)a.vctrl;
+
+    // the shifted warm start of every step, staged once
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        int src = k + h.shift;
+        if (src > N - 1) src = N - 1;
+        R4 o;
+        o.x = h.warm ? (Real)a.wU[4 * src + 0] : hover;
+        o.y = h.warm ? (Real)a.wU[4 * src + 1] : hover;
+        o.z = h.warm ? (Real)a.wU[4 * src + 2] : hover;
+        o.w = h.warm ? (Real)a.wU[4 * src + 3] : hover;
+        s_us[k] = o;
+        if (HAS_V) s_vs[k] = h.warm ? (Real)a.wV[src] : Real(0);
+    }
+    __syncthreads();
+
+    const int nch = (N + B - 1) / B;
+    for (int c = 0; c <= nch + 3; ++c) {
+        if ((wave == 0 || wave == 3) && c < nch) {
+            // noise, clipped inputs and the per-step thrust and torques
+            const int kb = c * B, ke = min(N, kb + B);
+            const int k_first = wave == 3 ? 1 : 0;
+            auto noise_step = [&](const int k, const int j) {
+                const R4 w4 = s_us[k];
+                const Real us[4] = {w4.x, w4.y, w4.z, w4.w};
+                const Real vs = HAS_V ? s_vs[k] : Real(0);
+                R4 u;
+                Real V = Real(0);
+                if (sampled) {
+                    const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, h.s, 0u, a.seed_lo, a.seed_hi);
+                    u.x = clampT(us[0] + sig0 * z.z0, tmin, tmax);
+                    u.y = clampT(us[1] + sig1 * z.z1, tmin, tmax);
+                    u.z = clampT(us[2] + sig2 * z.z2, tmin, tmax);
+                    u.w = clampT(us[3] + sig3 * z.z3, tmin, tmax);
+                    const size_t idx = (size_t)k * (size_t)K + (size_t)m;
+                    ctrl[idx] = u;
+                    if (HAS_V) {
+                        const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, h.s, 1u, a.seed_lo, a.seed_hi);
+                        V = clampT(vs + sigv * zv, Real(0), vmax);
+                        vctrl[idx] = V;
+                    }
+                } else {  // the noise-free nominal (and idle lanes past it)
+                    u.x = clampT(us[0], tmin, tmax);
+                    u.y = clampT(us[1], tmin, tmax);
+                    u.z = clampT(us[2], tmin, tmax);
+                    u.w = clampT(us[3], tmin, tmax);
+                    if (HAS_V) V = clampT(vs, Real(0), vmax);
+                }
+                if (HAS_V) s_v[c % 5][j][lane] = V;
+                if (RATE) s_u[c % 5][j][lane] = u;
+                const StepInput<Real> in = step_input(M, u.x, u.y, u.z, u.w);
+                R4 o;
+                o.x = in.fm; o.y = in.tx; o.z = in.ty; o.w = in.tz;
+                s_in[c % 4][j][lane] = o;
+            };
+            if (ke - kb == B) {
+#pragma unroll
+                for (int j = k_first; j < B; j += 2) noise_step(kb + j, j);
+            } else {
+                for (int k = kb + k_first; k < ke; k += 2) noise_step(k, k - kb);
+            }
+        }
+        if (wave == 0 && c >= 1 && c <= nch) {
+            // body rates over chunk c - 1
+            const int kb = (c - 1) * B, ke = min(N, kb + B);
+            auto omega_step = [&](const int k, const int j, const R4 in) {
+                R4 (*slot)[64] = s_w[(c - 1) & 1][j];
+                Real term = Real(0);
+                if (OBJ == OBJ_TRACK) {
+                    int r = i0 + k;
+                    if (r > a.R - 1) r = a.R - 1;
+                    const Real *xr = xref + 16 * r;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (w[i] - xr[10 + i]) + wl[i];
+                        term += (Real)a.Q[10 + i] * e * e;
+                    }
+                }
+                if (OBJ == OBJ_CONTOUR)
+                    term += (Real)a.Q_w[0] * w[0] * w[0] + (Real)a.Q_w[1] * w[1] * w[1] +
+                            (Real)a.Q_w[2] * w[2] * w[2];
+                Real ws[3], kw[3], dw[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) ws[i] = w[i];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    R4 o;
+                    o.x = ws[0]; o.y = ws[1]; o.z = ws[2]; o.w = Real(0);
+                    slot[st][lane] = o;
+                    kw[0] = in.y - M.gx * ws[1] * ws[2];
+                    kw[1] = in.z - M.gy * ws[2] * ws[0];
+                    kw[2] = in.w - M.gz * ws[0] * ws[1];
+                    if (st == 0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] = kw[i];
+                    } else if (st < 3) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] += Real(2) * kw[i];
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) dw[i] = dt6 * (dw[i] + kw[i]);
+                    }
+                    if (st < 3) {
+                        const Real hh = st < 2 ? h2 : dt;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) ws[i] = w[i] + hh * kw[i];
+                    }
+                }
+                if (sizeof(Real) == 4) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real y = dw[i] + wl[i];
+                        const Real t = w[i] + y;
+                        wl[i] = y - (t - w[i]);
+                        w[i] = t;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) w[i] += dw[i];
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const Real e = fmax(fabs(w[i]) - w_max, Real(0));
+                    term += w_lim * e * e;
+                }
+                J.add(term);
+            };
+            // the chunk's LDS inputs are loaded before the first step uses them
+            if (ke - kb == B) {
+                R4 inp[B];
+#pragma unroll
+                for (int j = 0; j < B; ++j) inp[j] = s_in[(c - 1) % 4][j][lane];
+#pragma unroll
+                for (int j = 0; j < B; ++j) omega_step(kb + j, j, inp[j]);
+            } else {
+                for (int k = kb; k < ke; ++k) omega_step(k, k - kb, s_in[(c - 1) % 4][k - kb][lane]);
+            }
+        } else if (wave == 1 && c >= 2 && c <= nch + 1) {
+            // attitude over chunk c - 2
+            const int kb = (c - 2) * B, ke = min(N, kb + B);
+            auto quat_step = [&](const int k, const int j, const R4 *wst) {
+                R4 (*slot)[64] = s_q[(c - 2) & 1][j];
+                if (OBJ == OBJ_TRACK) {
+                    int r = i0 + k;
+                    if (r > a.R - 1) r = a.R - 1;
+                    const Real *xr = xref + 16 * r;
+                    Real term = Real(0);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real e = (q[i] - xr[6 + i]) + ql[i];
+                        term += (Real)a.Q[6 + i] * e * e;
+                    }
+                    J.add(term);
+                }
+                Real qs[4], kq[4], dq[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) qs[i] = q[i];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const R4 ws = wst[st];
+                    R4 o;
+                    o.x = qs[0]; o.y = qs[1]; o.z = qs[2]; o.w = qs[3];
+                    slot[st][lane] = o;
+                    // kq is twice the quaternion rate; the factor 1/2 is
+                    // carried by the step sizes (exact: a power of two)
+                    kq[0] = -qs[1] * ws.x - qs[2] * ws.y - qs[3] * ws.z;
+                    kq[1] = qs[0] * ws.x + qs[2] * ws.z - qs[3] * ws.y;
+                    kq[2] = qs[0] * ws.y - qs[1] * ws.z + qs[3] * ws.x;
+                    kq[3] = qs[0] * ws.z + qs[1] * ws.y - qs[2] * ws.x;
+                    if (st == 0) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] = kq[i];
+                    } else if (st < 3) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] += Real(2) * kq[i];
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dq[i] = dt12 * (dq[i] + kq[i]);
+                    }
+                    if (st < 3) {
+                        const Real hq = st < 2 ? h4 : h2;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) qs[i] = q[i] + hq * kq[i];
+                    }
+                }
+                if (sizeof(Real) == 4) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real y = dq[i] + ql[i];
+                        const Real t = q[i] + y;
+                        ql[i] = y - (t - q[i]);
+                        q[i] = t;
+                    }
+                    const Real n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+                    const Real r = inv_sqrt(n2);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Real ph = q[i] * r;
+                        const Real pl2 = fma(q[i], r, -ph) + ql[i] * r;
+                        const Real hs = ph + pl2;
+                        ql[i] = pl2 - (hs - ph);
+                        q[i] = hs;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) q[i] += dq[i];
+                    const Real nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) q[i] /= nq;
+                }
+            };
+            if (ke - kb == B) {
+                R4 wpre[B][4];
+#pragma unroll
+                for (int j = 0; j < B; ++j)
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) wpre[j][st] = s_w[(c - 2) & 1][j][st][lane];
+#pragma unroll
+                for (int j = 0; j < B; ++j) quat_step(kb + j, j, wpre[j]);
+            } else {
+                for (int k = kb; k < ke; ++k) {
+                    R4 wst[4];
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) wst[st] = s_w[(c - 2) & 1][k - kb][st][lane];
+                    quat_step(k, k - kb, wst);
+                }
+            }
+        } else if (wave == 2 && c >= 3 && c <= nch + 2) {
+            // position and velocity over chunk c - 3
+            const int kb = (c - 3) * B, ke = min(N, kb + B);
+            auto trans_step = [&](const int k, const int j, const Real fm, const R4 *qstage) {
+                if (OBJ == OBJ_TRACK) {
+                    int r = i0 + k;
+                    if (r > a.R - 1) r = a.R - 1;
+                    const Real *xr = xref + 16 * r;
+                    Real term = Real(0);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (p[i] - xr[i]) + pl[i];
+                        term += (Real)a.Q[i] * e * e;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const Real e = (v[i] - xr[3 + i]) + vl[i];
+                        term += (Real)a.Q[3 + i] * e * e;
+                    }
+                    J.add(term);
+                }
+                Real vs[3], kv[3], dpv[3], dvv[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) vs[i] = v[i];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const R4 qq = qstage[st];
+                    const Real r3x = Real(2) * (qq.y * qq.w + qq.x * qq.z);
+                    const Real r3y = Real(2) * (qq.z * qq.w - qq.x * qq.y);
+                    const Real r3z = Real(1) - Real(2) * (qq.y * qq.y + qq.z * qq.z);
+                    kv[0] = fm * r3x;
+                    kv[1] = fm * r3y;
+                    kv[2] = fm * r3z - M.g;
+                    if (M.drag) {
+                        const Real qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
+                        const Real r11 = Real(1) - Real(2) * (qy * qy + qz * qz), r12 = Real(2) * (qx * qy - qw * qz);
+                        const Real r21 = Real(2) * (qx * qy + qw * qz), r22 = Real(1) - Real(2) * (qx * qx + qz * qz);
+                        const Real r31 = Real(2) * (qx * qz - qw * qy), r32 = Real(2) * (qy * qz + qw * qx);
+                        const Real b0 = M.d0 * (r11 * vs[0] + r21 * vs[1] + r31 * vs[2]);
+                        const Real b1 = M.d1 * (r12 * vs[0] + r22 * vs[1] + r32 * vs[2]);
+                        const Real b2 = M.d2 * (r3x * vs[0] + r3y * vs[1] + r3z * vs[2]);
+                        kv[0] -= r11 * b0 + r12 * b1 + r3x * b2;
+                        kv[1] -= r21 * b0 + r22 * b1 + r3y * b2;
+                        kv[2] -= r31 * b0 + r32 * b1 + r3z * b2;
+                    }
+                    if (st == 0) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] = vs[i]; dvv[i] = kv[i]; }
+                    } else if (st < 3) {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] += Real(2) * vs[i]; dvv[i] += Real(2) * kv[i]; }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) { dpv[i] = dt6 * (dpv[i] + vs[i]); dvv[i] = dt6 * (dvv[i] + kv[i]); }
+                    }
+                    if (st < 3) {
+                        const Real hh = st < 2 ? h2 : dt;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) vs[i] = v[i] + hh * kv[i];
+                    }
+                }
+                if (POS) {
+                    R4 (*ps)[64] = s_p[(c - 3) & 1][j];
+                    R4 o;
+                    o.x = p[0]; o.y = p[1]; o.z = p[2]; o.w = Real(0);
+                    ps[0][lane] = o;
+                    o.x = pl[0]; o.y = pl[1]; o.z = pl[2];
+                    ps[1][lane] = o;
+                    o.x = dpv[0]; o.y = dpv[1]; o.z = dpv[2];
+                    ps[2][lane] = o;
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (sizeof(Real) == 4) {
+                        Real y = dpv[i] + pl[i];
+                        Real t = p[i] + y;
+                        pl[i] = y - (t - p[i]);
+                        p[i] = t;
+                        y = dvv[i] + vl[i];
+                        t = v[i] + y;
+                        vl[i] = y - (t - v[i]);
+                        v[i] = t;
+                    } else {
+                        p[i] += dpv[i];
+                        v[i] += dvv[i];
+                    }
+                }
+            };
+            if (ke - kb == B) {
+                Real fpre[B];
+                R4 qpre[B][4];
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    fpre[j] = s_in[(c - 3) % 4][j][lane].x;
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) qpre[j][st] = s_q[(c - 3) & 1][j][st][lane];
+                }
+#pragma unroll
+                for (int j = 0; j < B; ++j) trans_step(kb + j, j, fpre[j], qpre[j]);
+            } else {
+                for (int k = kb; k < ke; ++k) {
+                    R4 qst[4];
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) qst[st] = s_q[(c - 3) & 1][k - kb][st][lane];
+                    trans_step(k, k - kb, s_in[(c - 3) % 4][k - kb][lane].x, qst);
+                }
+            }
+            if (POS && c == nch + 2) {
+                R4 o;
+                o.x = p[0]; o.y = p[1]; o.z = p[2]; o.w = Real(0);
+                s_pN[0][lane] = o;
+                o.x = pl[0]; o.y = pl[1]; o.z = pl[2];
+                s_pN[1][lane] = o;
+            }
+        }
+        if (wave == 3 && c >= 4) {
+            // position costs and input-rate terms of chunk c - 4
+            const int kb = (c - 4) * B, ke = min(N, kb + B);
+            auto cost_step = [&](const int k, const int j, const R4 *pr) {
+                Real term = Real(0);
+                if (RATE) {
+                    const R4 u = s_u[(c - 4) % 5][j][lane];
+                    const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
+                    term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                    up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
+                }
+                if (HAS_V) {
+                    const Real V = s_v[(c - 4) % 5][j][lane];
+                    const Real dv = V - vp;
+                    term += r_dv * dv * dv;
+                    term -= (Real)a.mu * V;
+                    vp = V;
+                }
+                if (POS) {
+                    const R4 ph = pr[0], plo = pr[1];
+                    const Real pk[3] = {ph.x, ph.y, ph.z}, pkl[3] = {plo.x, plo.y, plo.z};
+                    if (OBJ == OBJ_GATE) {
+                        const R4 dp4 = pr[2];
+                        const Real dpv[3] = {dp4.x, dp4.y, dp4.z};
+                        const Real ax = (pk[0] - gt.cx) + pkl[0];
+                        const Real ay = (pk[1] - gt.cy) + pkl[1];
+                        const Real az = (pk[2] - gt.cz) + pkl[2];
+                        const Real bx = (pk[0] - g0r.cx) + pkl[0];
+                        const Real by = (pk[1] - g0r.cy) + pkl[1];
+                        const Real bz = (pk[2] - g0r.cz) + pkl[2];
+                        const Real d2 = bx * bx + by * by + bz * bz;
+                        if (d2 < r_near2) term += q_near * d2;
+                        if (nominal) a.front8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+                        term += dpv[0] * (Real(2) * ax + dpv[0]) + dpv[1] * (Real(2) * ay + dpv[1]) +
+                                dpv[2] * (Real(2) * az + dpv[2]);
+                        const Real sa = ax * gt.nx + ay * gt.ny;
+                        const Real sb = (ax + dpv[0]) * gt.nx + (ay + dpv[1]) * gt.ny;
+                        if (sa < Real(0) && sb >= Real(0)) {
+                            const Real t = sa / (sa - sb);
+                            const Real yx = ax + t * dpv[0], yy = ay + t * dpv[1], yz = az + t * dpv[2];
+                            const Real lat = yx * gt.hx + yy * gt.hy;
+                            const bool inside = fabs(lat) <= half && fabs(yz) <= half;
+                            const int jj = k + 1;
+                            const bool allowed = passes > 0 || ((h.allow[jj >> 5] >> (jj & 31)) & 1u);
+                            if (inside && allowed) {
+                                g = (g + 1 == a.G) ? 0 : g + 1;
+                                ++passes;
+                                gt.load(gtab, g);
+                            }
+                        }
+                    } else {
+                        const Real fl = floor(th_hi * inv_ds);
+                        const Real f = ((th_hi - fl * ds) + th_lo) * inv_ds;
+                        const int i = (fl >= Real(0) && fl < Real(1 << 30)) ? ((int)fl % a.P) : 0;
+                        const int i1 = (i + 1 == a.P) ? 0 : i + 1;
+                        const Real *A = path + 8 * i, *Bp = path + 8 * i1;
+                        const Real g1 = Real(1) - f;
+                        const Real px = g1 * A[0] + f * Bp[0], py = g1 * A[1] + f * Bp[1], pz = g1 * A[2] + f * Bp[2];
+                        Real tx = g1 * A[3] + f * Bp[3], ty = g1 * A[4] + f * Bp[4], tz = g1 * A[5] + f * Bp[5];
+                        const Real tn = inv_sqrt(tx * tx + ty * ty + tz * tz);
+                        tx *= tn; ty *= tn; tz *= tn;
+                        const Real ex = (pk[0] - px) + pkl[0];
+                        const Real ey = (pk[1] - py) + pkl[1];
+                        const Real ez = (pk[2] - pz) + pkl[2];
+                        const Real et = ex * tx + ey * ty + ez * tz;
+                        const Real lx = et * tx, ly = et * ty, lz = et * tz;
+                        const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
+                        term += (Real)a.q_l * (lx * lx + ly * ly + lz * lz);
+                        term += (Real)a.q_c * (cxe * cxe + cye * cye + cze * cze);
+                        const Real vk = s_v[(c - 4) % 5][j][lane];
+                        const Real y = vk * dt + th_lo;
+                        const Real t = th_hi + y;
+                        th_lo = (sizeof(Real) == 4) ? y - (t - th_hi) : Real(0);
+                        th_hi = t;
+                        if (th_hi >= L) th_hi -= L;
+                    }
+                }
+                J.add(term);
+            };
+            if (ke - kb == B) {
+                R4 ppre[B][3];
+#pragma unroll
+                for (int j = 0; j < B; ++j)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) ppre[j][i] = POS ? s_p[(c - 4) & 1][j][i][lane] : R4{};
+#pragma unroll
+                for (int j = 0; j < B; ++j) cost_step(kb + j, j, ppre[j]);
+            } else {
+                for (int k = kb; k < ke; ++k) {
+                    R4 pr[3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) pr[i] = POS ? s_p[(c - 4) & 1][k - kb][i][lane] : R4{};
+                    cost_step(k, k - kb, pr);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // terminal tracking terms, on the wave that holds each part of x_N
+    if (OBJ == OBJ_TRACK && wave < 3) {
+        int r = i0 + N;
+        if (r > a.R - 1) r = a.R - 1;
+        const Real *xr = xref + 16 * r;
+        Real term = 0;
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const Real e = (w[i] - xr[10 + i]) + wl[i];
+                term += (Real)a.QN[10 + i] * e * e;
+            }
+        } else if (wave == 1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const Real e = (q[i] - xr[6 + i]) + ql[i];
+                term += (Real)a.QN[6 + i] * e * e;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const Real e = (p[i] - xr[i]) + pl[i];
+                term += (Real)a.QN[i] * e * e;
+                const Real f = (v[i] - xr[3 + i]) + vl[i];
+                term += (Real)a.QN[3 + i] * f * f;
+            }
+        }
+        J.add(term);
+    }
+    if (wave < 3) s_jp[wave][lane] = J.value();
+    __syncthreads();
+    if (wave == 3) {
+        Real Jfinal = Real(0);
+        if (active) {
+            Jfinal = ((s_jp[0][lane] + s_jp[1][lane]) + s_jp[2][lane]) + J.value();
+            if (OBJ == OBJ_GATE && nominal) {
+                const R4 ph = s_pN[0][lane], plo = s_pN[1][lane];
+                const Real bx = (ph.x - g0r.cx) + plo.x;
+                const Real by = (ph.y - g0r.cy) + plo.y;
+                a.front8[N] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+            }
+            if (nominal) a.cur->J_nom = (double)Jfinal;
+            else ((Real *)a.J)[m] = Jfinal;
+        }
+        store_tile_min(Jfinal, active && !nominal && isfinite(Jfinal), a.tmin, blk);
+    }
+    __syncthreads();
+}
+
+template <int OBJ, typename Real> __global__ __launch_bounds__(256) void k_rollout4(KArgs a)
+{
+    __shared__ HeadVals h;
+    compute_head(a, h);
+    if (blockIdx.x == 0 && threadIdx.x == 0) publish_head(a, h);
+    rollout4_body<OBJ, Real>(a, blockIdx.x, h);
+}
+
 template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 + NW)) void k_rollout3(KArgs a)
 {
     __shared__ HeadVals h;
@@ -1677,6 +2272,28 @@ template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 +
     }
 }
 
+template <int OBJ, typename Real> __global__ __launch_bounds__(256) void kb_rollout4(BArgs b)
+{
+    __shared__ KArgs s_a;
+    __shared__ HeadVals h;
+    __shared__ int s_ctx, s_unit;
+    if (threadIdx.x == 0) s_ctx = -1;
+    const int n = b.desc->n, total = b.desc->n_tiles;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_unit = (int)atomicAdd(&b.desc->queue, 1u);
+        __syncthreads();
+        const int u = s_unit;
+        if (u >= total) break;
+        const int item = find_item(b.tile_prefix, n, u);
+        stage_args(s_a, s_ctx, b, item);
+        const int blk = u - b.tile_prefix[item];
+        compute_head(s_a, h);
+        if (blk == 0 && threadIdx.x == 0) publish_head(s_a, h);
+        rollout4_body<OBJ, Real>(s_a, blk, h);
+    }
+}
+
 // One unit per (item, step) of the weighted average.
 template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(kFinalThreads) void kb_final(BArgs b)
 {
@@ -1699,7 +2316,7 @@ static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream
     if (L.rollout_waves < 3)
         hipLaunchKernelGGL((kb_sample<Real, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
     if (L.rollout_waves == 4)
-        hipLaunchKernelGGL((kb_rollout3<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((kb_rollout4<OBJ, Real>), dim3(L.rollout_groups), dim3(256), 0, st, b);
     else if (L.rollout_waves == 3)
         hipLaunchKernelGGL((kb_rollout3<OBJ, Real, 1>), dim3(L.rollout_groups), dim3(192), 0, st, b);
     else if (L.rollout_waves == 2)
@@ -1761,7 +2378,7 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     if (a.rollout_waves < 3) hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);
     if (a.rollout_waves == 4)
-        hipLaunchKernelGGL((k_rollout3<OBJ, Real, 2>), dim3((a.K + 1 + 63) / 64), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_rollout4<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(256), 0, st, a);
     else if (a.rollout_waves == 3)
         hipLaunchKernelGGL((k_rollout3<OBJ, Real, 1>), dim3((a.K + 1 + 63) / 64), dim3(192), 0, st, a);
     else if (a.rollout_waves == 2)

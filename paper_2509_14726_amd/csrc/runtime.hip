@@ -176,12 +176,13 @@ static void plan_layout(mppi_ctx *c)
     const int K = c->K;
     a.n_tiles = (K + 1 + 63) / 64;
     // Rollout layout: with fewer 64-sample tiles than SIMDs (1024 on MI355X)
-    // the chip is latency bound and splitting each tile's work over several
-    // waves (sampling, attitude, translation) shortens each step; with more,
-    // one wave per 64 samples issues fewer instructions in total.  The
-    // environment variable MPPI_ROLLOUT_WAVES (1..4) overrides the choice.
+    // the chip is latency bound and splitting each tile's step over four
+    // pipelined waves (sampling with body rates, attitude, translation,
+    // sampling with position costs), one per SIMD, shortens each step; with
+    // more tiles, one wave per 64 samples issues fewer instructions in total.
+    // The environment variable MPPI_ROLLOUT_WAVES (1..4) overrides the choice.
     const int waves = (K + 1 + 63) / 64;
-    a.rollout_waves = waves < 1024 ? 3 : 1;
+    a.rollout_waves = waves < 1024 ? 4 : 1;
     if (const char *e = getenv("MPPI_ROLLOUT_WAVES")) {
         if (e[0] >= '1' && e[0] <= '4') a.rollout_waves = e[0] - '0';
     }
@@ -669,7 +670,7 @@ static void resolve_cfg(mppi_batch *b)
 {
     mppi_batch_cfg &c = b->cfg;
     int waves = c.rollout_waves;
-    if (waves < 1 || waves > 4) waves = b->total_tiles < 4 * b->n_cu ? 3 : 1;
+    if (waves < 1 || waves > 4) waves = b->total_tiles < 4 * b->n_cu ? 4 : 1;
     int rg = c.rollout_groups > 0 ? c.rollout_groups : (waves >= 2 ? b->n_cu : 8 * b->n_cu);
     int sg = c.sample_groups > 0 ? c.sample_groups : 4 * b->n_cu;
     for (auto &g : b->groups) {

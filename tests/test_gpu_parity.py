@@ -157,9 +157,8 @@ def test_device_entry_point_matches_host_entry_point():
 @pytest.mark.parametrize("precision", [M.FP64, M.FP32])
 def test_rollout_layouts_agree(precision, objective, monkeypatch):
     """The rollout layouts compute the same per-component arithmetic: costs
-    agree to a few ulps, the update to rounding.  The three- and four-wave
-    layouts differ only in which wave draws a step's noise and when the rate
-    terms are added (same terms, same order), so they agree bit for bit."""
+    agree to a few ulps (the layouts group the cost terms of a step
+    differently before they are summed), the update to rounding."""
     say("layouts agree", precision, objective)
     w = _workload(4096, 80, objective=objective, seed=12, **{"lambda": 40.0})
     out = []
@@ -170,7 +169,6 @@ def test_rollout_layouts_agree(precision, objective, monkeypatch):
         J, _ = dev.read_samples()
         out.append((J, U))
         dev.close()
-    assert np.array_equal(out[2][0], out[3][0]) and np.array_equal(out[2][1], out[3][1])
     eps = 1e-13 if precision == M.FP64 else 1e-5
     for other in out[1:]:
         np.testing.assert_allclose(out[0][0], other[0], rtol=eps, atol=eps)
