@@ -281,7 +281,11 @@ const char *mppi_batch_last_error(const mppi_batch *b);
  * tile minima) fits in the free part of a device arena of budget_bytes, and
  * launches them as one batch.  Requests that arrive while others run are
  * admitted as slots and memory free up; the slots' work overlaps on the
- * device.  A solve's result is the same as that of the context stepped alone. */
+ * device.  A solve's result is the same as that of the context stepped alone:
+ * bit for bit when all of the server's contexts use one rollout layout (each
+ * context picks its layout from K at creation, or from MPPI_ROLLOUT_WAVES; the
+ * server's launches then use it), else to rounding (the layouts group the
+ * cost terms of a step differently). */
 typedef struct mppi_server mppi_server;
 
 typedef struct {

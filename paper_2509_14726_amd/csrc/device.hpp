@@ -152,6 +152,17 @@ template <typename T> __device__ __forceinline__ T clampT(T v, T lo, T hi)
     return v < lo ? lo : (v > hi ? hi : v);
 }
 
+// clampT for a finite v and lo <= hi, in one instruction for binary32
+// (median of three); equal to clampT for every finite v.
+__device__ __forceinline__ float clamp_finite(float v, float lo, float hi)
+{
+    return __builtin_amdgcn_fmed3f(v, lo, hi);
+}
+__device__ __forceinline__ double clamp_finite(double v, double lo, double hi)
+{
+    return fmin(fmax(v, lo), hi);
+}
+
 // Compensated (Kahan) running sum.  For double the compensation is dropped.
 template <typename Real> struct KSum {
     Real s = Real(0), c = Real(0);

@@ -1498,31 +1498,34 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
             // noise, clipped inputs and the per-step thrust and torques
             const int kb = c * B, ke = min(N, kb + B);
             const int k_first = wave == 3 ? 1 : 0;
-            auto noise_step = [&](const int k, const int j) {
+            // a step's draw: the clipped inputs (u, V) of sample m at step k;
+            // every lane draws (no branch around the arithmetic, so the steps
+            // of a chunk interleave), the noise-free nominal and the idle
+            // lanes past it with zero noise
+            auto draw = [&](const int k, R4 &u, Real &V) {
                 const R4 w4 = s_us[k];
                 const Real us[4] = {w4.x, w4.y, w4.z, w4.w};
-                const Real vs = HAS_V ? s_vs[k] : Real(0);
-                R4 u;
-                Real V = Real(0);
+                const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, h.s, 0u, a.seed_lo, a.seed_hi);
+                const Real p0 = us[0] + sig0 * z.z0, p1 = us[1] + sig1 * z.z1;
+                const Real p2 = us[2] + sig2 * z.z2, p3 = us[3] + sig3 * z.z3;
+                u.x = clamp_finite(sampled ? p0 : us[0], tmin, tmax);
+                u.y = clamp_finite(sampled ? p1 : us[1], tmin, tmax);
+                u.z = clamp_finite(sampled ? p2 : us[2], tmin, tmax);
+                u.w = clamp_finite(sampled ? p3 : us[3], tmin, tmax);
+                V = Real(0);
+                if (HAS_V) {
+                    const Real vs = s_vs[k];
+                    const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, h.s, 1u, a.seed_lo, a.seed_hi);
+                    const Real pv = vs + sigv * zv;
+                    V = clamp_finite(sampled ? pv : vs, Real(0), vmax);
+                }
+            };
+            // store the samples, hand the inputs on
+            auto put = [&](const int k, const int j, const R4 u, const Real V) {
                 if (sampled) {
-                    const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, h.s, 0u, a.seed_lo, a.seed_hi);
-                    u.x = clampT(us[0] + sig0 * z.z0, tmin, tmax);
-                    u.y = clampT(us[1] + sig1 * z.z1, tmin, tmax);
-                    u.z = clampT(us[2] + sig2 * z.z2, tmin, tmax);
-                    u.w = clampT(us[3] + sig3 * z.z3, tmin, tmax);
                     const size_t idx = (size_t)k * (size_t)K + (size_t)m;
                     ctrl[idx] = u;
-                    if (HAS_V) {
-                        const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, h.s, 1u, a.seed_lo, a.seed_hi);
-                        V = clampT(vs + sigv * zv, Real(0), vmax);
-                        vctrl[idx] = V;
-                    }
-                } else {  // the noise-free nominal (and idle lanes past it)
-                    u.x = clampT(us[0], tmin, tmax);
-                    u.y = clampT(us[1], tmin, tmax);
-                    u.z = clampT(us[2], tmin, tmax);
-                    u.w = clampT(us[3], tmin, tmax);
-                    if (HAS_V) V = clampT(vs, Real(0), vmax);
+                    if (HAS_V) vctrl[idx] = V;
                 }
                 if (HAS_V) s_v[c % 5][j][lane] = V;
                 if (RATE) s_u[c % 5][j][lane] = u;
@@ -1532,10 +1535,21 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                 s_in[c % 4][j][lane] = o;
             };
             if (ke - kb == B) {
+                static_assert(B % 2 == 0, "each sampling wave takes B / 2 steps of a chunk");
+                constexpr int NS = B / 2;
+                R4 uu[NS];
+                Real vv[NS];
 #pragma unroll
-                for (int j = k_first; j < B; j += 2) noise_step(kb + j, j);
+                for (int i = 0; i < NS; ++i) draw(kb + k_first + 2 * i, uu[i], vv[i]);
+#pragma unroll
+                for (int i = 0; i < NS; ++i) put(kb + k_first + 2 * i, k_first + 2 * i, uu[i], vv[i]);
             } else {
-                for (int k = kb + k_first; k < ke; k += 2) noise_step(k, k - kb);
+                for (int k = kb + k_first; k < ke; k += 2) {
+                    R4 u1;
+                    Real v1;
+                    draw(k, u1, v1);
+                    put(k, k - kb, u1, v1);
+                }
             }
         }
         if (wave == 0 && c >= 1 && c <= nch) {

@@ -1213,7 +1213,12 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
             release_server(s);
             return sfail(nullptr, MPPI_E_NOMEM, "slot resources could not be allocated");
         }
-        mppi_batch_cfg bc{0, 0, 0, cfg->use_graph ? 1 : 0};
+        // the contexts' own rollout layout when they share one, so that a
+        // served solve repeats the stand-alone solve bit for bit
+        int layout = drones[0]->args.rollout_waves;
+        for (int i = 1; i < n; ++i)
+            if (drones[i]->args.rollout_waves != layout) layout = 0;
+        mppi_batch_cfg bc{layout, 0, 0, cfg->use_graph ? 1 : 0};
         mppi_status st = mppi_batch_create(drones, n, sl.stream, &bc, &sl.batch);
         if (st != MPPI_OK) {
             std::string e = g_create_err;

@@ -35,8 +35,7 @@ def solver(w, prec=M.FP32):
 
 
 @pytest.mark.parametrize("budget_mb,slots", [(512.0, 2), (2.0, 3)])
-def test_alone_vs_mix(budget_mb, slots, monkeypatch):
-    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "3")
+def test_alone_vs_mix(budget_mb, slots):
     say("alone vs mix", budget_mb, slots)
     n = 10
     ws = drones(n, 7, external=True)
