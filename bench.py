@@ -198,6 +198,46 @@ def closed_loop_race(steps: int = 1000):
     return out
 
 
+def paper_table_config(steps: int = 200):
+    """The sampling parameters of the paper's simulation table (Sec. V-A,
+    Table I: 8192 samples, 20-step horizon, dt = 0.03 s, lambda = 0.01) with
+    this project's quadrotor and gate objective, as context for the paper's
+    own solve time (about 0.4 ms on its desktop GPU, Sec. V-B): mean solve
+    time device-driven and through the synchronous host entry point."""
+    import numpy as np
+    import torch
+    from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import synth
+    w = synth.single_solve_workload(K=8192, N=20, dt=0.03, seed=1, **{"lambda": 0.01})
+    stream = torch.cuda.current_stream()
+    sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32, stream=stream.cuda_stream)
+    req = torch.zeros((steps, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    req[:, :13] = torch.from_numpy(w["x0"]).cuda()
+    req[:, 13] = torch.arange(steps, dtype=torch.float64, device="cuda") * 0.03
+    u0 = torch.zeros((steps, 4), dtype=torch.float64, device="cuda")
+    for i in range(10):
+        sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dev_ms = e0.elapsed_time(e1) / steps
+    lat = []
+    for i in range(steps):
+        t0 = time.perf_counter()
+        sv.solve(w["x0"], (steps + i) * 0.03, want_U=False)
+        lat.append(time.perf_counter() - t0)
+    sv.close()
+    return {"K": 8192, "N": 20, "dt": 0.03, "lambda": 0.01, "solve_ms_device": dev_ms,
+            "solve_ms_host_entry_mean": float(np.mean(lat) * 1e3),
+            "rollout_steps_per_s": 8192 * 20 / (dev_ms * 1e-3),
+            "paper_desktop_ms": 0.4, "paper_hardware": "RTX 3090, JAX (context, other hardware)"}
+
+
 def large_bench(steps: int = 5):
     """K = 262144, N = 200, dt = 0.01 on a 12-gate track: the N x K x 4 sample
     tensor (839 MB) streams through HBM; the final average accumulates in
@@ -335,7 +375,8 @@ def main():
     }
     solver.close()
     if not args.no_extras:
-        for name, fn in (("batched", batched_bench), ("large", large_bench), ("closed_loop", closed_loop_race)):
+        for name, fn in (("batched", batched_bench), ("large", large_bench), ("closed_loop", closed_loop_race),
+                         ("paper_table_config", paper_table_config)):
             try:
                 out[name] = fn()
             except Exception as e:  # reported, never silently dropped
