@@ -896,24 +896,17 @@ template <typename Real> struct Ring3;
 template <> struct Ring3<float> { static constexpr int B = 8; };
 template <> struct Ring3<double> { static constexpr int B = 4; };
 
-//
-// With NW = 2 a fourth wave shares the sampling: waves 0 and 3 take the even
-// and the odd steps of each chunk, and the control-rate and progress-speed
-// cost terms, which need the previous step's input, are added by wave 0 one
-// chunk later from an LDS ring of the clipped inputs (same terms, same order).
-template <int OBJ, typename Real, int NW>
+template <int OBJ, typename Real>
 __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const HeadVals &h)
 {
     typedef typename Vec4<Real>::T R4;
     constexpr int B = Ring3<Real>::B;
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
-    constexpr bool DEFER_RATE = NW == 2 && OBJ != OBJ_GATE;
     __shared__ R4 s_in[3][B][64];                  // (F/m, tau_x/J_x, tau_y/J_y, tau_z/J_z)
     __shared__ Real s_v[HAS_V ? 3 : 1][B][64];     // progress speed
     __shared__ R4 s_q[2][B][4][64];                // stage quaternions
     __shared__ Real s_jp[2][64];                   // partial costs of waves 0 and 1
     __shared__ R4 s_us[kNMax];                     // shifted warm-start thrusts per step
-    __shared__ R4 s_u[DEFER_RATE ? 3 : 1][B][64];  // clipped inputs, for the deferred rate terms
     __shared__ Real s_vs[HAS_V ? kNMax : 1];       // shifted warm-start progress speed
 
     const int lane = threadIdx.x & 63;
@@ -995,29 +988,8 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     __syncthreads();
 
     const int nch = (N + B - 1) / B;
-    const bool noise_wave = wave == 0 || (NW == 2 && wave == 3);
-    const int k_first = (NW == 2 && wave == 3) ? 1 : 0;
     for (int c = 0; c <= nch + 1; ++c) {
-        if (DEFER_RATE && wave == 0 && c >= 1 && c <= nch) {
-            // rate terms of the previous chunk, in step order
-            const int kb = (c - 1) * B, ke = min(N, kb + B);
-            for (int k = kb; k < ke; ++k) {
-                const int j = k - kb;
-                const R4 u = s_u[(c - 1) % 3][j][lane];
-                const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
-                Real term = rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
-                if (HAS_V) {
-                    const Real V = s_v[(c - 1) % 3][j][lane];
-                    const Real dv = V - vp;
-                    term += r_dv * dv * dv;
-                    term -= (Real)a.mu * V;
-                    vp = V;
-                }
-                J.add(term);
-                up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
-            }
-        }
-        if (noise_wave && c < nch) {
+        if (wave == 0 && c < nch) {
             const int kb = c * B, ke = min(N, kb + B);
             auto noise_step = [&](const int k, const int j) {
                 const R4 w4 = s_us[k];
@@ -1046,9 +1018,7 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     if (HAS_V) V = clampT(vs, Real(0), vmax);
                 }
                 if (HAS_V) s_v[c % 3][j][lane] = V;
-                if (DEFER_RATE) {
-                    s_u[c % 3][j][lane] = u;
-                } else if (OBJ != OBJ_GATE) {
+                if (OBJ != OBJ_GATE) {
                     const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
                     Real term = rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
                     if (HAS_V) {
@@ -1067,9 +1037,9 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
             };
             if (ke - kb == B) {
 #pragma unroll
-                for (int j = 0; j < B; j += NW) noise_step(kb + j + k_first, j + k_first);
+                for (int j = 0; j < B; ++j) noise_step(kb + j, j);
             } else {
-                for (int k = kb + k_first; k < ke; k += NW) noise_step(k, k - kb);
+                for (int k = kb; k < ke; ++k) noise_step(k, k - kb);
             }
         } else if (wave == 1 && c >= 1 && c <= nch) {
             const int kb = (c - 1) * B, ke = min(N, kb + B);
@@ -1988,12 +1958,12 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(256) void k_rollo
     rollout4_body<OBJ, Real>(a, blockIdx.x, h);
 }
 
-template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 + NW)) void k_rollout3(KArgs a)
+template <int OBJ, typename Real> __global__ __launch_bounds__(192) void k_rollout3(KArgs a)
 {
     __shared__ HeadVals h;
     compute_head(a, h);
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_head(a, h);
-    rollout3_body<OBJ, Real, NW>(a, blockIdx.x, h);
+    rollout3_body<OBJ, Real>(a, blockIdx.x, h);
 }
 
 // ---------------------------------------------------------------- weighted average
@@ -2264,7 +2234,7 @@ template <int OBJ, typename Real, int WAVES> __global__ __launch_bounds__(64 * W
     }
 }
 
-template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 + NW)) void kb_rollout3(BArgs b)
+template <int OBJ, typename Real> __global__ __launch_bounds__(192) void kb_rollout3(BArgs b)
 {
     __shared__ KArgs s_a;
     __shared__ HeadVals h;
@@ -2282,7 +2252,7 @@ template <int OBJ, typename Real, int NW> __global__ __launch_bounds__(64 * (2 +
         const int blk = u - b.tile_prefix[item];
         compute_head(s_a, h);
         if (blk == 0 && threadIdx.x == 0) publish_head(s_a, h);
-        rollout3_body<OBJ, Real, NW>(s_a, blk, h);
+        rollout3_body<OBJ, Real>(s_a, blk, h);
     }
 }
 
@@ -2332,7 +2302,7 @@ static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream
     if (L.rollout_waves == 4)
         hipLaunchKernelGGL((kb_rollout4<OBJ, Real>), dim3(L.rollout_groups), dim3(256), 0, st, b);
     else if (L.rollout_waves == 3)
-        hipLaunchKernelGGL((kb_rollout3<OBJ, Real, 1>), dim3(L.rollout_groups), dim3(192), 0, st, b);
+        hipLaunchKernelGGL((kb_rollout3<OBJ, Real>), dim3(L.rollout_groups), dim3(192), 0, st, b);
     else if (L.rollout_waves == 2)
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(128), 0, st, b);
     else
@@ -2394,7 +2364,7 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     if (a.rollout_waves == 4)
         hipLaunchKernelGGL((k_rollout4<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(256), 0, st, a);
     else if (a.rollout_waves == 3)
-        hipLaunchKernelGGL((k_rollout3<OBJ, Real, 1>), dim3((a.K + 1 + 63) / 64), dim3(192), 0, st, a);
+        hipLaunchKernelGGL((k_rollout3<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(192), 0, st, a);
     else if (a.rollout_waves == 2)
         hipLaunchKernelGGL((k_rollout_split<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(128), 0, st, a);
     else
