@@ -133,11 +133,12 @@ struct BatchItem {
 // replays any batch composition.  Items are ordered by horizon, longest first.
 struct BatchDesc {
     int32_t n;                  // items
-    int32_t n_sample_units;     // sum over items of ceil((K+1)/256) * N
+    int32_t n_sample_units;     // sum over items of ceil((K+1)/256)
     int32_t n_tiles;            // sum over items of ceil((K+1)/64)
     int32_t n_steps;            // sum over items of N (units of the weighted-average kernel)
     uint32_t queue;             // rollout tile counter, reset by the sample kernel
-    uint32_t pad[3];
+    uint32_t sample_queue;      // sample unit counter
+    uint32_t pad[2];
 };
 
 struct BArgs {

@@ -1,14 +1,20 @@
 // Kernels of one MPPI step on gfx950 (wave64).
 //
-//   k_setup    once per context: problem tables -> device layout in Real
-//   k_sample   head (block 0) + noise -> clipped samples, Eq. (3)
-//   k_rollout  one sample per lane: RK4 rollout (Eq. (2)) with the per-step
-//              cost fused in (gate Eq. (6)-(7), tracking Eq. (8), contouring
-//              Eq. (9)), cost write and running minimum
-//   k_average  max-shifted softmax weights (Eq. (4)) and the weighted sum of
-//              the samples (Eq. (5)) over (step-tile, sample-tile) blocks;
-//              the last block merges the tiles in a fixed order, writes the
-//              update, the first input and the warm-start state
+//   k_setup          once per context: problem tables -> device layout in Real
+//   k_rollout4       (default for small K) a 64-sample tile per workgroup, the
+//                    step pipelined over four waves: noise and clipped samples
+//                    (Eq. (3)), RK4 of Eq. (2) split into body rates, attitude
+//                    and translation, per-step costs fused in (gate Eq. (6)-(7),
+//                    tracking Eq. (8), contouring Eq. (9)); cost write and the
+//                    smallest cost of the tile
+//   k_rollout3       the same over three waves
+//   k_sample +       (large K) noise and clipped samples for all (m, k), then
+//   k_rollout /      one sample per lane (k_rollout) or attitude and
+//   k_rollout_split  translation on two waves (k_rollout_split)
+//   k_final          one block per horizon step: J_min from the tile minima,
+//                    softmax weights (Eq. (4)), the weighted average (Eq. (5)),
+//                    the first input, the report and the warm-start hand-over
+//   kb_*             the same bodies as persistent kernels over a batch
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -206,52 +212,72 @@ __device__ void solve_head(const KArgs &a)
 
 // ---------------------------------------------------------------- sample
 
-// One block of 256 samples at step k; block (0, 0) also runs the head.
-template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body(const KArgs &a, int bx, int k)
+// One block of 256 samples over all N steps; block 0 also runs the head.  The
+// shifted warm start (R4 per step) is staged in LDS once, so each step is the
+// noise and the clipped samples of 256 samples with one coalesced store.
+template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body(const KArgs &a, int bx)
 {
-    if (bx == 0 && k == 0) solve_head(a);
-
-    const int m = bx * 256 + threadIdx.x;
-    if (m > a.K || k >= a.N) return;
+    typedef typename Vec4<Real>::T R4;
+    __shared__ R4 s_us[kNMax];
+    __shared__ Real s_vs[HAS_V ? kNMax : 1];
+    if (bx == 0) solve_head(a);
 
     // nominal of this solve: the previous solution shifted, or hover (cold)
     const DevWarm *w = a.warm;
     const int warm = w->warm;
     const int shift = solve_shift(warm, a.req[13], w->t_prev, a.dt);
-    int src = k + shift;
-    if (src > a.N - 1) src = a.N - 1;
-    Real us[4];
-    for (int i = 0; i < 4; ++i) us[i] = warm ? (Real)a.wU[4 * src + i] : (Real)a.hover;
-    const Real vs = warm ? (Real)a.wV[src] : Real(0);
-    const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max;
-
-    typedef typename Vec4<Real>::T R4;
-    if (m == a.K) {  // the noise-free sample
-        R4 o;
-        o.x = clampT(us[0], tmin, tmax); o.y = clampT(us[1], tmin, tmax);
-        o.z = clampT(us[2], tmin, tmax); o.w = clampT(us[3], tmin, tmax);
-        ((R4 *)a.nomU)[k] = o;
-        if (HAS_V) ((Real *)a.nomV)[k] = clampT(vs, Real(0), (Real)a.v_max);
-        return;
-    }
     const uint32_t s = w->s;
-    const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, s, 0u, a.seed_lo, a.seed_hi);
-    R4 o;
-    o.x = clampT(us[0] + (Real)a.sigma[0] * z.z0, tmin, tmax);
-    o.y = clampT(us[1] + (Real)a.sigma[1] * z.z1, tmin, tmax);
-    o.z = clampT(us[2] + (Real)a.sigma[2] * z.z2, tmin, tmax);
-    o.w = clampT(us[3] + (Real)a.sigma[3] * z.z3, tmin, tmax);
-    const size_t idx = (size_t)k * (size_t)a.K + (size_t)m;
-    ((R4 *)a.ctrl)[idx] = o;
-    if (HAS_V) {
-        const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, s, 1u, a.seed_lo, a.seed_hi);
-        ((Real *)a.vctrl)[idx] = clampT(vs + (Real)a.sigma_v * zv, Real(0), (Real)a.v_max);
+    const int N = a.N, K = a.K;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        int src = k + shift;
+        if (src > N - 1) src = N - 1;
+        R4 o;
+        o.x = warm ? (Real)a.wU[4 * src + 0] : (Real)a.hover;
+        o.y = warm ? (Real)a.wU[4 * src + 1] : (Real)a.hover;
+        o.z = warm ? (Real)a.wU[4 * src + 2] : (Real)a.hover;
+        o.w = warm ? (Real)a.wU[4 * src + 3] : (Real)a.hover;
+        s_us[k] = o;
+        if (HAS_V) s_vs[k] = warm ? (Real)a.wV[src] : Real(0);
     }
+    __syncthreads();
+
+    const int m = bx * 256 + threadIdx.x;
+    const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max;
+    if (m == K) {  // the noise-free sample
+        for (int k = 0; k < N; ++k) {
+            const R4 us = s_us[k];
+            R4 o;
+            o.x = clampT(us.x, tmin, tmax); o.y = clampT(us.y, tmin, tmax);
+            o.z = clampT(us.z, tmin, tmax); o.w = clampT(us.w, tmin, tmax);
+            ((R4 *)a.nomU)[k] = o;
+            if (HAS_V) ((Real *)a.nomV)[k] = clampT(s_vs[k], Real(0), (Real)a.v_max);
+        }
+    } else if (m < K) {
+        const Real sig0 = (Real)a.sigma[0], sig1 = (Real)a.sigma[1];
+        const Real sig2 = (Real)a.sigma[2], sig3 = (Real)a.sigma[3];
+#pragma unroll 2
+        for (int k = 0; k < N; ++k) {
+            const R4 us = s_us[k];
+            const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, s, 0u, a.seed_lo, a.seed_hi);
+            R4 o;
+            o.x = clampT(us.x + sig0 * z.z0, tmin, tmax);
+            o.y = clampT(us.y + sig1 * z.z1, tmin, tmax);
+            o.z = clampT(us.z + sig2 * z.z2, tmin, tmax);
+            o.w = clampT(us.w + sig3 * z.z3, tmin, tmax);
+            const size_t idx = (size_t)k * (size_t)K + (size_t)m;
+            ((R4 *)a.ctrl)[idx] = o;
+            if (HAS_V) {
+                const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, s, 1u, a.seed_lo, a.seed_hi);
+                ((Real *)a.vctrl)[idx] = clampT(s_vs[k] + (Real)a.sigma_v * zv, Real(0), (Real)a.v_max);
+            }
+        }
+    }
+    __syncthreads();
 }
 
 template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_sample(KArgs a)
 {
-    sample_body<Real, HAS_V>(a, blockIdx.x, blockIdx.y);
+    sample_body<Real, HAS_V>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- rollout
@@ -2155,16 +2181,14 @@ __global__ __launch_bounds__(kFinalThreads) void k_final(KArgs a)
 
 // ---------------------------------------------------------------- batched (persistent)
 
-// Largest i in [0, n) with prefix[i] <= u (prefix[0] = 0, prefix[n] = total).
-__device__ __forceinline__ int find_item(const int32_t *prefix, int n, int u)
+// The item of unit u: the largest i in [0, n) with prefix[i] <= u (prefix[0]
+// = 0, prefix[n] = total).  Every persistent kernel takes its units in
+// increasing order, so the item only moves forward from the block's previous
+// one: usually one load per unit instead of a binary search.
+__device__ __forceinline__ int advance_item(const int32_t *prefix, int n, int u, int item)
 {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= u) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+    while (item + 1 < n && prefix[item + 1] <= u) ++item;
+    return item;
 }
 
 // Stage the kernel arguments of an item's context in LDS, with the item's
@@ -2197,20 +2221,25 @@ __device__ __forceinline__ void stage_args(KArgs &s_a, int &s_ctx, const BArgs &
     __syncthreads();
 }
 
+// One unit per (item, block of 256 samples), all steps of the item; units
+// are taken from a device queue in order (longest horizons first).
 template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void kb_sample(BArgs b)
 {
     __shared__ KArgs s_a;
-    __shared__ int s_ctx;
+    __shared__ int s_ctx, s_unit;
     if (threadIdx.x == 0) s_ctx = -1;
     if (blockIdx.x == 0 && threadIdx.x == 0) b.desc->queue = 0u;
     const int n = b.desc->n, total = b.desc->n_sample_units;
-    for (int u = blockIdx.x; u < total; u += gridDim.x) {
-        const int item = find_item(b.sample_prefix, n, u);
-        stage_args(s_a, s_ctx, b, item);
-        const int local = u - b.sample_prefix[item];
-        const int nbx = (s_a.K + 1 + 255) / 256;
-        sample_body<Real, HAS_V>(s_a, local % nbx, local / nbx);
+    int item = 0;
+    for (;;) {
         __syncthreads();
+        if (threadIdx.x == 0) s_unit = (int)atomicAdd(&b.desc->sample_queue, 1u);
+        __syncthreads();
+        const int u = s_unit;
+        if (u >= total) break;
+        item = advance_item(b.sample_prefix, n, u, item);
+        stage_args(s_a, s_ctx, b, item);
+        sample_body<Real, HAS_V>(s_a, u - b.sample_prefix[item]);
     }
 }
 
@@ -2220,13 +2249,14 @@ template <int OBJ, typename Real, int WAVES> __global__ __launch_bounds__(64 * W
     __shared__ int s_ctx, s_unit;
     if (threadIdx.x == 0) s_ctx = -1;
     const int n = b.desc->n, total = b.desc->n_tiles;
+    int item = 0;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_unit = (int)atomicAdd(&b.desc->queue, 1u);
         __syncthreads();
         const int u = s_unit;
         if (u >= total) break;
-        const int item = find_item(b.tile_prefix, n, u);
+        item = advance_item(b.tile_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
         const int blk = u - b.tile_prefix[item];
         if (WAVES == 2) rollout2_body<OBJ, Real>(s_a, blk);
@@ -2241,13 +2271,14 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(192) void kb_roll
     __shared__ int s_ctx, s_unit;
     if (threadIdx.x == 0) s_ctx = -1;
     const int n = b.desc->n, total = b.desc->n_tiles;
+    int item = 0;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_unit = (int)atomicAdd(&b.desc->queue, 1u);
         __syncthreads();
         const int u = s_unit;
         if (u >= total) break;
-        const int item = find_item(b.tile_prefix, n, u);
+        item = advance_item(b.tile_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
         const int blk = u - b.tile_prefix[item];
         compute_head(s_a, h);
@@ -2263,13 +2294,14 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(256) void kb_roll
     __shared__ int s_ctx, s_unit;
     if (threadIdx.x == 0) s_ctx = -1;
     const int n = b.desc->n, total = b.desc->n_tiles;
+    int item = 0;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_unit = (int)atomicAdd(&b.desc->queue, 1u);
         __syncthreads();
         const int u = s_unit;
         if (u >= total) break;
-        const int item = find_item(b.tile_prefix, n, u);
+        item = advance_item(b.tile_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
         const int blk = u - b.tile_prefix[item];
         compute_head(s_a, h);
@@ -2285,8 +2317,9 @@ template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(
     __shared__ int s_ctx;
     if (threadIdx.x == 0) s_ctx = -1;
     const int n = b.desc->n, total = b.desc->n_steps;
+    int item = 0;
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
-        const int item = find_item(b.step_prefix, n, u);
+        item = advance_item(b.step_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
         final_body<Real, Acc, HAS_V>(s_a, u - b.step_prefix[item]);
         __syncthreads();
@@ -2357,7 +2390,7 @@ template <typename Real, int OBJ>
 static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hipEvent_t *ev)
 {
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
-    const dim3 gs((a.K + 1 + 255) / 256, a.N);
+    const dim3 gs((a.K + 1 + 255) / 256);
     if (ev) (void)hipEventRecord(ev[0], st);
     if (a.rollout_waves < 3) hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);

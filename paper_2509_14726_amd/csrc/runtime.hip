@@ -874,7 +874,7 @@ static mppi_status batch_solve(mppi_batch *b, const int32_t *active, int32_t n_a
             items[j].req = d_reqs + (size_t)kReqDoubles * lst[j].second;
             items[j].u0_out = d_u0s ? d_u0s + 4 * (size_t)lst[j].second : nullptr;
             items[j].ws = ws ? ws[lst[j].second] : nullptr;
-            s_units += (int64_t)((c->K + 1 + 255) / 256) * c->N;
+            s_units += (c->K + 1 + 255) / 256;
             t_units += (c->K + 1 + 63) / 64;
             a_units += c->N;
             if (s_units > INT32_MAX || a_units > INT32_MAX) return bfail(b, MPPI_E_INVAL, "batch too large");
@@ -887,6 +887,7 @@ static mppi_status batch_solve(mppi_batch *b, const int32_t *active, int32_t n_a
         desc->n_tiles = (int32_t)t_units;
         desc->n_steps = (int32_t)a_units;
         desc->queue = 0u;
+        desc->sample_queue = 0u;
         g.active = (int)lst.size();
         BHIP_TRY(b, hipMemcpyAsync(g.d_block, g.h_block, g.bytes, hipMemcpyHostToDevice, b->stream));
     }
