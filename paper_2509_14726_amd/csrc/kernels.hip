@@ -1568,13 +1568,12 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                     term += (Real)a.Q_w[0] * w[0] * w[0] + (Real)a.Q_w[1] * w[1] * w[1] +
                             (Real)a.Q_w[2] * w[2] * w[2];
                 Real ws[3], kw[3], dw[3];
+                R4 stv[4];   // stage body rates, stored once the step is done
 #pragma unroll
                 for (int i = 0; i < 3; ++i) ws[i] = w[i];
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
-                    R4 o;
-                    o.x = ws[0]; o.y = ws[1]; o.z = ws[2]; o.w = Real(0);
-                    slot[st][lane] = o;
+                    stv[st].x = ws[0]; stv[st].y = ws[1]; stv[st].z = ws[2];
                     kw[0] = in.y - M.gx * ws[1] * ws[2];
                     kw[1] = in.z - M.gy * ws[2] * ws[0];
                     kw[2] = in.w - M.gz * ws[0] * ws[1];
@@ -1606,12 +1605,16 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
 #pragma unroll
                     for (int i = 0; i < 3; ++i) w[i] += dw[i];
                 }
+                // the body rates after the step ride in the free fourth
+                // component of stages 1-3: the attitude wave adds their
+                // rate-limit term
+                stv[0].w = Real(0);
+                stv[1].w = w[0];
+                stv[2].w = w[1];
+                stv[3].w = w[2];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const Real e = fmax(fabs(w[i]) - w_max, Real(0));
-                    term += w_lim * e * e;
-                }
-                J.add(term);
+                for (int st = 0; st < 4; ++st) slot[st][lane] = stv[st];
+                if (OBJ != OBJ_GATE) J.add(term);
             };
             // the chunk's LDS inputs are loaded before the first step uses them
             if (ke - kb == B) {
@@ -1696,6 +1699,14 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
 #pragma unroll
                     for (int i = 0; i < 4; ++i) q[i] /= nq;
                 }
+                // rate limit on the body rates after the step
+                Real term = Real(0);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const Real e = fmax(fabs(wst[1 + i].w) - w_max, Real(0));
+                    term += w_lim * e * e;
+                }
+                J.add(term);
             };
             if (ke - kb == B) {
                 R4 wpre[B][4];
@@ -1737,14 +1748,17 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                 Real vs[3], kv[3], dpv[3], dvv[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) vs[i] = v[i];
+                // F/m times the thrust direction; the factor 2 of its first
+                // two components rides on F/m (exact: a power of two)
+                const Real fm2 = Real(2) * fm;
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                     const R4 qq = qstage[st];
                     const Real r3x = Real(2) * (qq.y * qq.w + qq.x * qq.z);
                     const Real r3y = Real(2) * (qq.z * qq.w - qq.x * qq.y);
                     const Real r3z = Real(1) - Real(2) * (qq.y * qq.y + qq.z * qq.z);
-                    kv[0] = fm * r3x;
-                    kv[1] = fm * r3y;
+                    kv[0] = fm2 * (qq.y * qq.w + qq.x * qq.z);
+                    kv[1] = fm2 * (qq.z * qq.w - qq.x * qq.y);
                     kv[2] = fm * r3z - M.g;
                     if (M.drag) {
                         const Real qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
