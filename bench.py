@@ -238,6 +238,34 @@ def paper_table_config(steps: int = 200):
             "paper_desktop_ms": 0.4, "paper_hardware": "RTX 3090, JAX (context, other hardware)"}
 
 
+def fp64_solve(steps: int = 100):
+    """The benchmark workload with every step of the path in binary64 (the
+    FP64 variant): mean solve time, device-driven."""
+    import torch
+    from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import synth
+    w = synth.single_solve_workload(K=8192, N=100, seed=1)
+    stream = torch.cuda.current_stream()
+    sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP64, stream=stream.cuda_stream)
+    req = torch.zeros((steps + 10, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    req[:, :13] = torch.from_numpy(w["x0"]).cuda()
+    req[:, 13] = torch.arange(steps + 10, dtype=torch.float64, device="cuda") * 0.02
+    u0 = torch.zeros((steps + 10, 4), dtype=torch.float64, device="cuda")
+    for i in range(10):
+        sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(10, steps + 10):
+        sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sv.close()
+    return {"K": 8192, "N": 100, "ms_per_solve": ms, "rollout_steps_per_s": 8192 * 100 / (ms * 1e-3)}
+
+
 def large_bench(steps: int = 5):
     """K = 262144, N = 200, dt = 0.01 on a 12-gate track: the N x K x 4 sample
     tensor (839 MB) streams through HBM; the final average accumulates in
@@ -376,7 +404,7 @@ def main():
     solver.close()
     if not args.no_extras:
         for name, fn in (("batched", batched_bench), ("large", large_bench), ("closed_loop", closed_loop_race),
-                         ("paper_table_config", paper_table_config)):
+                         ("paper_table_config", paper_table_config), ("fp64", fp64_solve)):
             try:
                 out[name] = fn()
             except Exception as e:  # reported, never silently dropped
