@@ -33,14 +33,14 @@ PEAK_HBM_GBPS = 8000.0
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a run
 # of its own, WRITE_SIZE (KiB per dispatch, mean of 12 dispatches of the
 # benchmark workload), scaled by what the same counters read for a plain
-# 256 MiB device copy (FETCH_SIZE 131086.6 KiB -> x 2.0, WRITE_SIZE
+# 256 MiB device copy (FETCH_SIZE 131085.1 KiB -> x 2.0, WRITE_SIZE
 # 262144.0 KiB -> x 1.0); see profiles/k_rollout4_gate_k8192_n100_traffic.md.
 # They hold only for the device sources they were taken on (sha256 of
 # kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order); for any
 # other source the traffic is reported as null.
-TRAFFIC_SOURCES = "3c4a882f2bae9ee9e92e7c1292bca795fec85199e942b6cbbf19267bbc57fda6"
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131086.6, 262144.0 / 262144.0
-TRAFFIC_KIB = {"k_rollout4": (246.7, 12836.5), "k_final": (6578.4, 6.6)}
+TRAFFIC_SOURCES = "017d8b566a8b3da64b4ef424808c3441bc8fb15bc3283f7066d63d5679a36d8c"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.1, 262144.0 / 262144.0
+TRAFFIC_KIB = {"k_rollout4": (234.7, 12836.5), "k_final": (6578.4, 6.6)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
 
