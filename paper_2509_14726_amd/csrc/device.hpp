@@ -77,7 +77,7 @@ struct KArgs {
     double q_l, q_c, Q_w[3], r_dv, mu, v_max;
     double path_len, ref_dt;
     // problem data
-    const double *gates_d;      // G x 4 (head, FP64)
+    const double *gates_d;      // G x 4 (as given), then G x 8 frames (centre, n, h, pad) for the head, FP64
     const void *gates_r;        // G x 8 Real: c, n.xy, h.xy, pad
     const double *path_d;       // P x 6 (head, FP64)
     const void *path_r;         // P x 8 Real: p, t, pad

@@ -35,9 +35,17 @@ template <typename Real> __global__ void k_setup(KArgs a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < a.G && a.gates_d) {
+        // gate frame (centre, normal n, lateral h) in binary64 for the head
+        // and in Real for the rollouts; the yaw's cosine and sine are taken
+        // once here
         const double *g = a.gates_d + 4 * i;
-        Real *o = (Real *)a.gates_r + 8 * i;
+        double *f = (double *)a.gates_d + 4 * a.G + 8 * i;
         const double cy = cos(g[3]), sy = sin(g[3]);
+        f[0] = g[0]; f[1] = g[1]; f[2] = g[2];
+        f[3] = cy; f[4] = sy;
+        f[5] = -sy; f[6] = cy;
+        f[7] = 0.0;
+        Real *o = (Real *)a.gates_r + 8 * i;
         o[0] = (Real)g[0]; o[1] = (Real)g[1]; o[2] = (Real)g[2];
         o[3] = (Real)cy; o[4] = (Real)sy;     // normal n
         o[5] = (Real)(-sy); o[6] = (Real)cy;  // lateral h
@@ -60,11 +68,12 @@ template <typename Real> __global__ void k_setup(KArgs a)
 
 // ---------------------------------------------------------------- head
 
-// Measured gate pass x_prev -> x0 (same geometry as the in-horizon switch).
+// Measured gate pass x_prev -> x0 (same geometry as the in-horizon switch);
+// gate = the binary64 frame (centre, n, h) written at set-up.
 __device__ bool gate_cross_d(const double *pa, const double *pb, const double *gate, double half)
 {
-    const double nx = cos(gate[3]), ny = sin(gate[3]);
-    const double hx = -sin(gate[3]), hy = cos(gate[3]);
+    const double nx = gate[3], ny = gate[4];
+    const double hx = gate[5], hy = gate[6];
     const double sa = (pa[0] - gate[0]) * nx + (pa[1] - gate[1]) * ny;
     const double sb = (pb[0] - gate[0]) * nx + (pb[1] - gate[1]) * ny;
     if (!(sa < 0.0 && sb >= 0.0)) return false;
@@ -157,7 +166,7 @@ __device__ void compute_head(const KArgs &a, HeadVals &h)
         uint32_t allow[kMaskWords];
         for (int j = 0; j < kMaskWords; ++j) allow[j] = warm ? w->allow[j] : 0xffffffffu;
         if (warm && a.objective == OBJ_GATE && g0 >= 0 && g0 < a.G &&
-            gate_cross_d(w->x_prev, a.req, a.gates_d + 4 * g0, a.gate_half)) {
+            gate_cross_d(w->x_prev, a.req, a.gates_d + 4 * a.G + 8 * g0, a.gate_half)) {
             g0 = (g0 + 1) % a.G;
             for (int j = 0; j < kMaskWords; ++j) allow[j] = 0xffffffffu;
         }

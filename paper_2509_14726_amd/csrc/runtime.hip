@@ -304,7 +304,7 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
         if (!path_d || !path_r) { release(c); return fail(nullptr, MPPI_E_NOMEM, "device allocation failed"); }
     }
     if (c->objective == MPPI_OBJ_GATE) {
-        gates_d = dev_alloc(c, sizeof(double) * 4 * (size_t)c->G);
+        gates_d = dev_alloc(c, sizeof(double) * 12 * (size_t)c->G);  // G x 4 as given, G x 8 frames
         gates_r = dev_alloc(c, rs * 8 * (size_t)c->G);
         if (!gates_d || !gates_r) { release(c); return fail(nullptr, MPPI_E_NOMEM, "device allocation failed"); }
     }
