@@ -112,6 +112,20 @@ def test_metric_configuration_fp32(rollout_waves):
     dev.close()
 
 
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+def test_paper_table_parameters(precision):
+    """The sampling parameters of the paper's simulation table (8192 samples,
+    20-step horizon, dt = 0.03 s, lambda = 0.01): the weights collapse onto
+    the cheapest samples, a cold and a warm solve."""
+    say("paper table parameters K=8192 N=20 dt=0.03 lambda=0.01", precision)
+    w = _workload(8192, 20, seed=2, dt=0.03, **{"lambda": 0.01})
+    dev, orc = build_pair(w, precision, n_threads=16)
+    for step in range(2):
+        st = solve_and_compare(dev, orc, w["x0"], step * 0.03, precision)
+        say("  step", step, "err_J", st["err_J"], "err_U", st["err_U"], "e2e", st["err_U_e2e"])
+    dev.close()
+
+
 def test_nonfinite_costs_leave_warm_state():
     say("nonfinite")
     w = _workload(256, 20)
