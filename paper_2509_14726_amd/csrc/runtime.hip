@@ -274,10 +274,8 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     plan_layout(c);
 
     const size_t rs = c->fp64 ? sizeof(double) : sizeof(float);
-    const size_t as = c->acc64 ? sizeof(double) : sizeof(float);
     a.C = c->C;
     a.real_bytes = (int32_t)rs;
-    a.acc_bytes = (int32_t)as;
     c->external_ws = (params->flags & MPPI_FLAG_EXTERNAL_WORKSPACE) != 0;
     struct Want { void **dst; size_t bytes; };
     void *gates_d = nullptr, *gates_r = nullptr, *path_d = nullptr, *path_r = nullptr, *xref_r = nullptr;
