@@ -37,6 +37,7 @@ extern "C" {
 #define MPPI_N_MAX 256            /* longest horizon                          */
 #define MPPI_K_MAX (1 << 24)      /* most samples per solve                   */
 #define MPPI_MASK_WORDS 9         /* (MPPI_N_MAX + 1) bits of per-state flags */
+#define MPPI_G_MAX 256            /* most gates of a gate track               */
 #define MPPI_REQ_DOUBLES 16       /* device request record, see mppi_solve_device */
 
 typedef struct mppi_ctx mppi_ctx;
@@ -99,7 +100,7 @@ typedef struct {
 /* Problem data: the inputs of Alg. 1 (waypoints W, path P_arc, tau_ref). */
 typedef struct {
     const double *gates;  /* G x 4 row-major: centre x, y, z, yaw (gate objective) */
-    int32_t n_gates;
+    int32_t n_gates;      /* G, 1..MPPI_G_MAX                                  */
     double gate_size;     /* side of the square aperture, m                    */
     const double *path;   /* P x 6 row-major: position, unit tangent; P points
                              uniformly spaced in arc length over a closed path */

@@ -18,6 +18,7 @@ namespace mppi {
 
 constexpr int kNMax = 256;
 constexpr int kMaskWords = 9;   // (kNMax + 1) bits
+constexpr int kGMax = 256;      // most gates (the pipelined rollouts stage the table in LDS)
 constexpr int kReqDoubles = 16;
 constexpr int kFinalThreads = 1024;  // threads of a block of the weighted-average kernel
 

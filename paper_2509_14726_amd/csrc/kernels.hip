@@ -943,6 +943,8 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     __shared__ Real s_jp[2][64];                   // partial costs of waves 0 and 1
     __shared__ R4 s_us[kNMax];                     // shifted warm-start thrusts per step
     __shared__ Real s_vs[HAS_V ? kNMax : 1];       // shifted warm-start progress speed
+    __shared__ Real s_gtab[OBJ == OBJ_GATE ? 8 * kGMax : 1];   // the gate table, staged once
+    __shared__ uint8_t s_f8[OBJ == OBJ_GATE ? kNMax : 1];      // front flags of the nominal, steps 0..N-1
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -986,11 +988,7 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     const Real *gtab = (const Real *)a.gates_r;
     const Real *path = (const Real *)a.path_r;
     Real th_hi = 0, th_lo = 0, ds = 0, inv_ds = 0, L = 0;
-    if (OBJ == OBJ_GATE) {
-        g = h.g0;
-        gt.load(gtab, g);
-        g0r = gt;
-    }
+    if (OBJ == OBJ_GATE) g = h.g0;
     if (OBJ == OBJ_CONTOUR) {
         th_hi = (Real)h.theta0;
         if (sizeof(Real) == 4) th_lo = (Real)(h.theta0 - (double)th_hi);
@@ -1006,6 +1004,10 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     R4g *ctrl = (R4g *)a.ctrl;
     Real *vctrl = (Real *)a.vctrl;
 
+    // the gate table in LDS: a gate switch inside the pipeline then waits on
+    // no global load (which would also wait on the wave's sample stores)
+    if (OBJ == OBJ_GATE)
+        for (int i = threadIdx.x; i < 8 * a.G; i += blockDim.x) s_gtab[i] = gtab[i];
     // the shifted warm start (Alg. 1, warm start) of every step, staged once
     // so that the sampling wave reads it from LDS instead of waiting on a
     // dependent global load per step
@@ -1021,6 +1023,10 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
         if (HAS_V) s_vs[k] = h.warm ? (Real)a.wV[src] : Real(0);
     }
     __syncthreads();
+    if (OBJ == OBJ_GATE) {
+        gt.load(s_gtab, g);
+        g0r = gt;
+    }
 
     const int nch = (N + B - 1) / B;
     for (int c = 0; c <= nch + 1; ++c) {
@@ -1210,7 +1216,7 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     const Real bz = (p[2] - g0r.cz) + pl[2];
                     const Real d2 = bx * bx + by * by + bz * bz;
                     if (d2 < r_near2) term += q_near * d2;
-                    if (nominal) a.front8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+                    if (nominal) s_f8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
                 } else if (OBJ == OBJ_TRACK) {
                     int r = i0 + k;
                     if (r > a.R - 1) r = a.R - 1;
@@ -1322,7 +1328,7 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                         if (inside && allowed) {
                             g = (g + 1 == a.G) ? 0 : g + 1;
                             ++passes;
-                            gt.load(gtab, g);
+                            gt.load(s_gtab, g);
                         }
                     }
                 }
@@ -1379,6 +1385,9 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
             if (nominal) a.cur->J_nom = (double)Jfinal;
             else ((Real *)a.J)[m] = Jfinal;
         }
+        // the tile of the nominal writes its front flags of steps 0..N-1
+        if (OBJ == OBJ_GATE && blk == (K >> 6))
+            for (int i = lane; i < N; i += 64) a.front8[i] = s_f8[i];
         store_tile_min(Jfinal, active && !nominal && isfinite(Jfinal), a.tmin, blk);
     }
     __syncthreads();
@@ -1422,6 +1431,8 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
     __shared__ Real s_vs[HAS_V ? kNMax : 1];       // shifted warm-start progress speed
     __shared__ Real s_jp[3][64];                   // partial costs of waves 0, 1, 2
     __shared__ R4 s_pN[2][64];                     // p_N hi and lo (front flag of the nominal)
+    __shared__ Real s_gtab[OBJ == OBJ_GATE ? 8 * kGMax : 1];   // the gate table, staged once
+    __shared__ uint8_t s_f8[OBJ == OBJ_GATE ? kNMax : 1];      // front flags of the nominal, steps 0..N-1
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -1463,11 +1474,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
     const Real *gtab = (const Real *)a.gates_r;
     const Real *path = (const Real *)a.path_r;
     Real th_hi = 0, th_lo = 0, ds = 0, inv_ds = 0, L = 0;
-    if (OBJ == OBJ_GATE) {
-        g = h.g0;
-        gt.load(gtab, g);
-        g0r = gt;
-    }
+    if (OBJ == OBJ_GATE) g = h.g0;
     if (OBJ == OBJ_CONTOUR) {
         th_hi = (Real)h.theta0;
         if (sizeof(Real) == 4) th_lo = (Real)(h.theta0 - (double)th_hi);
@@ -1483,6 +1490,10 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
     R4g *ctrl = (R4g *)a.ctrl;
     Real *vctrl = (Real *)a.vctrl;
 
+    // the gate table in LDS: a gate switch inside the pipeline then waits on
+    // no global load (which would also wait on the wave's sample stores)
+    if (OBJ == OBJ_GATE)
+        for (int i = threadIdx.x; i < 8 * a.G; i += blockDim.x) s_gtab[i] = gtab[i];
     // the shifted warm start of every step, staged once
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         int src = k + h.shift;
@@ -1496,6 +1507,10 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
         if (HAS_V) s_vs[k] = h.warm ? (Real)a.wV[src] : Real(0);
     }
     __syncthreads();
+    if (OBJ == OBJ_GATE) {
+        gt.load(s_gtab, g);
+        g0r = gt;
+    }
 
     const int nch = (N + B - 1) / B;
     for (int c = 0; c <= nch + 3; ++c) {
@@ -1883,7 +1898,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                         const Real bz = (pk[2] - g0r.cz) + pkl[2];
                         const Real d2 = bx * bx + by * by + bz * bz;
                         if (d2 < r_near2) term += q_near * d2;
-                        if (nominal) a.front8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
+                        if (nominal) s_f8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
                         term += dpv[0] * (Real(2) * ax + dpv[0]) + dpv[1] * (Real(2) * ay + dpv[1]) +
                                 dpv[2] * (Real(2) * az + dpv[2]);
                         const Real sa = ax * gt.nx + ay * gt.ny;
@@ -1898,7 +1913,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                             if (inside && allowed) {
                                 g = (g + 1 == a.G) ? 0 : g + 1;
                                 ++passes;
-                                gt.load(gtab, g);
+                                gt.load(s_gtab, g);
                             }
                         }
                     } else {
@@ -1994,6 +2009,9 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
             if (nominal) a.cur->J_nom = (double)Jfinal;
             else ((Real *)a.J)[m] = Jfinal;
         }
+        // the tile of the nominal writes its front flags of steps 0..N-1
+        if (OBJ == OBJ_GATE && blk == (K >> 6))
+            for (int i = lane; i < N; i += 64) a.front8[i] = s_f8[i];
         store_tile_min(Jfinal, active && !nominal && isfinite(Jfinal), a.tmin, blk);
     }
     __syncthreads();

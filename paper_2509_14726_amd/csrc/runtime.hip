@@ -23,6 +23,7 @@ using namespace mppi;
 
 static_assert(MPPI_MASK_WORDS == kMaskWords, "mask width");
 static_assert(MPPI_N_MAX == kNMax, "horizon bound");
+static_assert(MPPI_G_MAX == kGMax, "gate bound");
 static_assert(MPPI_REQ_DOUBLES == kReqDoubles, "request record");
 
 struct mppi_ctx {
@@ -149,6 +150,7 @@ static mppi_status validate(const mppi_params *p, const mppi_quad *q, const mppi
     if (!(q->t_max >= q->t_min)) return fail(nullptr, MPPI_E_INVAL, "t_max < t_min");
     if (p->objective == MPPI_OBJ_GATE) {
         if (!pb->gates || pb->n_gates < 1) return fail(nullptr, MPPI_E_INVAL, "gate objective needs >= 1 gate");
+        if (pb->n_gates > kGMax) return fail(nullptr, MPPI_E_INVAL, "at most %d gates", kGMax);
         if (!finite_all(pb->gates, 4 * pb->n_gates)) return fail(nullptr, MPPI_E_INVAL, "gate data must be finite");
         if (!(pb->gate_size > 0.0) || !isfinite(pb->gate_size)) return fail(nullptr, MPPI_E_INVAL, "gate_size must be > 0");
     }

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmppi.so")
 
 N_MAX = 256
 K_MAX = 1 << 24
+G_MAX = 256
 MASK_WORDS = 9
 REQ_DOUBLES = 16
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE = 0, -1, -2, -3, -4

@@ -69,6 +69,15 @@ def test_create_rejects_missing_problem_data():
         M.Solver(w["quad"], prm, path=np.zeros((10, 6)), path_len=1.0)  # v_max dt >= L
 
 
+def test_create_rejects_more_gates_than_the_bound():
+    w = synth.single_solve_workload(K=64, N=10)
+    g = np.zeros((M.G_MAX + 1, 4))
+    g[:, 0] = np.arange(M.G_MAX + 1)
+    with pytest.raises(M.MppiError) as e:
+        M.Solver(w["quad"], w["params"], gates=g)
+    assert e.value.status == M.E_INVAL and "gates" in str(e.value)
+
+
 def test_plant_step_free_fall_and_hover():
     q = synth.QUAD
     x = np.zeros(13); x[6] = 1.0; x[2] = 10.0; x[3] = 1.0

@@ -126,6 +126,42 @@ def test_paper_table_parameters(precision):
     dev.close()
 
 
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+def test_largest_gate_table(precision, rollout_waves):
+    """The most gates a track may have (MPPI_G_MAX), in a row 0.8 m apart
+    along x, flown through at 8 m/s: a dozen switches inside the horizon, and
+    from the last gate the switch wraps to gate 0."""
+    say("gate table G_MAX", precision, "waves", rollout_waves)
+    G = M.G_MAX
+    gates = np.zeros((G, 4))
+    gates[:, 0] = 0.5 + 0.8 * np.arange(G)
+    gates[:, 2] = 1.0
+    w = _workload(1000, 60, seed=3, **{"lambda": 20.0})
+    w["gates"] = gates
+    x0 = np.zeros(13)
+    x0[2] = 1.0
+    x0[3] = 8.0
+    x0[6] = 1.0
+    dev, orc = build_pair(w, precision)
+    st = solve_and_compare(dev, orc, x0, 0.0, precision)
+    say("  err_J", st["err_J"], "err_U", st["err_U"])
+    # 0.93 m before gate G-2 with gate G-2 current and every pass allowed:
+    # the horizon passes gates G-2 and G-1, and the switch after G-1 wraps to
+    # gate 0 (0.93 m, not 1 m: the start would sit on the near-gate radius)
+    x1 = x0.copy()
+    x1[0] = gates[G - 2, 0] - 0.93
+    wd = dev.get_warm()
+    wd.g0 = G - 2
+    for i in range(13):
+        wd.x_prev[i] = x1[i]
+    for i in range(M.MASK_WORDS):
+        wd.allow[i] = 0xFFFFFFFF
+    dev.set_warm(wd)
+    st = solve_and_compare(dev, orc, x1, w["params"]["dt"], precision)
+    say("  wrap: err_J", st["err_J"], "err_U", st["err_U"], "g0 handed on", dev.get_warm().g0)
+    dev.close()
+
+
 def test_nonfinite_costs_leave_warm_state():
     say("nonfinite")
     w = _workload(256, 20)
