@@ -38,9 +38,9 @@ PEAK_HBM_GBPS = 8000.0
 # They hold only for the device sources they were taken on (sha256 of
 # kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order); for any
 # other source the traffic is reported as null.
-TRAFFIC_SOURCES = "017d8b566a8b3da64b4ef424808c3441bc8fb15bc3283f7066d63d5679a36d8c"
+TRAFFIC_SOURCES = "83859b89ddccf730eb8c33c4b3efe0d3da046d91173435a9f37623e14752f025"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.1, 262144.0 / 262144.0
-TRAFFIC_KIB = {"k_rollout4": (234.7, 12836.5), "k_final": (6578.4, 6.6)}
+TRAFFIC_KIB = {"k_rollout4": (216.5, 12836.4), "k_final": (6578.0, 6.6)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
 

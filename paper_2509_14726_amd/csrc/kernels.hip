@@ -29,6 +29,25 @@ template <typename Real> struct Vec4;
 template <> struct Vec4<float> { using T = float4; };
 template <> struct Vec4<double> { using T = double4; };
 
+// Streaming (non-temporal) stores of the sample tensor from the pipelined
+// rollouts: the tensor is read once, by the weighted-average kernel, and
+// written this way it leaves no dirty L2 lines to write back when the rollout
+// kernel ends.
+__device__ __forceinline__ void store_nt(float4 *p, const float4 v)
+{
+    typedef float V __attribute__((ext_vector_type(4)));
+    const V x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, (V *)p);
+}
+__device__ __forceinline__ void store_nt(double4 *p, const double4 v)
+{
+    typedef double V __attribute__((ext_vector_type(4)));
+    const V x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, (V *)p);
+}
+__device__ __forceinline__ void store_nt(float *p, const float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_nt(double *p, const double v) { __builtin_nontemporal_store(v, p); }
+
 // ---------------------------------------------------------------- setup
 
 template <typename Real> __global__ void k_setup(KArgs a)
@@ -1045,11 +1064,11 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     u.z = clampT(us[2] + sig2 * z.z2, tmin, tmax);
                     u.w = clampT(us[3] + sig3 * z.z3, tmin, tmax);
                     const size_t idx = (size_t)k * (size_t)K + (size_t)m;
-                    ctrl[idx] = u;
+                    store_nt(&ctrl[idx], u);
                     if (HAS_V) {
                         const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, h.s, 1u, a.seed_lo, a.seed_hi);
                         V = clampT(vs + sigv * zv, Real(0), vmax);
-                        vctrl[idx] = V;
+                        store_nt(&vctrl[idx], V);
                     }
                 } else {  // the noise-free nominal (and idle lanes past it)
                     u.x = clampT(us[0], tmin, tmax);
@@ -1544,8 +1563,8 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
             auto put = [&](const int k, const int j, const R4 u, const Real V) {
                 if (sampled) {
                     const size_t idx = (size_t)k * (size_t)K + (size_t)m;
-                    ctrl[idx] = u;
-                    if (HAS_V) vctrl[idx] = V;
+                    store_nt(&ctrl[idx], u);
+                    if (HAS_V) store_nt(&vctrl[idx], V);
                 }
                 if (HAS_V) s_v[c % 5][j][lane] = V;
                 if (RATE) s_u[c % 5][j][lane] = u;
