@@ -152,8 +152,8 @@ typedef struct {
 } mppi_warm;
 
 /* Create a solver context.  Validates every argument (K, N, dt, lambda, sigma,
- * objective and the data it needs: G >= 1 gates, P >= 2 path points, R >= 1
- * reference rows), copies the problem data to the device and allocates all
+ * objective and the data it needs: 1..MPPI_G_MAX gates, P >= 2 path points,
+ * R >= 1 reference rows), copies the problem data to the device and allocates all
  * device buffers: the N x K x 4 sample tensor (step-major: sample m of step k
  * at element (k*K + m)*4), K costs, the per-tile cost minima and the
  * warm-start state.  stream is a hipStream_t (NULL: the library creates a non-blocking
