@@ -312,11 +312,18 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, large-solve and serving measurements")
     ap.add_argument("--serving-seconds", type=float, default=60.0)
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the large solve (K = 262144, N = 200) and print its figures; "
+                         "for profiling its kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.large_only:
+        print(json.dumps({"large": large_bench(steps=2)}), flush=True)
+        return
 
     import torch
     from paper_2509_14726_amd import mppi as M
