@@ -44,12 +44,8 @@ TRAFFIC_KIB = {"k_rollout4": (216.5, 12836.4), "k_final": (6578.0, 6.6)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
 
-def rollout_kernel(K: int) -> str:
-    """The rollout kernel the library launches for K samples (its layout rule,
-    or the MPPI_ROLLOUT_WAVES override)."""
-    tiles = (K + 1 + 63) // 64
-    env = os.environ.get("MPPI_ROLLOUT_WAVES", "")
-    waves = int(env) if env in ("1", "2", "3", "4") else (4 if tiles < 1024 else 1)
+def rollout_kernel(waves: int) -> str:
+    """The rollout kernel of a layout (the solve report names the layout)."""
     return ROLLOUT_KERNELS[waves]
 
 
@@ -300,6 +296,48 @@ def large_bench(steps: int = 5):
             "average_GBps": avg_bytes / (float(kern[2]) * 1e-3) / 1e9}
 
 
+def layout_sweep(steps: int = 30):
+    """Device-driven solve time of every rollout layout (forced with
+    MPPI_ROLLOUT_WAVES) around the automatic rule's crossover: the four-wave
+    workgroups run one per CU, so past two rounds (2 x 256 tiles of 64
+    samples) one wave per 64 samples wins."""
+    import torch
+    from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import synth
+    stream = torch.cuda.current_stream()
+    rows = []
+    for N in (50, 100, 200):
+        for K in (8192, 16383, 16384, 32767, 32768, 65000):
+            row = {"K": K, "N": N, "tiles": (K + 64) // 64}
+            for waves in ("1", "2", "3", "4", ""):
+                os.environ["MPPI_ROLLOUT_WAVES"] = waves
+                w = synth.single_solve_workload(K=K, N=N, seed=2)
+                sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32,
+                              stream=stream.cuda_stream)
+                req = torch.zeros((steps + 5, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+                req[:, :13] = torch.from_numpy(w["x0"]).cuda()
+                req[:, 13] = torch.arange(steps + 5, dtype=torch.float64, device="cuda") * w["params"]["dt"]
+                u0 = torch.zeros((steps + 5, 4), dtype=torch.float64, device="cuda")
+                for i in range(5):
+                    sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for i in range(5, steps + 5):
+                    sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
+                e1.record(stream)
+                torch.cuda.synchronize()
+                st, info = sv.read_info()
+                assert st == M.OK, info
+                row["auto" if waves == "" else f"waves{waves}_us"] = (
+                    info["rollout_waves"] if waves == "" else 1e3 * e0.elapsed_time(e1) / steps)
+                sv.close()
+            os.environ.pop("MPPI_ROLLOUT_WAVES", None)
+            print(json.dumps(row), flush=True)
+            rows.append(row)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +350,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, large-solve and serving measurements")
     ap.add_argument("--serving-seconds", type=float, default=60.0)
+    ap.add_argument("--layout-sweep", action="store_true",
+                    help="time every rollout layout over K and N around the automatic choice and exit")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the large solve (K = 262144, N = 200) and print its figures; "
                          "for profiling its kernels")
@@ -321,7 +361,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.layout_sweep:
+        import torch
+        torch.cuda.set_stream(torch.cuda.Stream(torch.device("cuda:0")))
+        layout_sweep()
+        return
     if args.large_only:
+        import torch
+        # the extras time on the current stream: make it one of our own
+        torch.cuda.set_stream(torch.cuda.Stream(torch.device("cuda:0")))
         print(json.dumps({"large": large_bench(steps=2)}), flush=True)
         return
 
@@ -369,6 +417,7 @@ def main():
     kern_ms, n_prof = solver.read_profile()
     st, info = solver.read_info()
     assert st == M.OK, info
+    rk = rollout_kernel(info["rollout_waves"])
     assert torch.isfinite(u0).all().item()
 
     K, N = args.K, args.N
@@ -400,8 +449,8 @@ def main():
         "kernels_ms": {"sample": float(kern_ms[0]), "rollout": roll_ms, "average": float(kern_ms[2]),
                        "solves_timed": n_prof},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(rollout_kernel(K)),
-                     "kernel": rollout_kernel(K), "flops_per_launch": flops},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(rk),
+                     "kernel": rk, "flops_per_launch": flops},
         # the weighted average streams the sample tensor once: HBM-bound
         "average_kernel": {"bound": "hbm", "kernel": "k_final", "bytes_per_launch": avg_bytes,
                            "achieved": avg_bytes / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,

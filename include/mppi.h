@@ -133,7 +133,8 @@ typedef struct {
     int32_t i0;            /* tracking: reference row of the initial state      */
     int32_t shift;         /* steps the previous solution was shifted by        */
     uint32_t solve_index;  /* Philox counter word of this solve                 */
-    uint32_t pad_;
+    int32_t rollout_waves; /* rollout layout of the context's own solves: waves
+                              per 64-sample tile (see mppi_batch_cfg)           */
 } mppi_info;
 
 /* Warm-start state inherited by the next solve (checkpoint / restore). */
@@ -231,8 +232,9 @@ typedef struct {
                                   (sampling joins the rollout) or 4 (four-stage
                                   pipeline: sampling with body rates, attitude,
                                   translation, sampling with position costs);
-                                  0: automatic (4 when the batch has fewer tiles
-                                  than four per CU, else 1) */
+                                  0: automatic (4 for at most one 64-sample
+                                  tile per CU, 2 for at most two, else 1;
+                                  the same rule picks a context's layout) */
     int32_t rollout_groups;    /* persistent rollout workgroups; 0: automatic    */
     int32_t sample_groups;     /* workgroups of the sample and reduction kernels;
                                   0: automatic                                   */

@@ -177,14 +177,22 @@ static void plan_layout(mppi_ctx *c)
     KArgs &a = c->args;
     const int K = c->K;
     a.n_tiles = (K + 1 + 63) / 64;
-    // Rollout layout: with fewer 64-sample tiles than SIMDs (1024 on MI355X)
-    // the chip is latency bound and splitting each tile's step over four
-    // pipelined waves (sampling with body rates, attitude, translation,
-    // sampling with position costs), one per SIMD, shortens each step; with
-    // more tiles, one wave per 64 samples issues fewer instructions in total.
-    // The environment variable MPPI_ROLLOUT_WAVES (1..4) overrides the choice.
-    const int waves = (K + 1 + 63) / 64;
-    a.rollout_waves = waves < 1024 ? 4 : 1;
+    // Rollout layout: with few 64-sample tiles the chip is latency bound and
+    // splitting each tile's step over four pipelined waves (sampling with body
+    // rates, attitude, translation, sampling with position costs), one per
+    // SIMD, shortens each step.  Its LDS rings hold one such workgroup per CU,
+    // so past one tile per CU the tiles would run in rounds; up to two tiles
+    // per CU the two-wave split (attitude | translation, two workgroups per
+    // CU) runs them in one round, and beyond that one wave per 64 samples,
+    // which issues the fewest instructions, keeps the whole chip busy
+    // (measured on 256 CUs for N = 50, 100 and 200 at 129, 256, 257, 512,
+    // 513 and 1016 tiles).  The environment variable MPPI_ROLLOUT_WAVES
+    // (1..4) overrides the choice.
+    int n_cu = 0, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n_cu < 1) n_cu = 256;
+    a.rollout_waves = a.n_tiles <= n_cu ? 4 : (a.n_tiles <= 2 * n_cu ? 2 : 1);
     if (const char *e = getenv("MPPI_ROLLOUT_WAVES")) {
         if (e[0] >= '1' && e[0] <= '4') a.rollout_waves = e[0] - '0';
     }
@@ -423,7 +431,7 @@ static mppi_status copy_info(mppi_ctx *ctx, const DevResult &r, mppi_info *info)
         info->i0 = r.i0;
         info->shift = r.shift;
         info->solve_index = r.s;
-        info->pad_ = 0;
+        info->rollout_waves = ctx->args.rollout_waves;
     }
     if (r.status == ST_NONFINITE)
         return fail(ctx, MPPI_E_NONFINITE, "every sample cost was non-finite; warm state kept");
@@ -670,8 +678,12 @@ static void resolve_cfg(mppi_batch *b)
 {
     mppi_batch_cfg &c = b->cfg;
     int waves = c.rollout_waves;
-    if (waves < 1 || waves > 4) waves = b->total_tiles < 4 * b->n_cu ? 4 : 1;
-    int rg = c.rollout_groups > 0 ? c.rollout_groups : (waves >= 2 ? b->n_cu : 8 * b->n_cu);
+    if (waves < 1 || waves > 4)
+        waves = b->total_tiles <= b->n_cu ? 4 : (b->total_tiles <= 2 * b->n_cu ? 2 : 1);
+    // persistent rollout workgroups: one four- or three-wave workgroup per CU
+    // (their LDS rings), two two-wave ones, eight one-wave ones
+    int rg = c.rollout_groups > 0 ? c.rollout_groups
+                                  : (waves >= 3 ? b->n_cu : (waves == 2 ? 2 * b->n_cu : 8 * b->n_cu));
     int sg = c.sample_groups > 0 ? c.sample_groups : 4 * b->n_cu;
     for (auto &g : b->groups) {
         g.launch.objective = g.objective;

@@ -256,3 +256,26 @@ def test_large_solve_fp32_with_fp64_average(lam):
     st = solve_and_compare(dev, orc, w["x0"], 0.0, M.FP32)
     say("  err_J", st["err_J"], "err_U", st["err_U"], "e2e", st["err_U_e2e"], "ambiguous", st["n_amb"])
     dev.close()
+
+
+def test_automatic_layout_rule(monkeypatch):
+    """Four waves per tile up to one tile per CU, the two-wave split up to
+    two, one wave per 64 samples beyond; the solve report names the layout,
+    and the environment override wins."""
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    monkeypatch.delenv("MPPI_ROLLOUT_WAVES", raising=False)
+    for K, want in ((100, 4), (n_cu * 64 - 1, 4), (n_cu * 64, 2), (2 * n_cu * 64 - 1, 2), (2 * n_cu * 64, 1)):
+        say("layout rule K", K, "CUs", n_cu)
+        w = _workload(K, 8, seed=3)
+        dev = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32)
+        dev.solve(w["x0"], 0.0)
+        st, info = dev.read_info()
+        assert st == M.OK and info["rollout_waves"] == want, (K, info["rollout_waves"])
+        dev.close()
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "2")
+    w = _workload(100, 8, seed=3)
+    dev = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32)
+    dev.solve(w["x0"], 0.0)
+    assert dev.read_info()[1]["rollout_waves"] == 2
+    dev.close()
