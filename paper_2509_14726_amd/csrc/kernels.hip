@@ -2112,10 +2112,12 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     // head values for the report and the hand-over (block of step 0)
     const bool fr = head && gate && tid <= N && tid < 256 && a.front8[tid] != 0;
     const bool fr_last = head && gate && tid == 0 && N >= 256 && a.front8[256] != 0;
-    double rep_Jnom = 0.0, rep_theta0 = 0.0, rep_t = 0.0, rep_x0[13];
+    // (spread over the lanes of wave 0: lane 5 the report's head fields,
+    // lane 6 the warm-start fields, lanes 7..19 one state component each)
+    double rep_Jnom = 0.0, rep_theta0 = 0.0, rep_t = 0.0, rep_x = 0.0;
     int32_t rep_g0 = 0, rep_i0 = 0, rep_shift = 0;
     uint32_t rep_s = 0;
-    if (head && tid == 0) {
+    if (head && (tid == 5 || tid == 6)) {
         rep_Jnom = cur->J_nom;
         rep_theta0 = cur->theta0;
         rep_t = cur->t_now;
@@ -2123,8 +2125,8 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
         rep_i0 = cur->i0;
         rep_shift = cur->shift;
         rep_s = cur->s;
-        for (int i = 0; i < 13; ++i) rep_x0[i] = cur->x0[i];
     }
+    if (head && tid >= 7 && tid < 20) rep_x = cur->x0[tid - 7];
     // J_min
     for (int off = 32; off > 0; off >>= 1) {
         const Real o = __shfl_xor(mn, off, 64);
@@ -2203,17 +2205,18 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     } else if (tid < kMaskWords && ok) {
         w->allow[tid] = 0xffffffffu;
     }
-    if (tid == 0) {
-        DevResult *r = a.res;
-        for (int i = 0; i < 4; ++i) {
-            const double u0 = ok ? (double)(s_tot[i] / den) : (double)NAN;
-            r->u0[i] = u0;
-            if (a.u0_out) a.u0_out[i] = u0;
-        }
+    // the report and the warm-start hand-over, one group of fields per lane
+    DevResult *r = a.res;
+    if (tid < 4) {
+        const double u0 = ok ? (double)(s_tot[tid] / den) : (double)NAN;
+        r->u0[tid] = u0;
+        if (a.u0_out) a.u0_out[tid] = u0;
+    } else if (tid == 4) {
         r->J_min = (double)jmin;
         r->S = (double)den;
         r->S2 = (double)den2;
         r->ess = ok ? (double)den * (double)den / (double)den2 : 0.0;
+    } else if (tid == 5) {
         r->J_nom = rep_Jnom;
         r->theta0 = rep_theta0;
         r->status = ok ? ST_OK : ST_NONFINITE;
@@ -2221,15 +2224,15 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
         r->i0 = rep_i0;
         r->shift = rep_shift;
         r->s = rep_s;
-        if (ok) {
-            w->warm = 1;
-            w->g0 = rep_g0;
-            w->s = rep_s + 1u;
-            w->N = N;
-            w->t_prev = rep_t;
-            w->theta0 = rep_theta0;
-            for (int i = 0; i < 13; ++i) w->x_prev[i] = rep_x0[i];
-        }
+    } else if (tid == 6 && ok) {
+        w->warm = 1;
+        w->g0 = rep_g0;
+        w->s = rep_s + 1u;
+        w->N = N;
+        w->t_prev = rep_t;
+        w->theta0 = rep_theta0;
+    } else if (tid >= 7 && tid < 20 && ok) {
+        w->x_prev[tid - 7] = rep_x;
     }
 }
 
