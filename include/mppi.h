@@ -231,9 +231,12 @@ typedef struct {
                                   kernel), 2 (attitude / translation split), 3
                                   (sampling joins the rollout) or 4 (four-stage
                                   pipeline: sampling with body rates, attitude,
-                                  translation, sampling with position costs);
-                                  0: automatic (4 for at most one 64-sample
-                                  tile per CU, 2 for at most two, else 1;
+                                  translation, sampling with position costs;
+                                  chunks of 4 steps with one workgroup per CU,
+                                  of 2 with two, the same results);
+                                  0: automatic (binary32: 4 for at most two
+                                  64-sample tiles per CU, else 1; binary64: 4
+                                  for at most one, 2 for at most two, else 1;
                                   the same rule picks a context's layout) */
     int32_t rollout_groups;    /* persistent rollout workgroups; 0: automatic    */
     int32_t sample_groups;     /* workgroups of the sample and reduction kernels;

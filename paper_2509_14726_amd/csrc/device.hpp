@@ -61,7 +61,8 @@ struct DevResult {
 struct KArgs {
     int32_t K, N, G, P, R, objective;
     int32_t C, real_bytes;      // channels (4, 5 contouring); bytes of Real (for ws_layout)
-    int32_t n_tiles, pad2;      // 64-sample rollout tiles: ceil((K + 1) / 64)
+    int32_t n_tiles;            // 64-sample rollout tiles: ceil((K + 1) / 64)
+    int32_t ring4_b;            // chunk of the four-wave rollout: 4 or 2 steps (binary32)
     int32_t proj_window, has_drag;
     int32_t rollout_waves, pad_;  // 1: one wave per 64 samples; 2: attitude and translation on two waves
     uint32_t seed_lo, seed_hi;

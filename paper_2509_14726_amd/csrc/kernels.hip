@@ -1427,16 +1427,15 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
 //   wave 2  integrates position and velocity over chunk c-3 from the stage
 //           attitudes, with the tracking terms of position and velocity.
 // Each stage hands its stage values on through LDS rings; every quantity is
-// computed with the same operations as in the three-wave layout.
-template <typename Real> struct Ring4;
-template <> struct Ring4<float> { static constexpr int B = 4; };
-template <> struct Ring4<double> { static constexpr int B = 2; };
-
-template <int OBJ, typename Real>
+// computed with the same operations as in the three-wave layout, whatever the
+// chunk size B: the chunking only moves the barriers.  B = 4 for binary32
+// with one workgroup per CU; B = 2 halves the rings so that two workgroups
+// share a CU (binary32 with more tiles than CUs; always for binary64, whose
+// rings are twice as large).
+template <int OBJ, typename Real, int B>
 __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const HeadVals &h)
 {
     typedef typename Vec4<Real>::T R4;
-    constexpr int B = Ring4<Real>::B;
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
     constexpr bool RATE = OBJ != OBJ_GATE;
     constexpr bool POS = OBJ != OBJ_TRACK;        // position costs in wave 3
@@ -2036,12 +2035,12 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
     __syncthreads();
 }
 
-template <int OBJ, typename Real> __global__ __launch_bounds__(256) void k_rollout4(KArgs a)
+template <int OBJ, typename Real, int B> __global__ __launch_bounds__(256) void k_rollout4(KArgs a)
 {
     __shared__ HeadVals h;
     compute_head(a, h);
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_head(a, h);
-    rollout4_body<OBJ, Real>(a, blockIdx.x, h);
+    rollout4_body<OBJ, Real, B>(a, blockIdx.x, h);
 }
 
 template <int OBJ, typename Real> __global__ __launch_bounds__(192) void k_rollout3(KArgs a)
@@ -2350,7 +2349,7 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(192) void kb_roll
     }
 }
 
-template <int OBJ, typename Real> __global__ __launch_bounds__(256) void kb_rollout4(BArgs b)
+template <int OBJ, typename Real, int B> __global__ __launch_bounds__(256) void kb_rollout4(BArgs b)
 {
     __shared__ KArgs s_a;
     __shared__ HeadVals h;
@@ -2369,7 +2368,7 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(256) void kb_roll
         const int blk = u - b.tile_prefix[item];
         compute_head(s_a, h);
         if (blk == 0 && threadIdx.x == 0) publish_head(s_a, h);
-        rollout4_body<OBJ, Real>(s_a, blk, h);
+        rollout4_body<OBJ, Real, B>(s_a, blk, h);
     }
 }
 
@@ -2395,9 +2394,16 @@ static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
     if (L.rollout_waves < 3)
         hipLaunchKernelGGL((kb_sample<Real, HAS_V>), dim3(L.sample_groups), dim3(256), 0, st, b);
-    if (L.rollout_waves == 4)
-        hipLaunchKernelGGL((kb_rollout4<OBJ, Real>), dim3(L.rollout_groups), dim3(256), 0, st, b);
-    else if (L.rollout_waves == 3)
+    if (L.rollout_waves == 4) {
+        if constexpr (sizeof(Real) == 4) {
+            if (L.ring4_b == 4)
+                hipLaunchKernelGGL((kb_rollout4<OBJ, Real, 4>), dim3(L.rollout_groups), dim3(256), 0, st, b);
+            else
+                hipLaunchKernelGGL((kb_rollout4<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(256), 0, st, b);
+        } else {
+            hipLaunchKernelGGL((kb_rollout4<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(256), 0, st, b);
+        }
+    } else if (L.rollout_waves == 3)
         hipLaunchKernelGGL((kb_rollout3<OBJ, Real>), dim3(L.rollout_groups), dim3(192), 0, st, b);
     else if (L.rollout_waves == 2)
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(128), 0, st, b);
@@ -2457,14 +2463,23 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     if (ev) (void)hipEventRecord(ev[0], st);
     if (a.rollout_waves < 3) hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);
-    if (a.rollout_waves == 4)
-        hipLaunchKernelGGL((k_rollout4<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(256), 0, st, a);
-    else if (a.rollout_waves == 3)
-        hipLaunchKernelGGL((k_rollout3<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(192), 0, st, a);
-    else if (a.rollout_waves == 2)
-        hipLaunchKernelGGL((k_rollout_split<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(128), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_rollout<OBJ, Real>), dim3((a.K + 1 + 63) / 64), dim3(64), 0, st, a);
+    const dim3 gt((a.K + 1 + 63) / 64);
+    if (a.rollout_waves == 4) {
+        if constexpr (sizeof(Real) == 4) {
+            if (a.ring4_b == 4)
+                hipLaunchKernelGGL((k_rollout4<OBJ, Real, 4>), gt, dim3(256), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_rollout4<OBJ, Real, 2>), gt, dim3(256), 0, st, a);
+        } else {
+            hipLaunchKernelGGL((k_rollout4<OBJ, Real, 2>), gt, dim3(256), 0, st, a);
+        }
+    } else if (a.rollout_waves == 3) {
+        hipLaunchKernelGGL((k_rollout3<OBJ, Real>), gt, dim3(192), 0, st, a);
+    } else if (a.rollout_waves == 2) {
+        hipLaunchKernelGGL((k_rollout_split<OBJ, Real>), gt, dim3(128), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_rollout<OBJ, Real>), gt, dim3(64), 0, st, a);
+    }
     if (ev) (void)hipEventRecord(ev[2], st);
     hipError_t e = (acc64 || sizeof(Real) == 8) ? launch_average_t<Real, double, HAS_V>(a, st)
                                                 : launch_average_t<Real, float, HAS_V>(a, st);

@@ -21,6 +21,7 @@ struct BatchLaunch {
     int objective;
     bool fp64, acc64;
     int rollout_waves;    // 1..4 (see mppi_batch_cfg)
+    int ring4_b;          // four-wave chunk (binary32): 4, one workgroup per CU; 2, two
     int rollout_groups;   // persistent rollout workgroups
     int sample_groups;    // grid-stride workgroups of the sample kernel
     int final_groups;     // grid-stride workgroups of the weighted-average kernel

@@ -180,22 +180,26 @@ static void plan_layout(mppi_ctx *c)
     // Rollout layout: with few 64-sample tiles the chip is latency bound and
     // splitting each tile's step over four pipelined waves (sampling with body
     // rates, attitude, translation, sampling with position costs), one per
-    // SIMD, shortens each step.  Its LDS rings hold one such workgroup per CU,
-    // so past one tile per CU the tiles would run in rounds; up to two tiles
-    // per CU the two-wave split (attitude | translation, two workgroups per
-    // CU) runs them in one round, and beyond that one wave per 64 samples,
-    // which issues the fewest instructions, keeps the whole chip busy
-    // (measured on 256 CUs for N = 50, 100 and 200 at 129, 256, 257, 512,
-    // 513 and 1016 tiles).  The environment variable MPPI_ROLLOUT_WAVES
-    // (1..4) overrides the choice.
+    // SIMD, shortens each step.  With chunks of 4 steps its LDS rings hold one
+    // such workgroup per CU; with chunks of 2 (binary32) two share a CU, which
+    // takes up to two tiles per CU in one round.  Beyond that one wave per 64
+    // samples, which issues the fewest instructions, keeps the whole chip
+    // busy.  Binary64 rings (chunks of 2) fit one workgroup per CU, so from
+    // one to two tiles per CU the two-wave split (attitude | translation, two
+    // workgroups per CU) takes over there.  Measured on 256 CUs for N = 50,
+    // 100 and 200 at 129 to 1016 tiles.  The environment variable
+    // MPPI_ROLLOUT_WAVES (1..4) overrides the layout.
     int n_cu = 0, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (n_cu < 1) n_cu = 256;
-    a.rollout_waves = a.n_tiles <= n_cu ? 4 : (a.n_tiles <= 2 * n_cu ? 2 : 1);
+    if (a.n_tiles <= n_cu) a.rollout_waves = 4;
+    else if (a.n_tiles <= 2 * n_cu) a.rollout_waves = c->fp64 ? 2 : 4;
+    else a.rollout_waves = 1;
     if (const char *e = getenv("MPPI_ROLLOUT_WAVES")) {
         if (e[0] >= '1' && e[0] <= '4') a.rollout_waves = e[0] - '0';
     }
+    a.ring4_b = (!c->fp64 && a.n_tiles <= n_cu) ? 4 : 2;
 }
 
 extern "C" {
@@ -678,18 +682,29 @@ static void resolve_cfg(mppi_batch *b)
 {
     mppi_batch_cfg &c = b->cfg;
     int waves = c.rollout_waves;
-    if (waves < 1 || waves > 4)
-        waves = b->total_tiles <= b->n_cu ? 4 : (b->total_tiles <= 2 * b->n_cu ? 2 : 1);
-    // persistent rollout workgroups: one four- or three-wave workgroup per CU
-    // (their LDS rings), two two-wave ones, eight one-wave ones
-    int rg = c.rollout_groups > 0 ? c.rollout_groups
-                                  : (waves >= 3 ? b->n_cu : (waves == 2 ? 2 * b->n_cu : 8 * b->n_cu));
+    const int cu = b->n_cu, tiles = b->total_tiles;
+    if (waves < 1 || waves > 4) waves = tiles <= cu ? 4 : (tiles <= 2 * cu ? (b->fp64 ? 2 : 4) : 1);
+    // four-wave chunk: the contexts' own when they all agree (a served solve
+    // then runs exactly its stand-alone kernel), else by the batch's tiles
+    int ring = b->ctxs[0]->args.ring4_b;
+    for (const mppi_ctx *x : b->ctxs)
+        if (x->args.ring4_b != ring) ring = 0;
+    if (ring == 0) ring = (!b->fp64 && tiles <= cu) ? 4 : 2;
+    // persistent rollout workgroups: what fits one CU times the CUs (one
+    // four-wave workgroup with 4-step chunks or in binary64, two with 2-step
+    // chunks in binary32, one three-wave, two two-wave, eight one-wave)
+    int per_cu = 8;
+    if (waves == 4) per_cu = (!b->fp64 && ring == 2) ? 2 : 1;
+    else if (waves == 3) per_cu = 1;
+    else if (waves == 2) per_cu = 2;
+    int rg = c.rollout_groups > 0 ? c.rollout_groups : per_cu * cu;
     int sg = c.sample_groups > 0 ? c.sample_groups : 4 * b->n_cu;
     for (auto &g : b->groups) {
         g.launch.objective = g.objective;
         g.launch.fp64 = b->fp64;
         g.launch.acc64 = g.acc64;
         g.launch.rollout_waves = waves;
+        g.launch.ring4_b = ring;
         g.launch.rollout_groups = rg;
         g.launch.sample_groups = sg;
         // kFinalThreads-thread workgroups, two per CU

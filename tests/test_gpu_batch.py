@@ -138,3 +138,42 @@ def test_autotuner_picks_a_valid_shape():
     assert best["rollout_waves"] in (1, 2, 3, 4) and best["rollout_groups"] > 0 and ms > 0
     assert B.get_cfg()["rollout_waves"] == best["rollout_waves"]
     B.close()
+
+
+def test_chunk_sizes_give_the_same_bits(monkeypatch):
+    """Four-wave rollouts with 4-step chunks and with 2-step chunks compute
+    the same bits: the small contexts run alone with 4-step chunks (at most
+    one tile per CU); the first has more tiles than CUs and so 2-step chunks,
+    the contexts disagree, and the batch (more tiles than CUs in total) runs
+    them all with 2-step chunks, two workgroups per CU."""
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "4")
+    say("chunk sizes", "CUs", n_cu)
+    inst = []
+    for i, (K, obj) in enumerate([(n_cu * 64 + 100, "gate"), (2000, "contour"), (3000, "track"), (700, "gate")]):
+        inst.append(synth.single_solve_workload(K=K, N=24, objective=obj, seed=300 + i, track_seed=300 + i,
+                                                **{"lambda": 20.0}))
+    solo = [solver_for(w, M.FP32) for w in inst]
+    bat = [solver_for(w, M.FP32) for w in inst]
+    B = M.Batch(bat, rollout_waves=4, use_graph=True)
+    n = len(inst)
+    reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    u0s = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    for step in range(2):
+        for i, w in enumerate(inst):
+            reqs[i, :13] = torch.from_numpy(w["x0"])
+            reqs[i, 13] = step * w["params"]["dt"]
+        torch.cuda.synchronize()
+        B.solve_device(reqs.data_ptr(), u0s.data_ptr())
+        torch.cuda.synchronize()
+        got = u0s.cpu().numpy()
+        for i, w in enumerate(inst):
+            u0, U, info = solo[i].solve(w["x0"], step * w["params"]["dt"])
+            assert np.array_equal(got[i], u0), (step, i)
+            Jb, _ = bat[i].read_samples()
+            Js, _ = solo[i].read_samples()
+            assert np.array_equal(Jb, Js), (step, i)
+    B.close()
+    for s in solo + bat:
+        s.close()

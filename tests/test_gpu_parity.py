@@ -259,23 +259,45 @@ def test_large_solve_fp32_with_fp64_average(lam):
 
 
 def test_automatic_layout_rule(monkeypatch):
-    """Four waves per tile up to one tile per CU, the two-wave split up to
-    two, one wave per 64 samples beyond; the solve report names the layout,
-    and the environment override wins."""
+    """Four waves per tile up to two tiles per CU in binary32 (chunks of 4
+    steps up to one tile per CU, of 2 steps beyond), in binary64 up to one
+    tile per CU and the two-wave split up to two; one wave per 64 samples
+    beyond.  The solve report names the layout, and the environment override
+    wins."""
     import torch
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     monkeypatch.delenv("MPPI_ROLLOUT_WAVES", raising=False)
-    for K, want in ((100, 4), (n_cu * 64 - 1, 4), (n_cu * 64, 2), (2 * n_cu * 64 - 1, 2), (2 * n_cu * 64, 1)):
-        say("layout rule K", K, "CUs", n_cu)
+    cases = [(M.FP32, 100, 4), (M.FP32, n_cu * 64 - 1, 4), (M.FP32, n_cu * 64, 4),
+             (M.FP32, 2 * n_cu * 64 - 1, 4), (M.FP32, 2 * n_cu * 64, 1),
+             (M.FP64, n_cu * 64 - 1, 4), (M.FP64, n_cu * 64, 2), (M.FP64, 2 * n_cu * 64, 1)]
+    for prec, K, want in cases:
+        say("layout rule K", K, "precision", prec, "CUs", n_cu)
         w = _workload(K, 8, seed=3)
-        dev = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32)
+        dev = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=prec)
         dev.solve(w["x0"], 0.0)
         st, info = dev.read_info()
-        assert st == M.OK and info["rollout_waves"] == want, (K, info["rollout_waves"])
+        assert st == M.OK and info["rollout_waves"] == want, (K, prec, info["rollout_waves"])
         dev.close()
     monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "2")
     w = _workload(100, 8, seed=3)
     dev = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32)
     dev.solve(w["x0"], 0.0)
     assert dev.read_info()[1]["rollout_waves"] == 2
+    dev.close()
+
+
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
+def test_four_waves_with_two_step_chunks(objective):
+    """More tiles than CUs: binary32 four-wave rollouts with 2-step chunks,
+    two workgroups per CU, against the oracle (a cold and a warm solve)."""
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    K = n_cu * 64 + 1000
+    say("four waves, 2-step chunks", objective, "K", K, "N 30")
+    w = _workload(K, 30, objective=objective, seed=8, track_seed=3, **{"lambda": 25.0})
+    dev, orc = build_pair(w, M.FP32, n_threads=16)
+    st = solve_and_compare(dev, orc, w["x0"], 0.0, M.FP32)
+    assert st["info"]["rollout_waves"] == 4
+    say("  err_J", st["err_J"], "err_U", st["err_U"], "ambiguous", st["n_amb"])
+    st = solve_and_compare(dev, orc, w["x0"], w["params"]["dt"], M.FP32)
     dev.close()
