@@ -38,9 +38,9 @@ PEAK_HBM_GBPS = 8000.0
 # They hold only for the device sources they were taken on (sha256 of
 # kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order); for any
 # other source the traffic is reported as null.
-TRAFFIC_SOURCES = "25f186484c355eacff3a08b90ce364759e2ae9df33dd3190e17bc53259ba2c58"
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.2, 262144.0 / 262144.0
-TRAFFIC_KIB = {"k_rollout4": (217.9, 12836.4), "k_final": (6574.8, 6.6)}
+TRAFFIC_SOURCES = "8b6a76e36c420f353d2e1baef514e474f3b36d7ef8eedfd99aaaf29e70de5235"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.0, 262144.0 / 262144.0
+TRAFFIC_KIB = {"k_rollout4": (225.5, 12836.4), "k_final": (6578.0, 6.6)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
 
