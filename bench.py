@@ -133,7 +133,9 @@ def closed_loop_race(steps: int = 1000):
     path; tracking of the 5 m/s reference).  Between solves the FP64 host
     plant (RK4, 4 substeps) advances with the first input of each solve, so
     every solve goes through the host entry point (upload, solve, download).
-    Reports the host-observed solve latency and what the flight achieved.
+    Reports the host-observed solve latency and the race metrics of the
+    flight (paper_2509_14726_amd.race: waypoint pass errors, gate passes in
+    order and lap time, tracking error, total-thrust profile).
 
     The race samples with sigma = 0.15 N and lambda = 10: with thrust as the
     sampled input, i.i.d. noise of 1 N per rotor and 20 ms step spins this
@@ -142,6 +144,7 @@ def closed_loop_race(steps: int = 1000):
     and the loop tumbles; the single-solve workload keeps sigma = 1 N."""
     import numpy as np
     from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import race
     from paper_2509_14726_amd import synth
     out = {}
     for obj in ("gate", "contour", "track"):
@@ -151,45 +154,36 @@ def closed_loop_race(steps: int = 1000):
                       path_len=w.get("path_len", 0.0), xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0),
                       precision=M.FP32)
         dt = w["params"]["dt"]
-        x = w["x0"].copy()
-        lat, gates, theta_adv, err = [], 0, 0.0, []
-        g_prev, th_prev = None, None
-        status = "ok"
-        try:
-            for i in range(steps):
-                t0 = time.perf_counter()
-                u0, _, info = sv.solve(x, i * dt)
-                lat.append(time.perf_counter() - t0)
-                if obj == "gate":
-                    if g_prev is not None and info["g0"] != g_prev:
-                        gates += 1
-                    g_prev = info["g0"]
-                if obj == "contour":
-                    th = info["theta0"]
-                    if th_prev is not None:
-                        d = th - th_prev
-                        if d < -0.5 * w["path_len"]:
-                            d += w["path_len"]
-                        theta_adv += d
-                    th_prev = th
-                if obj == "track":
-                    r = min(int(round(i * dt / w["ref_dt"])), len(w["xref"]) - 1)
-                    err.append(float(np.linalg.norm(x[:3] - w["xref"][r, :3])))
-                x = M.plant_step(w["quad"], x, u0, dt, 4)
-        except M.MppiError as e:
-            status = f"stopped at step {len(lat)}: {e}"
+        lat = []
+
+        def solve(x, t):
+            t0 = time.perf_counter()
+            u0, _, info = sv.solve(x, t, want_U=False)
+            lat.append(time.perf_counter() - t0)
+            return u0, info
+
+        fl = race.fly(solve, w["quad"], w["x0"], steps, dt, substeps=4)
         sv.close()
         lat = np.array(lat)
-        rec = {"steps": int(lat.size), "status": status, "sigma_N": 0.15, "lambda": 10.0,
+        rec = {"steps": int(lat.size),
+               "status": "ok" if fl["error"] is None else f"stopped at step {lat.size}: {fl['error']}",
+               "sigma_N": 0.15, "lambda": 10.0,
                "solve_ms_mean": float(lat.mean() * 1e3),
                "solve_ms_p99": float(np.percentile(lat, 99) * 1e3),
                "rollout_steps_per_s": 8192 * 100 / float(lat.mean())}
+        infos = fl["info"]
         if obj == "gate":
-            rec["gates_passed"] = gates
+            # switches of the controller's current gate (measured passes)
+            rec["gates_passed"] = int(sum(1 for a, b in zip(infos, infos[1:]) if b["g0"] != a["g0"]))
         if obj == "contour":
-            rec["arc_length_m"] = theta_adv
-        if obj == "track":
-            rec["pos_err_m_mean"] = float(np.mean(err)) if err else None
+            adv = 0.0
+            for a, b in zip(infos, infos[1:]):
+                d = b["theta0"] - a["theta0"]
+                if d < -0.5 * w["path_len"]:
+                    d += w["path_len"]
+                adv += d
+            rec["arc_length_m"] = adv
+        rec["race"] = race.score(fl, w, obj)
         out[obj] = rec
     return out
 

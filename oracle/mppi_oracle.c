@@ -317,14 +317,16 @@ static int get_bit(const uint32_t *mask, int j)
  *              theta_{k+1} = theta_k + V_k dt (mod L).
  * When front is non-NULL the rollout is the nominal one and bit j of front is
  * set when state j (j = 0..N) is in front of gate g0.                        */
-double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13],
-                        const double *U, const double *V, int32_t g0, const uint32_t *allow,
-                        const double u_prev[4], double v_prev, double theta0, int32_t i0,
-                        double *margin, uint32_t *front, uint32_t *front_amb)
+double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[13],
+                           const double *U, const double *V, int32_t g0, const uint32_t *allow,
+                           const double u_prev[4], double v_prev, double theta0, int32_t i0,
+                           double *margin, uint32_t *front, uint32_t *front_amb, double *abs_sum)
 {
     double x[13], xn[13];
     memcpy(x, x0, sizeof x);
     double J = 0.0;
+    double Jabs = 0.0; /* sum of the magnitudes of the terms added to J */
+#define ORC_ADD(t) do { const double t_ = (t); J += t_; Jabs += fabs(t_); } while (0)
     double mrg = INFINITY;
     int g = g0, passes = 0;
     const double *gate0 = c->gates ? c->gates + 4 * g0 : NULL;
@@ -345,11 +347,11 @@ double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13]
         if (c->objective == ORC_OBJ_TRACK) {
             int r = i0 + k < c->n_ref ? i0 + k : c->n_ref - 1;
             const double *xr = c->xref + 13 * r;
-            for (int i = 0; i < 13; ++i) J += c->Q[i] * (x[i] - xr[i]) * (x[i] - xr[i]);
+            for (int i = 0; i < 13; ++i) ORC_ADD(c->Q[i] * (x[i] - xr[i]) * (x[i] - xr[i]));
             const double *Up = k > 0 ? U + 4 * (k - 1) : u_prev;
             for (int i = 0; i < 4; ++i) {
                 double d = (Uk[i] - Up[i]) / c->dt;
-                J += c->R_dT[i] * d * d;
+                ORC_ADD(c->R_dT[i] * d * d);
             }
         } else if (c->objective == ORC_OBJ_CONTOUR) {
             double sr = theta / ds;
@@ -368,24 +370,24 @@ double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13]
             for (int d = 0; d < 3; ++d) e[d] = x[d] - pi_[d];
             double et = e[0] * t[0] + e[1] * t[1] + e[2] * t[2];
             for (int d = 0; d < 3; ++d) { el[d] = et * t[d]; ec[d] = e[d] - el[d]; }
-            J += c->q_l * (el[0] * el[0] + el[1] * el[1] + el[2] * el[2]);
-            J += c->q_c * (ec[0] * ec[0] + ec[1] * ec[1] + ec[2] * ec[2]);
-            for (int d = 0; d < 3; ++d) J += c->Q_w[d] * x[10 + d] * x[10 + d];
+            ORC_ADD(c->q_l * (el[0] * el[0] + el[1] * el[1] + el[2] * el[2]));
+            ORC_ADD(c->q_c * (ec[0] * ec[0] + ec[1] * ec[1] + ec[2] * ec[2]));
+            for (int d = 0; d < 3; ++d) ORC_ADD(c->Q_w[d] * x[10 + d] * x[10 + d]);
             double Vp = k > 0 ? V[k - 1] : v_prev;
             double dv = (V[k] - Vp) / c->dt;
-            J += c->r_dv * dv * dv;
+            ORC_ADD(c->r_dv * dv * dv);
             const double *Up = k > 0 ? U + 4 * (k - 1) : u_prev;
             for (int d = 0; d < 4; ++d) {
                 double dT = (Uk[d] - Up[d]) / c->dt;
-                J += c->R_dT[d] * dT * dT;
+                ORC_ADD(c->R_dT[d] * dT * dT);
             }
-            J -= c->mu * V[k];
+            ORC_ADD(-c->mu * V[k]);
             theta = wrap_len(theta + V[k] * c->dt, c->path_len);
         } else {
             /* near-gate term, Eq. (7), w.r.t. the current gate g0 */
             double d2 = sqdist3(x, gate0);
             double d = sqrt(d2);
-            if (d < c->r_near) J += c->q_near * d2;
+            if (d < c->r_near) ORC_ADD(c->q_near * d2);
             if (fabs(d - c->r_near) < mrg) mrg = fabs(d - c->r_near);
         }
 
@@ -394,9 +396,9 @@ double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13]
         if (c->objective == ORC_OBJ_GATE) {
             const double *gc = c->gates + 4 * g;
             /* progress term, Eq. (6), toward the gate targeted by state k */
-            J += sqdist3(xn, gc) - sqdist3(x, gc);
+            ORC_ADD(sqdist3(xn, gc) - sqdist3(x, gc));
         }
-        J += limit_cost(c, q, xn);
+        ORC_ADD(limit_cost(c, q, xn));
 
         if (c->objective == ORC_OBJ_GATE) {
             const double *gc = c->gates + 4 * g;
@@ -413,7 +415,7 @@ double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13]
     if (c->objective == ORC_OBJ_TRACK) {
         int r = i0 + c->N < c->n_ref ? i0 + c->N : c->n_ref - 1;
         const double *xr = c->xref + 13 * r;
-        for (int i = 0; i < 13; ++i) J += c->QN[i] * (x[i] - xr[i]) * (x[i] - xr[i]);
+        for (int i = 0; i < 13; ++i) ORC_ADD(c->QN[i] * (x[i] - xr[i]) * (x[i] - xr[i]));
     }
     if (front) {
         double s = (x[0] - gate0[0]) * cos(gate0[3]) + (x[1] - gate0[1]) * sin(gate0[3]);
@@ -421,7 +423,18 @@ double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13]
         set_bit(front_amb, c->N, fabs(s) < c->eps_dec);
     }
     if (margin) *margin = mrg;
+    if (abs_sum) *abs_sum = Jabs;
+#undef ORC_ADD
     return J;
+}
+
+double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13],
+                        const double *U, const double *V, int32_t g0, const uint32_t *allow,
+                        const double u_prev[4], double v_prev, double theta0, int32_t i0,
+                        double *margin, uint32_t *front, uint32_t *front_amb)
+{
+    return orc_rollout_cost_ex(c, q, x0, U, V, g0, allow, u_prev, v_prev, theta0, i0, margin, front,
+                               front_amb, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -512,18 +525,19 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
     double Jmin = INFINITY;
     int n_amb = 0;
     int nt = c->n_threads > 0 ? c->n_threads : 1;
-    double *Jv = out->J, *Mv = out->margin;
+    double *Jv = out->J, *Mv = out->margin, *Av = out->absJ;
 #pragma omp parallel num_threads(nt) reduction(+ : n_amb)
     {
         double Um[ORC_NMAX * 4], Vm[ORC_NMAX];
 #pragma omp for schedule(dynamic, 16)
         for (int m = 0; m < K; ++m) {
             orc_sample(c, q, Ustar, Vstar, (uint32_t)m, s, Um, Vm);
-            double mg;
-            double Jm = orc_rollout_cost(c, q, x0, Um, Vm, g0, allow, u_prev, v_prev, theta0, i0,
-                                         &mg, NULL, NULL);
+            double mg, am;
+            double Jm = orc_rollout_cost_ex(c, q, x0, Um, Vm, g0, allow, u_prev, v_prev, theta0, i0,
+                                            &mg, NULL, NULL, &am);
             if (Jv) Jv[m] = Jm;
             if (Mv) Mv[m] = mg;
+            if (Av) Av[m] = am;
             if (mg < c->eps_dec) n_amb += 1;
         }
     }

@@ -98,6 +98,7 @@ typedef struct {
     uint32_t allow[ORC_MASK_WORDS];     /* mask used by this solve                     */
     uint32_t front[ORC_MASK_WORDS];     /* nominal rollout states in front of gate g0  */
     uint32_t front_amb[ORC_MASK_WORDS]; /* front decisions within eps_dec of the plane */
+    double *absJ;    /* K   sum over a sample's cost terms of their magnitudes (may be NULL) */
 } orc_out;
 
 /* ---- building blocks (exported for the pin tests) ---------------------- */
@@ -115,6 +116,12 @@ double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13]
                         const double *U, const double *V, int32_t g0, const uint32_t *allow,
                         const double u_prev[4], double v_prev, double theta0, int32_t i0,
                         double *margin, uint32_t *front, uint32_t *front_amb);
+/* The same, also returning the sum of the magnitudes of the terms added to
+ * the cost (the scale of its rounding error). */
+double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[13],
+                           const double *U, const double *V, int32_t g0, const uint32_t *allow,
+                           const double u_prev[4], double v_prev, double theta0, int32_t i0,
+                           double *margin, uint32_t *front, uint32_t *front_amb, double *abs_sum);
 
 /* ---- one MPPI step --------------------------------------------------------
  * warm is read (inherited state) and, on success, replaced by the state the

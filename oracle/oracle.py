@@ -73,7 +73,7 @@ class Out(C.Structure):
                 ("g0", C.c_int32), ("i0", C.c_int32), ("shift", C.c_int32), ("n_amb", C.c_int32),
                 ("status", C.c_int32), ("pad_", C.c_int32),
                 ("allow", C.c_uint32 * MASK_WORDS), ("front", C.c_uint32 * MASK_WORDS),
-                ("front_amb", C.c_uint32 * MASK_WORDS)]
+                ("front_amb", C.c_uint32 * MASK_WORDS), ("absJ", C.POINTER(C.c_double))]
 
 
 _D = C.POINTER(C.c_double)
@@ -253,7 +253,8 @@ class Problem:
         J = np.zeros(K); w = np.zeros(K); U = np.zeros(4 * N); V = np.zeros(N)
         mg = np.zeros(K); Us = np.zeros(4 * N); Vs = np.zeros(N)
         o = Out()
-        o.J = _dp(J); o.w = _dp(w); o.U = _dp(U); o.V = _dp(V); o.margin = _dp(mg)
+        A = np.zeros(K)
+        o.J = _dp(J); o.w = _dp(w); o.U = _dp(U); o.V = _dp(V); o.margin = _dp(mg); o.absJ = _dp(A)
         o.Ustar = _dp(Us); o.Vstar = _dp(Vs)
         x0 = _arr(x0, 13)
         jr = _arr(J_rep, K) if J_rep is not None else None
@@ -263,7 +264,7 @@ class Problem:
                              float(t_now), _dp(jr),
                              rm.ctypes.data_as(C.POINTER(C.c_uint8)) if rm is not None else None,
                              C.byref(o))
-        return dict(status=st, J=J, w=w, U=U.reshape(N, 4), V=V, margin=mg,
+        return dict(status=st, J=J, w=w, U=U.reshape(N, 4), V=V, margin=mg, absJ=A,
                     Ustar=Us.reshape(N, 4), Vstar=Vs, J_min=o.J_min, S=o.S, ess=o.ess,
                     J_nom=o.J_nom, theta0=o.theta0, g0=o.g0, i0=o.i0, shift=o.shift,
                     n_amb=o.n_amb, allow=list(o.allow), front=list(o.front),

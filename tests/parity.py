@@ -2,11 +2,12 @@
 problem from one seeded workload, and compare their results with the
 tolerances stated here.
 
-Tolerances (derived in the design notes):
+Tolerances (derived in the design notes), with A = the sum of the
+magnitudes of a sample's cost terms (the oracle reports it):
   FP64 device path, end to end:
-      costs |dJ| <= 1e-9 * max(|J|, 1), controls |dU| <= 1e-9 * max(|U|, sigma)
+      costs |dJ| <= 1e-9 * max(A, |J|, 1), controls |dU| <= 1e-9 * max(|U|, sigma)
   FP32 device path, stage by stage:
-      costs   |dJ| <= 1e-4 * max(|J|, 1) against the oracle's costs;
+      costs   |dJ| <= 1e-4 * max(A, |J|, 1) against the oracle's costs;
       update  |dU| <= 1e-4 * max(|U|, sigma) against the oracle's weights and
               average (Eq. (4)-(5)) formed from the device's costs.
   The FP32 end-to-end control error (oracle costs in, oracle update out) is
@@ -72,7 +73,9 @@ def solve_and_compare(dev: M.Solver, orc: O.Problem, x0, t_now: float, precision
     assert info["g0"] == r["g0"] and info["shift"] == r["shift"] and info["i0"] == r["i0"]
     assert info["solve_index"] == wd.solve_index
     amb = r["margin"] < EPS_DEC[precision]
-    scale = np.maximum(np.abs(r["J"]), 1.0)
+    # a cost is a sum of terms; its rounding error scales with the terms'
+    # magnitudes (absJ), not with the net sum, which can telescope to ~0
+    scale = np.maximum(np.maximum(np.abs(r["J"]), r["absJ"]), 1.0)
     err_J = np.abs(Jd - r["J"]) / scale
     bad = np.where((err_J > tol) & ~amb)[0]
     assert bad.size == 0, f"{bad.size} costs off, worst {err_J[bad].max():.3e} at m={bad[:5]}"

@@ -328,3 +328,32 @@ def test_projection_on_circle():
     # midway between two table points, the projection is the chord midpoint
     mid = 0.5 * (tab[10, :3] + tab[11, :3])
     assert abs(pb.project(mid) - 10.5 * L / P) < 1e-9
+
+
+# ---------------------------------------------------------------- term magnitudes
+
+def _glide_absJ(gates):
+    """All samples of a zero-noise solve glide at 5 m/s along +x from
+    (0, 0, 2) for 20 steps of 0.02 s (hover thrust): (J, absJ) of sample 0."""
+    pb = gate_problem(gates, 20, q_near=0.0, sigma=(0.0, 0.0, 0.0, 0.0))
+    w = pb.warm(0)
+    r = pb.solve(w, state(p=(0, 0, 2.0), v=(5.0, 0, 0)), 0.0)
+    assert r["status"] == O.OK
+    return r["J"][0], r["absJ"][0]
+
+
+def test_term_magnitude_sum_of_one_signed_terms_is_the_cost_magnitude():
+    # toward a gate 20 m ahead: every progress term is negative, J = 18^2 - 20^2
+    J, A = _glide_absJ([[20.0, 0.0, 2.0, 0.0], [40.0, 0.0, 2.0, 0.0]])
+    assert abs(J - (18.0 ** 2 - 20.0 ** 2)) < 1e-9 and abs(A + J) < 1e-9
+    # away from a gate 20 m behind: every term is positive, J = 22^2 - 20^2
+    J, A = _glide_absJ([[-20.0, 0.0, 2.0, math.pi], [40.0, 0.0, 2.0, 0.0]])
+    assert abs(J - (22.0 ** 2 - 20.0 ** 2)) < 1e-9 and abs(A - J) < 1e-9
+
+
+def test_term_magnitude_sum_of_a_telescoped_cost():
+    # past a gate 0.5 m to the side (its plane along x is never crossed): the
+    # squared distance falls from 1.25 to 0.25 at x = 1 and rises back to
+    # 1.25, so J = 0 while the terms add up to 2 in magnitude
+    J, A = _glide_absJ([[1.0, 0.5, 2.0, math.pi / 2], [40.0, 0.0, 2.0, 0.0]])
+    assert abs(J) < 1e-12 and abs(A - 2.0) < 1e-9

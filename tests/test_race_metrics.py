@@ -1,0 +1,91 @@
+"""CPU pins of the race metrics (paper_2509_14726_amd.race) on paths whose
+answers are known in closed form: straight flights past and through gates,
+a constant tracking offset, a hand-made thrust log."""
+import math
+
+import numpy as np
+
+from paper_2509_14726_amd import race
+
+
+def _line(x0, x1, n, y=0.0, z=1.0):
+    t = np.linspace(0.0, 1.0, n)
+    P = np.stack([x0 + (x1 - x0) * t, np.full(n, y), np.full(n, z)], axis=1)
+    return P, t
+
+
+def test_pass_error_is_the_perpendicular_distance_of_a_straight_pass():
+    # the path runs along x at y = 0.3, z = 1.4; gate centre (5, 0, 1): the
+    # nearest point is (5, 0.3, 1.4), at distance 0.5 -- between samples
+    P, _ = _line(0.1, 9.7, 7, y=0.3, z=1.4)
+    gates = np.array([[5.0, 0.0, 1.0, 0.0], [20.0, 0.0, 1.0, 0.0]])
+    pe = race.waypoint_pass_errors(P, gates)
+    assert abs(pe[0] - 0.5) < 1e-12
+    # beyond the end of the path: distance to the last point (9.7, 0.3, 1.4)
+    assert abs(pe[1] - math.sqrt(10.3 ** 2 + 0.3 ** 2 + 0.4 ** 2)) < 1e-12
+
+
+def test_crossing_time_is_interpolated_on_the_segment():
+    # x(t) = 2 t + 0.25 passes x = 5 at t = 2.375
+    t = np.arange(0.0, 4.01, 0.5)
+    P = np.stack([2.0 * t + 0.25, np.zeros_like(t), np.ones_like(t)], axis=1)
+    gates = np.array([[5.0, 0.0, 1.0, 0.0]])
+    res = race.lap(P, t, gates, 1.5)
+    assert res["gates_passed"] == 1 and abs(res["pass_times"][0] - 2.375) < 1e-12
+    assert abs(res["lap_time"] - 2.375) < 1e-12
+
+
+def test_passes_outside_the_square_or_backwards_do_not_count():
+    t = np.linspace(0.0, 1.0, 11)
+    gates = np.array([[5.0, 0.0, 1.0, 0.0]])
+    # lateral offset 0.76 > 0.75: outside the 1.5 m square
+    P = np.stack([10.0 * t, np.full_like(t, 0.76), np.ones_like(t)], axis=1)
+    assert race.lap(P, t, gates, 1.5)["gates_passed"] == 0
+    # on the edge (0.75): inside the closed square
+    P[:, 1] = 0.75
+    assert race.lap(P, t, gates, 1.5)["gates_passed"] == 1
+    # flown against the gate normal (yaw 0 points along +x): no pass
+    P = np.stack([10.0 - 10.0 * t, np.zeros_like(t), np.ones_like(t)], axis=1)
+    assert race.lap(P, t, gates, 1.5)["gates_passed"] == 0
+    # a gate turned by pi faces -x: the same backward flight passes it
+    gates_back = np.array([[5.0, 0.0, 1.0, math.pi]])
+    assert race.lap(P, t, gates_back, 1.5)["gates_passed"] == 1
+
+
+def test_lap_counts_only_the_next_gate_in_order():
+    # gates along x at 2, 4, 6 in the order 0: x=4, 1: x=2, 2: x=6; a flight
+    # along +x passes x=2 (gate 1, not next), x=4 (gate 0), x=6 (gate 2, but
+    # gate 1 is next): one pass only
+    t = np.linspace(0.0, 8.0, 81)
+    P = np.stack([t, np.zeros_like(t), np.ones_like(t)], axis=1)
+    gates = np.array([[4.0, 0.0, 1.0, 0.0], [2.0, 0.0, 1.0, 0.0], [6.0, 0.0, 1.0, 0.0]])
+    res = race.lap(P, t, gates, 1.5)
+    assert res["gates_passed"] == 1 and abs(res["pass_times"][0] - 4.0) < 1e-12
+    assert res["lap_time"] is None
+    # in track order 2, 4, 6 the lap completes at the third pass, t = 6
+    ordered = gates[[1, 0, 2]]
+    res = race.lap(P, t, ordered, 1.5)
+    assert res["gates_passed"] == 3 and abs(res["lap_time"] - 6.0) < 1e-12
+
+
+def test_tracking_rmse_of_a_constant_offset():
+    ref_dt = 0.02
+    n = 50
+    xref = np.zeros((n + 10, 13))
+    xref[:, 0] = np.arange(n + 10) * 0.1
+    t = np.arange(n) * ref_dt
+    P = xref[:n, :3] + np.array([0.1, 0.2, 0.2])
+    assert abs(race.tracking_rmse(P, t, xref, ref_dt) - 0.3) < 1e-12
+    # past the end of the reference the last row is held
+    t_late = np.full(3, 100.0)
+    P_late = np.tile(xref[-1, :3], (3, 1)) + np.array([0.0, 0.0, 2.0])
+    assert abs(race.tracking_rmse(P_late, t_late, xref, ref_dt) - 2.0) < 1e-12
+
+
+def test_thrust_profile():
+    U = np.array([[1.0, 2.0, 3.0, 4.0], [0.0, 2.0, 2.0, 2.0], [7.0, 1.0, 1.0, 1.0], [2.0, 2.0, 2.0, 2.0]])
+    p = race.thrust_profile(U, 0.0, 7.0)
+    assert p["total_mean_N"] == (10.0 + 6.0 + 10.0 + 8.0) / 4
+    assert p["total_min_N"] == 6.0 and p["total_max_N"] == 10.0
+    assert p["saturated_share"] == 0.5
+    assert race.thrust_profile(np.zeros((0, 4)), 0.0, 7.0)["total_mean_N"] is None
