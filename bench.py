@@ -164,9 +164,12 @@ def closed_loop_race(steps: int = 1000):
 
         fl = race.fly(solve, w["quad"], w["x0"], steps, dt, substeps=4)
         sv.close()
-        lat = np.array(lat)
-        rec = {"steps": int(lat.size),
-               "status": "ok" if fl["error"] is None else f"stopped at step {lat.size}: {fl['error']}",
+        n_done = len(lat)
+        # latency over the steps after the first: the first solve of a
+        # process also loads the kernels' code objects
+        lat = np.array(lat[1:] if len(lat) > 1 else lat)
+        rec = {"steps": n_done,
+               "status": "ok" if fl["error"] is None else f"stopped at step {n_done}: {fl['error']}",
                "sigma_N": 0.15, "lambda": 10.0,
                "solve_ms_mean": float(lat.mean() * 1e3),
                "solve_ms_p99": float(np.percentile(lat, 99) * 1e3),
