@@ -89,3 +89,28 @@ def test_thrust_profile():
     assert p["total_min_N"] == 6.0 and p["total_max_N"] == 10.0
     assert p["saturated_share"] == 0.5
     assert race.thrust_profile(np.zeros((0, 4)), 0.0, 7.0)["total_mean_N"] is None
+
+
+def test_fly_closes_the_loop_with_the_host_plant():
+    """A controller that always commands hover thrust keeps a level body at
+    rest: the logged states stay at the start, the times advance by dt, and
+    a controller error ends the flight with its message."""
+    from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import synth
+    q = synth.QUAD
+    x0 = np.zeros(13)
+    x0[2] = 3.0
+    x0[6] = 1.0
+    hover = np.full(4, synth.hover_thrust(q))
+    fl = race.fly(lambda x, t: (hover, {"t": t}), q, x0, 10, 0.02)
+    assert fl["error"] is None and fl["X"].shape == (11, 13) and fl["U"].shape == (10, 4)
+    np.testing.assert_allclose(fl["t"], np.arange(11) * 0.02, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(fl["X"], np.tile(x0, (11, 1)), rtol=0, atol=1e-12)
+
+    def failing(x, t):
+        if t > 0.05:
+            raise M.MppiError(M.E_NONFINITE, "all costs non-finite")
+        return hover, {}
+
+    fl = race.fly(failing, q, x0, 10, 0.02)
+    assert fl["X"].shape == (4, 13) and "non-finite" in fl["error"]
