@@ -22,6 +22,12 @@ pytestmark = pytest.mark.gpu
 OBJECTIVES = ("gate", "contour", "track")
 
 
+def _gates_for(objective, g):
+    """The contouring path and the tracking reference are splines through
+    the gate centres: they need at least three gates."""
+    return g if objective == "gate" else max(3, g)
+
+
 def _cases(n=24, seed=20240917):
     rng = np.random.default_rng(seed)
     out = []
@@ -35,7 +41,7 @@ def _cases(n=24, seed=20240917):
         out.append(dict(
             i=i, precision=precision, objective=obj, K=max(K, 1), N=N,
             dt=float(rng.uniform(0.005, 0.05)), lam=float(np.exp(rng.uniform(np.log(1e-2), np.log(1e3)))),
-            sigma=sigma, n_gates=int(rng.integers(1, 21)), seed=int(rng.integers(1, 1 << 30)),
+            sigma=sigma, n_gates=_gates_for(obj, int(rng.integers(1, 21))), seed=int(rng.integers(1, 1 << 30)),
             track_seed=int(rng.integers(1, 1000)), waves=str(int(rng.integers(0, 5))),
             shift=int(rng.integers(1, 4))))
     return out
