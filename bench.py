@@ -33,14 +33,16 @@ PEAK_HBM_GBPS = 8000.0
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a run
 # of its own, WRITE_SIZE (KiB per dispatch, mean of 12 dispatches of the
 # benchmark workload), scaled by what the same counters read for a plain
-# 256 MiB device copy (FETCH_SIZE 131085.1 KiB -> x 2.0, WRITE_SIZE
+# 256 MiB device copy (FETCH_SIZE 131085.0 KiB -> x 2.0, WRITE_SIZE
 # 262144.0 KiB -> x 1.0); see profiles/k_rollout4_gate_k8192_n100_traffic.md.
-# They hold only for the device sources they were taken on (sha256 of
-# kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order); for any
-# other source the traffic is reported as null.
+# They hold only for the workload (K = 8192, N = 100, gate, binary32, the
+# four-wave layout with 4-step chunks) and the device sources they were taken
+# on (sha256 of kernels.hip, device.hpp, rollout.hpp, noise.hpp in that
+# order); otherwise the traffic is reported as null.
 TRAFFIC_SOURCES = "8b6a76e36c420f353d2e1baef514e474f3b36d7ef8eedfd99aaaf29e70de5235"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.0, 262144.0 / 262144.0
 TRAFFIC_KIB = {"k_rollout4": (225.5, 12836.4), "k_final": (6578.0, 6.6)}
+TRAFFIC_WORKLOAD = (8192, 100, "fp32")
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
 
@@ -58,10 +60,12 @@ def device_sources_hash() -> str:
     return h.hexdigest()
 
 
-def traffic_bytes(kernel: str):
+def traffic_bytes(kernel: str, workload=TRAFFIC_WORKLOAD):
     """Measured HBM bytes per launch of a kernel (fetch + write), or None when
-    the device sources differ from the ones the counters were taken on."""
-    if device_sources_hash() != TRAFFIC_SOURCES or kernel not in TRAFFIC_KIB:
+    the workload or the device sources differ from the ones the counters were
+    taken on."""
+    if (workload != TRAFFIC_WORKLOAD or device_sources_hash() != TRAFFIC_SOURCES
+            or kernel not in TRAFFIC_KIB):
         return None
     f, w = TRAFFIC_KIB[kernel]
     return (f * FETCH_SCALE + w * WRITE_SCALE) * 1024.0
@@ -415,6 +419,8 @@ def main():
     st, info = solver.read_info()
     assert st == M.OK, info
     rk = rollout_kernel(info["rollout_waves"])
+    # the counters hold for one workload; a forced layout is another
+    wl = (args.K, args.N, args.precision) if not os.environ.get("MPPI_ROLLOUT_WAVES") else None
     assert torch.isfinite(u0).all().item()
 
     K, N = args.K, args.N
@@ -428,7 +434,7 @@ def main():
     flops = FLOPS_PER_ROLLOUT_STEP * K * N
     achieved = flops / (roll_ms * 1e-3) / 1e12
     out = {
-        "metric": "rollout-steps/sec (K*N/s) at K=8192,N=100",
+        "metric": f"rollout-steps/sec (K*N/s) at K={K},N={N}",
         "value": value,
         "unit": "rollout-steps/s",
         "n_gpus": 1,
@@ -446,13 +452,13 @@ def main():
         "kernels_ms": {"sample": float(kern_ms[0]), "rollout": roll_ms, "average": float(kern_ms[2]),
                        "solves_timed": n_prof},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(rk),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(rk, wl),
                      "kernel": rk, "flops_per_launch": flops},
         # the weighted average streams the sample tensor once: HBM-bound
         "average_kernel": {"bound": "hbm", "kernel": "k_final", "bytes_per_launch": avg_bytes,
                            "achieved": avg_bytes / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
                            "unit": "GB/s", "frac": avg_bytes / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
-                           "traffic": traffic_bytes("k_final")},
+                           "traffic": traffic_bytes("k_final", wl)},
     }
     solver.close()
     if not args.no_extras:

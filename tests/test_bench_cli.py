@@ -1,6 +1,7 @@
-"""CPU checks of the benchmark's command line: more than one GPU is refused
-with a message (this build measures one GPU), before anything touches a
-device."""
+"""CPU checks of the benchmark's command line and host logic: more than one
+GPU is refused with a message (the benchmark measures one GPU) before
+anything touches a device, and measured HBM traffic is reported only for the
+workload the counters were taken on."""
 import os
 import subprocess
 import sys
@@ -14,3 +15,21 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_traffic_is_reported_only_for_the_counted_workload():
+    sys.path.insert(0, ROOT)
+    try:
+        import bench
+    finally:
+        sys.path.remove(ROOT)
+    here = bench.device_sources_hash() == bench.TRAFFIC_SOURCES
+    tb = bench.traffic_bytes("k_rollout4", (8192, 100, "fp32"))
+    assert (tb is not None) == here
+    if here:
+        f, w = bench.TRAFFIC_KIB["k_rollout4"]
+        assert abs(tb - (f * bench.FETCH_SCALE + w * bench.WRITE_SCALE) * 1024.0) < 1e-6
+    for wl in [(32767, 100, "fp32"), (8192, 200, "fp32"), (8192, 100, "fp64"), None]:
+        assert bench.traffic_bytes("k_rollout4", wl) is None
+        assert bench.traffic_bytes("k_final", wl) is None
+    assert bench.traffic_bytes("k_rollout", (8192, 100, "fp32")) is None
