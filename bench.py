@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=60.0)
     ap.add_argument("--layout-sweep", action="store_true",
                     help="time every rollout layout over K and N around the automatic choice and exit")
+    ap.add_argument("--regen", action="store_true",
+                    help="the weighted average draws the samples again instead of reading the sample tensor")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the large solve (K = 262144, N = 200) and print its figures; "
                          "for profiling its kernels")
@@ -380,6 +382,8 @@ def main():
 
     w = synth.single_solve_workload(K=args.K, N=args.N, seed=1)
     prm = w["params"]
+    if args.regen:
+        prm = dict(prm, flags=M.FLAG_REGEN_AVERAGE)
     prec = M.FP32 if args.precision == "fp32" else M.FP64
     dev = torch.device("cuda:0")
     # a stream of our own (default priority): the solver's kernels and the
@@ -420,7 +424,8 @@ def main():
     assert st == M.OK, info
     rk = rollout_kernel(info["rollout_waves"])
     # the counters hold for one workload; a forced layout is another
-    wl = (args.K, args.N, args.precision) if not os.environ.get("MPPI_ROLLOUT_WAVES") else None
+    forced = os.environ.get("MPPI_ROLLOUT_WAVES") or info["regen_average"]
+    wl = None if forced else (args.K, args.N, args.precision)
     assert torch.isfinite(u0).all().item()
 
     K, N = args.K, args.N
@@ -431,6 +436,8 @@ def main():
     # algorithmic bytes of the weighted average: the sample tensor and the
     # costs (read once per step block), the tile minima
     avg_bytes = K * N * 16 + K * 4 * N + ((K + 64) // 64) * 4 * N
+    if info["regen_average"]:  # the samples are drawn again, not read
+        avg_bytes -= K * N * 16
     flops = FLOPS_PER_ROLLOUT_STEP * K * N
     achieved = flops / (roll_ms * 1e-3) / 1e12
     out = {
@@ -448,7 +455,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single MPPI solve, gate-progress objective, K={K}, N={N}, dt={prm['dt']}, "
                                f"lambda={prm['lambda']}, sigma=1 N, seeded 7-gate track",
-                   "K": K, "N": N, "objective": "gate", "precision": args.precision},
+                   "K": K, "N": N, "objective": "gate", "precision": args.precision,
+                   "average": "regenerated" if info["regen_average"] else "stored samples"},
         "kernels_ms": {"sample": float(kern_ms[0]), "rollout": roll_ms, "average": float(kern_ms[2]),
                        "solves_timed": n_prof},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

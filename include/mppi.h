@@ -97,6 +97,18 @@ typedef struct {
  * mppi_read_samples return MPPI_E_INVAL). */
 #define MPPI_FLAG_EXTERNAL_WORKSPACE 1
 
+/* The weighted average of Eq. (5) draws every sample again from the
+ * counter-based noise of the solve (the sampling of Eq. (3) repeated with the
+ * same counters and the same arithmetic) instead of reading the N x K sample
+ * tensor, which the rollout then does not write: the same result bit for
+ * bit, with Philox and Box-Muller work in place of 16 B (20 B contouring) of
+ * HBM traffic per sample and step.  It takes effect in the three- and
+ * four-wave rollout layouts, whose rollout draws the samples itself
+ * (mppi_info.regen_average reports it); batched and served solves keep the
+ * tensor.  mppi_read_samples then returns the costs only (MPPI_E_INVAL when
+ * U_samples is requested). */
+#define MPPI_FLAG_REGEN_AVERAGE 2
+
 /* Problem data: the inputs of Alg. 1 (waypoints W, path P_arc, tau_ref). */
 typedef struct {
     const double *gates;  /* G x 4 row-major: centre x, y, z, yaw (gate objective) */
@@ -135,6 +147,9 @@ typedef struct {
     uint32_t solve_index;  /* Philox counter word of this solve                 */
     int32_t rollout_waves; /* rollout layout of the context's own solves: waves
                               per 64-sample tile (see mppi_batch_cfg)           */
+    int32_t regen_average; /* 1: the average draws the samples again
+                              (MPPI_FLAG_REGEN_AVERAGE in effect)               */
+    int32_t pad_;
 } mppi_info;
 
 /* Warm-start state inherited by the next solve (checkpoint / restore). */
@@ -194,7 +209,8 @@ mppi_status mppi_read_info(mppi_ctx *ctx, mppi_info *info);
 
 /* Copy the latest solve's sample costs (K doubles, as computed, in FP64
  * whatever the precision) and optionally the sample controls (N x K x 4
- * doubles, step-major).  Waits for the context stream. */
+ * doubles, step-major; MPPI_E_INVAL when the context's average regenerates
+ * the samples).  Waits for the context stream. */
 mppi_status mppi_read_samples(mppi_ctx *ctx, double *J, double *U_samples);
 
 /* Export / import the warm-start state (waits for the context stream).

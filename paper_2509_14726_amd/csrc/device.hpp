@@ -64,7 +64,9 @@ struct KArgs {
     int32_t n_tiles;            // 64-sample rollout tiles: ceil((K + 1) / 64)
     int32_t ring4_b;            // chunk of the four-wave rollout: 4 or 2 steps (binary32)
     int32_t proj_window, has_drag;
-    int32_t rollout_waves, pad_;  // 1: one wave per 64 samples; 2: attitude and translation on two waves
+    int32_t rollout_waves;      // 1: one wave per 64 samples; 2: attitude and translation on two waves; 3, 4
+    int32_t regen;              // 1: no sample tensor; the weighted average draws the samples again
+                                // (three- and four-wave layouts, whose rollout draws them)
     uint32_t seed_lo, seed_hi;
     // model
     double inv_mass, gravity, arm_s, c_tau;

@@ -1040,6 +1040,11 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
         o.w = h.warm ? (Real)a.wU[4 * src + 3] : hover;
         s_us[k] = o;
         if (HAS_V) s_vs[k] = h.warm ? (Real)a.wV[src] : Real(0);
+        // the weighted average regenerates the samples from these rows
+        if (a.regen && blk == (K >> 6)) {
+            ((R4 *)a.nomU)[k] = o;
+            if (HAS_V) ((Real *)a.nomV)[k] = s_vs[k];
+        }
     }
     __syncthreads();
     if (OBJ == OBJ_GATE) {
@@ -1064,11 +1069,11 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     u.z = clampT(us[2] + sig2 * z.z2, tmin, tmax);
                     u.w = clampT(us[3] + sig3 * z.z3, tmin, tmax);
                     const size_t idx = (size_t)k * (size_t)K + (size_t)m;
-                    store_nt(&ctrl[idx], u);
+                    if (!a.regen) store_nt(&ctrl[idx], u);
                     if (HAS_V) {
                         const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, h.s, 1u, a.seed_lo, a.seed_hi);
                         V = clampT(vs + sigv * zv, Real(0), vmax);
-                        store_nt(&vctrl[idx], V);
+                        if (!a.regen) store_nt(&vctrl[idx], V);
                     }
                 } else {  // the noise-free nominal (and idle lanes past it)
                     u.x = clampT(us[0], tmin, tmax);
@@ -1523,6 +1528,11 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
         o.w = h.warm ? (Real)a.wU[4 * src + 3] : hover;
         s_us[k] = o;
         if (HAS_V) s_vs[k] = h.warm ? (Real)a.wV[src] : Real(0);
+        // the weighted average regenerates the samples from these rows
+        if (a.regen && blk == (K >> 6)) {
+            ((R4 *)a.nomU)[k] = o;
+            if (HAS_V) ((Real *)a.nomV)[k] = s_vs[k];
+        }
     }
     __syncthreads();
     if (OBJ == OBJ_GATE) {
@@ -1560,7 +1570,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
             };
             // store the samples, hand the inputs on
             auto put = [&](const int k, const int j, const R4 u, const Real V) {
-                if (sampled) {
+                if (sampled && !a.regen) {
                     const size_t idx = (size_t)k * (size_t)K + (size_t)m;
                     store_nt(&ctrl[idx], u);
                     if (HAS_V) store_nt(&vctrl[idx], V);
@@ -2069,7 +2079,14 @@ template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
 // the report, the nominal's pass mask for the next solve and the warm-start
 // hand-over.  Every load the block needs (tile minima, its first samples,
 // head values) is issued before the first of them is used.
-template <typename Real, typename Acc, bool HAS_V>
+//
+// REGEN: the samples are not read from the sample tensor (which the rollout
+// then does not write) but drawn again from the counter-based noise of this
+// solve and the shifted warm start of step k that the rollout left in nomU /
+// nomV, with the same operations as the rollout's draw, so the weighted sums
+// are the same bit for bit: Philox and Box-Muller arithmetic in place of
+// 16 B (20 B contouring) of HBM traffic per sample and step.
+template <typename Real, typename Acc, bool HAS_V, bool REGEN>
 __device__ __forceinline__ void final_body(const KArgs &a, int k)
 {
     constexpr int C = HAS_V ? 5 : 4;
@@ -2090,6 +2107,29 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     DevWarm *w = a.warm;
     const bool head = k == 0;
     const bool gate = a.objective == OBJ_GATE;
+    // regenerated draws: the shifted warm start of step k and the noise key
+    R4 us{};
+    Real vs = Real(0);
+    uint32_t s_solve = 0;
+    if (REGEN) {
+        us = ((const R4 *)a.nomU)[k];
+        if (HAS_V) vs = ((const Real *)a.nomV)[k];
+        s_solve = cur->s;
+    }
+    const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max, vmax = (Real)a.v_max;
+    const Real sig0 = (Real)a.sigma[0], sig1 = (Real)a.sigma[1], sig2 = (Real)a.sigma[2], sig3 = (Real)a.sigma[3];
+    const Real sigv = (Real)a.sigma_v;
+    auto redraw = [&](const int m, R4 &u, Real &V) {
+        const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, s_solve, 0u, a.seed_lo, a.seed_hi);
+        u.x = clamp_finite(us.x + sig0 * z.z0, tmin, tmax);
+        u.y = clamp_finite(us.y + sig1 * z.z1, tmin, tmax);
+        u.z = clamp_finite(us.z + sig2 * z.z2, tmin, tmax);
+        u.w = clamp_finite(us.w + sig3 * z.z3, tmin, tmax);
+        if (HAS_V) {
+            const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, s_solve, 1u, a.seed_lo, a.seed_hi);
+            V = clamp_finite(vs + sigv * zv, Real(0), vmax);
+        }
+    };
 
     // loads: tile minima, the first UR samples of this thread
     Real mn = Real(INFINITY);
@@ -2104,8 +2144,10 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
         const int m = tid + NT * i;
         if (m < K) {
             Jm[i] = J[m];
-            u[i] = ctrl[m];
-            if (HAS_V) vm[i] = vctrl[m];
+            if (!REGEN) {
+                u[i] = ctrl[m];
+                if (HAS_V) vm[i] = vctrl[m];
+            }
         }
     }
     // head values for the report and the hand-over (block of step 0)
@@ -2148,14 +2190,17 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
                 const int m = m0 + NT * i;
                 if (m < K) {
                     Jm[i] = J[m];
-                    u[i] = ctrl[m];
-                    if (HAS_V) vm[i] = vctrl[m];
+                    if (!REGEN) {
+                        u[i] = ctrl[m];
+                        if (HAS_V) vm[i] = vctrl[m];
+                    }
                 }
             }
         }
 #pragma unroll
         for (int i = 0; i < UR; ++i) {
             if (m0 + NT * i < K) {
+                if (REGEN) redraw(m0 + NT * i, u[i], vm[i]);
                 const Real wr = isfinite(Jm[i]) ? exp(-(Jm[i] - jmin) * inv_lambda) : Real(0);
                 const Acc wa = (Acc)wr;
                 v[0] += wa * (Acc)u[i].x;
@@ -2235,10 +2280,10 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     }
 }
 
-template <typename Real, typename Acc, bool HAS_V>
+template <typename Real, typename Acc, bool HAS_V, bool REGEN>
 __global__ __launch_bounds__(kFinalThreads) void k_final(KArgs a)
 {
-    final_body<Real, Acc, HAS_V>(a, blockIdx.x);
+    final_body<Real, Acc, HAS_V, REGEN>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- batched (persistent)
@@ -2383,7 +2428,7 @@ template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         item = advance_item(b.step_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
-        final_body<Real, Acc, HAS_V>(s_a, u - b.step_prefix[item]);
+        final_body<Real, Acc, HAS_V, false>(s_a, u - b.step_prefix[item]);
         __syncthreads();
     }
 }
@@ -2451,7 +2496,10 @@ hipError_t launch_setup(const KArgs &a, bool fp64, hipStream_t st)
 template <typename Real, typename Acc, bool HAS_V>
 static hipError_t launch_average_t(const KArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_final<Real, Acc, HAS_V>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
+    if (a.regen)
+        hipLaunchKernelGGL((k_final<Real, Acc, HAS_V, true>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_final<Real, Acc, HAS_V, false>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
     return hipGetLastError();
 }
 

@@ -291,6 +291,8 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.C = c->C;
     a.real_bytes = (int32_t)rs;
     c->external_ws = (params->flags & MPPI_FLAG_EXTERNAL_WORKSPACE) != 0;
+    // the average can draw the samples again only where the rollout draws them
+    a.regen = ((params->flags & MPPI_FLAG_REGEN_AVERAGE) != 0 && a.rollout_waves >= 3) ? 1 : 0;
     struct Want { void **dst; size_t bytes; };
     void *gates_d = nullptr, *gates_r = nullptr, *path_d = nullptr, *path_r = nullptr, *xref_r = nullptr;
     void *warm = nullptr, *wU = nullptr, *wV = nullptr, *cur = nullptr, *res = nullptr, *req = nullptr;
@@ -436,6 +438,7 @@ static mppi_status copy_info(mppi_ctx *ctx, const DevResult &r, mppi_info *info)
         info->shift = r.shift;
         info->solve_index = r.s;
         info->rollout_waves = ctx->args.rollout_waves;
+        info->regen_average = ctx->args.regen;
     }
     if (r.status == ST_NONFINITE)
         return fail(ctx, MPPI_E_NONFINITE, "every sample cost was non-finite; warm state kept");
@@ -498,6 +501,9 @@ mppi_status mppi_read_samples(mppi_ctx *ctx, double *J, double *U_samples)
         }
     }
     if (U_samples) {
+        if (ctx->args.regen)
+            return fail(ctx, MPPI_E_INVAL,
+                        "the context was created with MPPI_FLAG_REGEN_AVERAGE: its solves keep no sample tensor");
         if (ctx->fp64) {
             HIP_TRY(ctx, hipMemcpy(U_samples, ctx->args.ctrl, sizeof(double) * 4 * K * N, hipMemcpyDeviceToHost));
         } else {
@@ -788,7 +794,11 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
     }
     // device table of kernel arguments
     std::vector<KArgs> table(n);
-    for (int i = 0; i < n; ++i) table[i] = ctxs[i]->args;
+    // batched solves keep the sample tensor (their layout is the batch's own)
+    for (int i = 0; i < n; ++i) {
+        table[i] = ctxs[i]->args;
+        table[i].regen = 0;
+    }
     if (hipMalloc((void **)&b->d_table, sizeof(KArgs) * n) != hipSuccess ||
         hipMemcpy(b->d_table, table.data(), sizeof(KArgs) * n, hipMemcpyHostToDevice) != hipSuccess) {
         release_batch(b);

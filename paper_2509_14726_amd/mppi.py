@@ -57,6 +57,7 @@ class mppi_params(C.Structure):
 
 
 FLAG_EXTERNAL_WORKSPACE = 1
+FLAG_REGEN_AVERAGE = 2
 
 
 class mppi_problem(C.Structure):
@@ -78,7 +79,8 @@ class mppi_info(C.Structure):
     _fields_ = [("J_min", C.c_double), ("S", C.c_double), ("ess", C.c_double),
                 ("J_nom", C.c_double), ("theta0", C.c_double), ("status", C.c_int32),
                 ("g0", C.c_int32), ("i0", C.c_int32), ("shift", C.c_int32),
-                ("solve_index", C.c_uint32), ("rollout_waves", C.c_int32)]
+                ("solve_index", C.c_uint32), ("rollout_waves", C.c_int32),
+                ("regen_average", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 def test_struct_sizes_match_header_layout():
     # sizes implied by the C declarations (x86-64 ABI)
     assert C.sizeof(M.mppi_quad) == 8 * 13
-    assert C.sizeof(M.mppi_info) == 5 * 8 + 6 * 4
+    assert C.sizeof(M.mppi_info) == 5 * 8 + 8 * 4
     assert C.sizeof(M.mppi_warm) == 4 * 4 + 9 * 4 + 4 + 8 + 13 * 8 + 8 + 256 * 4 * 8 + 256 * 8
     assert M.mppi_params.R_dT.offset == 4 * 4 + 8 * 2 + 8 * 4 + 8 + 8 + 8 * 3 + 13 * 8 * 2
 

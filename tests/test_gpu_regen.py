@@ -1,0 +1,119 @@
+"""The weighted average that draws the samples again (MPPI_FLAG_REGEN_AVERAGE)
+against the one that reads the sample tensor, and against the oracle.
+
+The regenerating average repeats the rollout's draw with the same counters and
+the same operations, so a context with the flag must hand on the same
+solution, report and warm state bit for bit as one without it, solve after
+solve; where the rollout does not draw the samples itself (one- and two-wave
+layouts) the flag has no effect.  Every case prints its name and sizes before
+it touches the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_14726_amd import mppi as M
+from paper_2509_14726_amd import synth
+from tests.parity import build_pair, solve_and_compare
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(w, precision):
+    plain = M.Solver(w["quad"], w["params"], gates=w["gates"], path=w.get("path"),
+                     path_len=w.get("path_len", 0.0), xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0),
+                     precision=precision)
+    prm = dict(w["params"], flags=M.FLAG_REGEN_AVERAGE)
+    regen = M.Solver(w["quad"], prm, gates=w["gates"], path=w.get("path"), path_len=w.get("path_len", 0.0),
+                     xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0), precision=precision)
+    return plain, regen
+
+
+def _warm_arrays(s):
+    wd = s.get_warm()
+    return (np.array(wd.U), np.array(wd.V), wd.g0, wd.solve_index, list(wd.allow), np.array(wd.x_prev))
+
+
+@pytest.mark.parametrize("waves", ["3", "4"])
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
+@pytest.mark.parametrize("precision", [M.FP32, M.FP64])
+def test_regenerated_average_repeats_the_stored_one(precision, objective, waves, monkeypatch):
+    # K + 1 = 2001 gives a ragged last tile; N = 37 a ragged last chunk
+    say("regen bits", precision, objective, "waves", waves, "K=2000 N=37")
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", waves)
+    w = synth.single_solve_workload(K=2000, N=37, objective=objective, seed=21, track_seed=3,
+                                    **{"lambda": 5.0})
+    plain, regen = _pair(w, precision)
+    x = np.array(w["x0"], dtype=np.float64)
+    for step in range(4):
+        t = step * w["params"]["dt"]
+        u0a, Ua, ia = plain.solve(x, t)
+        u0b, Ub, ib = regen.solve(x, t)
+        assert ia["regen_average"] == 0 and ib["regen_average"] == 1
+        assert ib["rollout_waves"] == int(waves)
+        np.testing.assert_array_equal(u0a, u0b)
+        np.testing.assert_array_equal(Ua, Ub)
+        for f in ("J_min", "S", "ess", "J_nom", "theta0", "g0", "i0", "shift", "solve_index", "status"):
+            assert ia[f] == ib[f], f
+        Ja, _ = plain.read_samples()
+        Jb, _ = regen.read_samples()
+        np.testing.assert_array_equal(Ja, Jb)
+        wa, wb = _warm_arrays(plain), _warm_arrays(regen)
+        for a, b in zip(wa, wb):
+            np.testing.assert_array_equal(a, b)
+        x = M.plant_step(w["quad"], x, u0a, w["params"]["dt"], 2)
+    plain.close()
+    regen.close()
+
+
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
+@pytest.mark.parametrize("precision", [M.FP64, M.FP32])
+def test_regenerated_average_against_the_oracle(precision, objective):
+    """Three warm solves of a context with the flag against the oracle, with
+    the tolerances of the other parity tests (the automatic layout of
+    K = 4096 is the four-wave pipeline)."""
+    say("regen vs oracle", precision, objective, "K=4096 N=60")
+    w = synth.single_solve_workload(K=4096, N=60, objective=objective, seed=22, track_seed=4,
+                                    **{"lambda": 20.0})
+    w["params"] = dict(w["params"], flags=M.FLAG_REGEN_AVERAGE)
+    dev, orc = build_pair(w, precision)
+    x = np.array(w["x0"], dtype=np.float64)
+    for step in range(3):
+        st = solve_and_compare(dev, orc, x, step * w["params"]["dt"], precision)
+        say("  step", step, "err_J", st["err_J"], "err_U", st["err_U"], "ambiguous", st["n_amb"])
+        st_, info = dev.read_info()
+        assert info["regen_average"] == 1
+        u0 = dev.get_warm().U[:4]
+        x = M.plant_step(w["quad"], x, np.array(u0), w["params"]["dt"], 2)
+    dev.close()
+
+
+def test_regeneration_needs_a_drawing_rollout(monkeypatch):
+    """In the one-wave layout the flag is not in effect: the sample tensor is
+    written and can be read; with it in effect the samples cannot be read."""
+    say("regen flag effect", "K=1000 N=20")
+    w = synth.single_solve_workload(K=1000, N=20, objective="gate", seed=23, track_seed=1)
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "1")
+    plain, regen = _pair(w, M.FP32)
+    u0a, _, ia = plain.solve(w["x0"], 0.0)
+    u0b, _, ib = regen.solve(w["x0"], 0.0)
+    assert ib["regen_average"] == 0 and ib["rollout_waves"] == 1
+    np.testing.assert_array_equal(u0a, u0b)
+    _, Ub = regen.read_samples(want_U=True)
+    assert Ub.shape[0] == 20
+    plain.close()
+    regen.close()
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "4")
+    plain, regen = _pair(w, M.FP32)
+    plain.close()
+    regen.solve(w["x0"], 0.0)
+    regen.read_samples()
+    with pytest.raises(M.MppiError, match="REGEN"):
+        regen.read_samples(want_U=True)
+    regen.close()
