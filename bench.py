@@ -33,16 +33,18 @@ PEAK_HBM_GBPS = 8000.0
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a run
 # of its own, WRITE_SIZE (KiB per dispatch, mean of 12 dispatches of the
 # benchmark workload), scaled by what the same counters read for a plain
-# 256 MiB device copy (FETCH_SIZE 131085.0 KiB -> x 2.0, WRITE_SIZE
+# 256 MiB device copy (FETCH_SIZE 131085.3 KiB -> x 2.0, WRITE_SIZE
 # 262144.0 KiB -> x 1.0); see profiles/k_rollout4_gate_k8192_n100_traffic.md.
 # They hold only for the workload (K = 8192, N = 100, gate, binary32, the
-# four-wave layout with 4-step chunks) and the device sources they were taken
-# on (sha256 of kernels.hip, device.hpp, rollout.hpp, noise.hpp in that
-# order); otherwise the traffic is reported as null.
-TRAFFIC_SOURCES = "8b6a76e36c420f353d2e1baef514e474f3b36d7ef8eedfd99aaaf29e70de5235"
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.0, 262144.0 / 262144.0
-TRAFFIC_KIB = {"k_rollout4": (225.5, 12836.4), "k_final": (6578.0, 6.6)}
-TRAFFIC_WORKLOAD = (8192, 100, "fp32")
+# four-wave layout with 4-step chunks; the average reading the sample tensor
+# or drawing the samples again) and the device sources they were taken on
+# (sha256 of kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order);
+# otherwise the traffic is reported as null.
+TRAFFIC_SOURCES = "5ce9cc70fa4b4416b32d2c5c604810eb6dd7141faf946e54c4c9940bb068b7ae"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.3, 262144.0 / 262144.0
+TRAFFIC_KIB = {("k_rollout4", 0): (215.0, 12836.4), ("k_final", 0): (6577.5, 6.6),
+               ("k_rollout4", 1): (214.9, 38.0), ("k_final", 1): (195.3, 6.6)}
+TRAFFIC_WORKLOADS = {(8192, 100, "fp32", 0), (8192, 100, "fp32", 1)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
 
@@ -60,14 +62,14 @@ def device_sources_hash() -> str:
     return h.hexdigest()
 
 
-def traffic_bytes(kernel: str, workload=TRAFFIC_WORKLOAD):
+def traffic_bytes(kernel: str, workload=(8192, 100, "fp32", 0)):
     """Measured HBM bytes per launch of a kernel (fetch + write), or None when
-    the workload or the device sources differ from the ones the counters were
-    taken on."""
-    if (workload != TRAFFIC_WORKLOAD or device_sources_hash() != TRAFFIC_SOURCES
-            or kernel not in TRAFFIC_KIB):
+    the workload (K, N, precision, regenerating average) or the device
+    sources differ from the ones the counters were taken on."""
+    if (workload not in TRAFFIC_WORKLOADS or device_sources_hash() != TRAFFIC_SOURCES
+            or (kernel, workload[3]) not in TRAFFIC_KIB):
         return None
-    f, w = TRAFFIC_KIB[kernel]
+    f, w = TRAFFIC_KIB[(kernel, workload[3])]
     return (f * FETCH_SCALE + w * WRITE_SCALE) * 1024.0
 
 
@@ -424,8 +426,8 @@ def main():
     assert st == M.OK, info
     rk = rollout_kernel(info["rollout_waves"])
     # the counters hold for one workload; a forced layout is another
-    forced = os.environ.get("MPPI_ROLLOUT_WAVES") or info["regen_average"]
-    wl = None if forced else (args.K, args.N, args.precision)
+    wl = None if os.environ.get("MPPI_ROLLOUT_WAVES") else (args.K, args.N, args.precision,
+                                                               int(info["regen_average"]))
     assert torch.isfinite(u0).all().item()
 
     K, N = args.K, args.N
@@ -463,7 +465,9 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(rk, wl),
                      "kernel": rk, "flops_per_launch": flops},
         # the weighted average streams the sample tensor once: HBM-bound
-        "average_kernel": {"bound": "hbm", "kernel": "k_final", "bytes_per_launch": avg_bytes,
+        # (drawing the samples again it is bound by the vector ALU instead)
+        "average_kernel": {"bound": "alu" if info["regen_average"] else "hbm", "kernel": "k_final",
+                           "bytes_per_launch": avg_bytes,
                            "achieved": avg_bytes / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
                            "unit": "GB/s", "frac": avg_bytes / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS,
                            "traffic": traffic_bytes("k_final", wl)},

@@ -24,12 +24,17 @@ def test_traffic_is_reported_only_for_the_counted_workload():
     finally:
         sys.path.remove(ROOT)
     here = bench.device_sources_hash() == bench.TRAFFIC_SOURCES
-    tb = bench.traffic_bytes("k_rollout4", (8192, 100, "fp32"))
-    assert (tb is not None) == here
+    for regen in (0, 1):
+        tb = bench.traffic_bytes("k_rollout4", (8192, 100, "fp32", regen))
+        assert (tb is not None) == here
+        if here:
+            f, w = bench.TRAFFIC_KIB[("k_rollout4", regen)]
+            assert abs(tb - (f * bench.FETCH_SCALE + w * bench.WRITE_SCALE) * 1024.0) < 1e-6
     if here:
-        f, w = bench.TRAFFIC_KIB["k_rollout4"]
-        assert abs(tb - (f * bench.FETCH_SCALE + w * bench.WRITE_SCALE) * 1024.0) < 1e-6
-    for wl in [(32767, 100, "fp32"), (8192, 200, "fp32"), (8192, 100, "fp64"), None]:
+        # drawing the samples again removes the sample tensor from both kernels
+        assert bench.traffic_bytes("k_rollout4", (8192, 100, "fp32", 1)) < 1e6
+        assert bench.traffic_bytes("k_final", (8192, 100, "fp32", 1)) < 1e6
+    for wl in [(32767, 100, "fp32", 0), (8192, 200, "fp32", 0), (8192, 100, "fp64", 0), None]:
         assert bench.traffic_bytes("k_rollout4", wl) is None
         assert bench.traffic_bytes("k_final", wl) is None
-    assert bench.traffic_bytes("k_rollout", (8192, 100, "fp32")) is None
+    assert bench.traffic_bytes("k_rollout", (8192, 100, "fp32", 0)) is None
