@@ -1,6 +1,8 @@
 """A seeded sweep of solve configurations against the FP64 oracle, through the
 C ABI: random K, N, dt, lambda, per-channel sigma (zeros included), gate
-count, objective, precision and rollout layout, a cold and a warm solve each.
+count, objective, precision and rollout layout, a cold and a warm solve each;
+half of the cases ask for the regenerating average (in effect where the
+rollout layout draws the samples itself).
 
 The configurations are drawn once from a fixed seed, so every run checks the
 same cases.  Binary32 cases keep N <= 120 and sigma <= 1.5 N: over longer
@@ -43,7 +45,7 @@ def _cases(n=24, seed=20240917):
             dt=float(rng.uniform(0.005, 0.05)), lam=float(np.exp(rng.uniform(np.log(1e-2), np.log(1e3)))),
             sigma=sigma, n_gates=_gates_for(obj, int(rng.integers(1, 21))), seed=int(rng.integers(1, 1 << 30)),
             track_seed=int(rng.integers(1, 1000)), waves=str(int(rng.integers(0, 5))),
-            shift=int(rng.integers(1, 4))))
+            shift=int(rng.integers(1, 4)), regen=i % 4 >= 2))
     return out
 
 
@@ -58,6 +60,8 @@ def test_sweep_case(c, monkeypatch):
     w = synth.single_solve_workload(K=c["K"], N=c["N"], objective=c["objective"], seed=c["seed"],
                                     track_seed=c["track_seed"], n_gates=c["n_gates"], dt=c["dt"],
                                     sigma=c["sigma"], **{"lambda": c["lam"]})
+    if c["regen"]:
+        w["params"] = dict(w["params"], flags=M.FLAG_REGEN_AVERAGE)
     dev, orc = build_pair(w, c["precision"])
     st = solve_and_compare(dev, orc, w["x0"], 0.0, c["precision"])
     print("[gpu-case]   cold err_J", st["err_J"], "err_U", st["err_U"], "ambiguous", st["n_amb"], flush=True)
