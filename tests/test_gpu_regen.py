@@ -117,3 +117,24 @@ def test_regeneration_needs_a_drawing_rollout(monkeypatch):
     with pytest.raises(M.MppiError, match="REGEN"):
         regen.read_samples(want_U=True)
     regen.close()
+
+
+def test_regenerated_average_at_the_benchmark_point():
+    """The benchmark workload (K = 8192, N = 100, gate, binary32, automatic
+    layout: four waves with 4-step chunks): three warm solves with and without
+    the flag agree bit for bit."""
+    say("regen bits at the benchmark point", "K=8192 N=100")
+    w = synth.single_solve_workload(K=8192, N=100, seed=1)
+    plain, regen = _pair(w, M.FP32)
+    x = np.array(w["x0"], dtype=np.float64)
+    for step in range(3):
+        t = step * w["params"]["dt"]
+        u0a, Ua, ia = plain.solve(x, t)
+        u0b, Ub, ib = regen.solve(x, t)
+        assert ib["regen_average"] == 1 and ib["rollout_waves"] == 4
+        np.testing.assert_array_equal(u0a, u0b)
+        np.testing.assert_array_equal(Ua, Ub)
+        assert ia["S"] == ib["S"] and ia["J_min"] == ib["J_min"] and ia["ess"] == ib["ess"]
+        x = M.plant_step(w["quad"], x, u0a, w["params"]["dt"], 2)
+    plain.close()
+    regen.close()
