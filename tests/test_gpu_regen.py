@@ -138,3 +138,26 @@ def test_regenerated_average_at_the_benchmark_point():
         x = M.plant_step(w["quad"], x, u0a, w["params"]["dt"], 2)
     plain.close()
     regen.close()
+
+
+@pytest.mark.parametrize("K,N", [(1, 1), (63, 256), (64, 5), (1, 256)])
+@pytest.mark.parametrize("precision", [M.FP32, M.FP64])
+def test_regenerated_average_at_extreme_shapes(precision, K, N):
+    """A single sample, a full last tile (K + 1 = 64), a nominal alone in a
+    new tile (K + 1 = 65) and the longest horizon: the flag repeats the
+    stored-tensor solve bit for bit over two warm solves."""
+    say("regen extreme shape", precision, "K", K, "N", N)
+    w = synth.single_solve_workload(K=K, N=N, objective="gate", seed=31, track_seed=2)
+    plain, regen = _pair(w, precision)
+    x = np.array(w["x0"], dtype=np.float64)
+    for step in range(2):
+        t = step * w["params"]["dt"]
+        u0a, Ua, ia = plain.solve(x, t)
+        u0b, Ub, ib = regen.solve(x, t)
+        assert ib["regen_average"] == 1
+        np.testing.assert_array_equal(u0a, u0b)
+        np.testing.assert_array_equal(Ua, Ub)
+        assert ia["S"] == ib["S"] and ia["J_min"] == ib["J_min"]
+        x = M.plant_step(w["quad"], x, u0a, w["params"]["dt"], 2)
+    plain.close()
+    regen.close()
