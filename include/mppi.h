@@ -149,7 +149,8 @@ typedef struct {
                               per 64-sample tile (see mppi_batch_cfg)           */
     int32_t regen_average; /* 1: the average draws the samples again
                               (MPPI_FLAG_REGEN_AVERAGE in effect)               */
-    int32_t pad_;
+    int32_t rollout_draw;  /* 1: the one-wave rollout draws its samples itself
+                              (binary32, sample tensor larger than 256 MiB)     */
 } mppi_info;
 
 /* Warm-start state inherited by the next solve (checkpoint / restore). */

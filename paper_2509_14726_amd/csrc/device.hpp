@@ -67,6 +67,8 @@ struct KArgs {
     int32_t rollout_waves;      // 1: one wave per 64 samples; 2: attitude and translation on two waves; 3, 4
     int32_t regen;              // 1: no sample tensor; the weighted average draws the samples again
                                 // (three- and four-wave layouts, whose rollout draws them)
+    int32_t rollout_draw;       // 1: the one-wave rollout draws its samples (no sample kernel)
+    int32_t pad_;
     uint32_t seed_lo, seed_hi;
     // model
     double inv_mass, gravity, arm_s, c_tau;

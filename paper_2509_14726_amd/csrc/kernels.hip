@@ -308,6 +308,31 @@ template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_sa
     sample_body<Real, HAS_V>(a, blockIdx.x);
 }
 
+// The head and the nominal's clipped inputs, for a rollout that draws its
+// samples itself (one-wave layout): one block.
+template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_head(KArgs a)
+{
+    typedef typename Vec4<Real>::T R4;
+    __shared__ HeadVals h;
+    compute_head(a, h);
+    if (threadIdx.x == 0) {
+        publish_head(a, h);
+        a.cur->J_nom = 0.0;
+    }
+    const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max;
+    for (int k = threadIdx.x; k < a.N; k += blockDim.x) {
+        int src = k + h.shift;
+        if (src > a.N - 1) src = a.N - 1;
+        R4 o;
+        o.x = clampT(h.warm ? (Real)a.wU[4 * src + 0] : (Real)a.hover, tmin, tmax);
+        o.y = clampT(h.warm ? (Real)a.wU[4 * src + 1] : (Real)a.hover, tmin, tmax);
+        o.z = clampT(h.warm ? (Real)a.wU[4 * src + 2] : (Real)a.hover, tmin, tmax);
+        o.w = clampT(h.warm ? (Real)a.wU[4 * src + 3] : (Real)a.hover, tmin, tmax);
+        ((R4 *)a.nomU)[k] = o;
+        if (HAS_V) ((Real *)a.nomV)[k] = clampT(h.warm ? (Real)a.wV[src] : Real(0), Real(0), (Real)a.v_max);
+    }
+}
+
 // ---------------------------------------------------------------- rollout
 
 // Smallest finite sample cost of a 64-sample tile (+inf when there is none),
@@ -333,15 +358,39 @@ template <typename Real> struct GateRegs {
 };
 
 // One wave: samples 64*blk .. 64*blk+63 (sample K is the noise-free nominal).
-template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
+// DRAW: the wave draws its samples itself (the noise, perturbation and clip
+// of the sample kernel, same operations, one step ahead of the dynamics) and
+// stores them for the weighted average with streaming stores; the shifted
+// warm start is staged in LDS from the head that k_head published.
+// Otherwise the wave reads the samples that the sample kernel stored.
+template <int OBJ, typename Real, bool DRAW = false>
+__device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
 {
     typedef typename Vec4<Real>::T R4;
+    constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
+    __shared__ R4 s_us[DRAW ? kNMax : 1];
+    __shared__ Real s_vs[DRAW && HAS_V ? kNMax : 1];
     const int m = blk * 64 + (int)(threadIdx.x & 63);
     const int K = a.K, N = a.N;
     const bool active = m <= K;
     const bool nominal = m == K;
     const DevCur *cur = a.cur;
     Real Jfinal = Real(0);
+    if (DRAW) {
+        const int shift = cur->shift, warm = cur->warm;
+        for (int k = (int)threadIdx.x; k < N; k += 64) {
+            int src = k + shift;
+            if (src > N - 1) src = N - 1;
+            R4 o;
+            o.x = warm ? (Real)a.wU[4 * src + 0] : (Real)a.hover;
+            o.y = warm ? (Real)a.wU[4 * src + 1] : (Real)a.hover;
+            o.z = warm ? (Real)a.wU[4 * src + 2] : (Real)a.hover;
+            o.w = warm ? (Real)a.wU[4 * src + 3] : (Real)a.hover;
+            s_us[k] = o;
+            if (HAS_V) s_vs[k] = warm ? (Real)a.wV[src] : Real(0);
+        }
+        __syncthreads();
+    }
 
     if (active) {
         const Model<Real> M(a);
@@ -355,6 +404,32 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(
         const size_t ustride = nominal ? 1 : (size_t)K;
         const Real *vrow = nullptr;
         if (OBJ == OBJ_CONTOUR) vrow = nominal ? (const Real *)a.nomV : (const Real *)a.vctrl + m;
+        // the inputs (u, V) of step k: drawn (and stored) or read
+        const bool draw = DRAW && !nominal;
+        const uint32_t s_solve = cur->s;
+        const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max;
+        const Real sig0 = (Real)a.sigma[0], sig1 = (Real)a.sigma[1];
+        const Real sig2 = (Real)a.sigma[2], sig3 = (Real)a.sigma[3];
+        auto input = [&](const int k, R4 &uo, Real &vo) {
+            if (draw) {
+                const R4 us = s_us[k];
+                const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, s_solve, 0u, a.seed_lo, a.seed_hi);
+                uo.x = clampT(us.x + sig0 * z.z0, tmin, tmax);
+                uo.y = clampT(us.y + sig1 * z.z1, tmin, tmax);
+                uo.z = clampT(us.z + sig2 * z.z2, tmin, tmax);
+                uo.w = clampT(us.w + sig3 * z.z3, tmin, tmax);
+                const size_t idx = (size_t)k * (size_t)K + (size_t)m;
+                store_nt(&((R4 *)a.ctrl)[idx], uo);
+                if (HAS_V) {
+                    const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, s_solve, 1u, a.seed_lo, a.seed_hi);
+                    vo = clampT(s_vs[k] + (Real)a.sigma_v * zv, Real(0), (Real)a.v_max);
+                    store_nt(&((Real *)a.vctrl)[idx], vo);
+                }
+            } else {
+                uo = urow[(size_t)k * ustride];
+                if (HAS_V) vo = vrow[(size_t)k * ustride];
+            }
+        };
 
         // gate objective state
         const Real *gtab = (const Real *)a.gates_r;
@@ -389,9 +464,13 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(
             inv_ds = (Real)((double)a.P / a.path_len);
         }
 
-        R4 u = urow[0];
+        R4 u;
+        Real v = Real(0);
+        input(0, u, v);
         for (int k = 0; k < N; ++k) {
-            const R4 un = (k + 1 < N) ? urow[(size_t)(k + 1) * ustride] : u;
+            R4 un = u;
+            Real vn = v;
+            if (k + 1 < N) input(k + 1, un, vn);
             Real term = Real(0);
 
             // ---- stage terms at state k
@@ -439,7 +518,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(
                 term += (Real)a.q_c * (cxe * cxe + cye * cye + cze * cze);
                 term += (Real)a.Q_w[0] * st.x[10] * st.x[10] + (Real)a.Q_w[1] * st.x[11] * st.x[11] +
                         (Real)a.Q_w[2] * st.x[12] * st.x[12];
-                const Real vk = vrow[(size_t)k * ustride];
+                const Real vk = v;
                 const Real dv = vk - vp;
                 term += (Real)(a.r_dv / (a.dt * a.dt)) * dv * dv;
                 const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
@@ -491,6 +570,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(
             J.add(term);
             up[0] = u.x; up[1] = u.y; up[2] = u.z; up[3] = u.w;
             u = un;
+            v = vn;
         }
         if (OBJ == OBJ_TRACK) {
             int r = i0 + N;
@@ -517,9 +597,9 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout1_body(
     store_tile_min(Jfinal, active && !nominal && isfinite(Jfinal), a.tmin, blk);
 }
 
-template <int OBJ, typename Real> __global__ __launch_bounds__(64) void k_rollout(KArgs a)
+template <int OBJ, typename Real, bool DRAW> __global__ __launch_bounds__(64) void k_rollout(KArgs a)
 {
-    rollout1_body<OBJ, Real>(a, blockIdx.x);
+    rollout1_body<OBJ, Real, DRAW>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- rollout, two waves
@@ -2509,7 +2589,13 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
     const dim3 gs((a.K + 1 + 255) / 256);
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (a.rollout_waves < 3) hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
+    // a one-wave rollout that draws its samples (binary32) needs only the head first
+    const bool draw = sizeof(Real) == 4 && a.rollout_draw;
+    if (draw) {
+        if constexpr (sizeof(Real) == 4) hipLaunchKernelGGL((k_head<Real, HAS_V>), dim3(1), dim3(256), 0, st, a);
+    } else if (a.rollout_waves < 3) {
+        hipLaunchKernelGGL((k_sample<Real, HAS_V>), gs, dim3(256), 0, st, a);
+    }
     if (ev) (void)hipEventRecord(ev[1], st);
     const dim3 gt((a.K + 1 + 63) / 64);
     if (a.rollout_waves == 4) {
@@ -2525,8 +2611,10 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
         hipLaunchKernelGGL((k_rollout3<OBJ, Real>), gt, dim3(192), 0, st, a);
     } else if (a.rollout_waves == 2) {
         hipLaunchKernelGGL((k_rollout_split<OBJ, Real>), gt, dim3(128), 0, st, a);
+    } else if (draw) {
+        if constexpr (sizeof(Real) == 4) hipLaunchKernelGGL((k_rollout<OBJ, Real, true>), gt, dim3(64), 0, st, a);
     } else {
-        hipLaunchKernelGGL((k_rollout<OBJ, Real>), gt, dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_rollout<OBJ, Real, false>), gt, dim3(64), 0, st, a);
     }
     if (ev) (void)hipEventRecord(ev[2], st);
     hipError_t e = (acc64 || sizeof(Real) == 8) ? launch_average_t<Real, double, HAS_V>(a, st)

@@ -200,6 +200,17 @@ static void plan_layout(mppi_ctx *c)
         if (e[0] >= '1' && e[0] <= '4') a.rollout_waves = e[0] - '0';
     }
     a.ring4_b = (!c->fp64 && a.n_tiles <= n_cu) ? 4 : 2;
+    // The one-wave rollout draws its samples itself (binary32) when the
+    // sample tensor exceeds the 256 MiB last-level cache: the separate
+    // sample pass then costs more than the draw adds to the rollout.  Below
+    // that the average reads a cached tensor, and the separate pass is as
+    // fast or faster (measured at K = 32768 and 65000, N = 100 and 200).
+    // MPPI_ROLLOUT_DRAW (0 or 1) overrides the rule.
+    const double tensor_bytes = 16.0 * (double)c->K * (double)c->N;
+    a.rollout_draw = (!c->fp64 && a.rollout_waves == 1 && tensor_bytes > 256.0 * 1048576.0) ? 1 : 0;
+    if (const char *e = getenv("MPPI_ROLLOUT_DRAW")) {
+        if (e[0] == '0' || e[0] == '1') a.rollout_draw = (!c->fp64 && a.rollout_waves == 1) ? e[0] - '0' : 0;
+    }
 }
 
 extern "C" {
@@ -439,6 +450,7 @@ static mppi_status copy_info(mppi_ctx *ctx, const DevResult &r, mppi_info *info)
         info->solve_index = r.s;
         info->rollout_waves = ctx->args.rollout_waves;
         info->regen_average = ctx->args.regen;
+        info->rollout_draw = ctx->args.rollout_draw;
     }
     if (r.status == ST_NONFINITE)
         return fail(ctx, MPPI_E_NONFINITE, "every sample cost was non-finite; warm state kept");

@@ -80,7 +80,7 @@ class mppi_info(C.Structure):
                 ("J_nom", C.c_double), ("theta0", C.c_double), ("status", C.c_int32),
                 ("g0", C.c_int32), ("i0", C.c_int32), ("shift", C.c_int32),
                 ("solve_index", C.c_uint32), ("rollout_waves", C.c_int32),
-                ("regen_average", C.c_int32), ("pad_", C.c_int32)]
+                ("regen_average", C.c_int32), ("rollout_draw", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -255,7 +255,38 @@ def test_large_solve_fp32_with_fp64_average(lam):
     dev, orc = build_pair(w, M.FP32, n_threads=16)
     st = solve_and_compare(dev, orc, w["x0"], 0.0, M.FP32)
     say("  err_J", st["err_J"], "err_U", st["err_U"], "e2e", st["err_U_e2e"], "ambiguous", st["n_amb"])
+    _, info = dev.read_info()
+    # the 839 MB sample tensor exceeds the last-level cache: the rollout draws
+    assert info["rollout_waves"] == 1 and info["rollout_draw"] == 1
     dev.close()
+
+
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
+def test_one_wave_rollout_drawing_its_samples(objective, monkeypatch):
+    """The one-wave rollout that draws its own samples (forced at a size
+    where the sample kernel would run) against the sample-kernel path: the
+    same samples, costs, solution and warm state bit for bit over three warm
+    solves; K + 1 = 3001 leaves a ragged last tile."""
+    say("one-wave draw vs sample kernel", objective, "K=3000 N=41")
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "1")
+    w = _workload(3000, 41, objective=objective, seed=17, track_seed=6, **{"lambda": 8.0})
+    out = []
+    for draw in ("0", "1"):
+        monkeypatch.setenv("MPPI_ROLLOUT_DRAW", draw)
+        dev, _ = build_pair(w, M.FP32)
+        x = np.array(w["x0"], dtype=np.float64)
+        steps = []
+        for step in range(3):
+            u0, U, info = dev.solve(x, step * w["params"]["dt"])
+            assert info["rollout_waves"] == 1 and info["rollout_draw"] == int(draw)
+            J, Us = dev.read_samples(want_U=True)
+            steps.append((u0, U, J, Us, info["S"], info["J_nom"], np.array(dev.get_warm().U)))
+            x = M.plant_step(w["quad"], x, u0, w["params"]["dt"], 2)
+        out.append(steps)
+        dev.close()
+    for a, b in zip(out[0], out[1]):
+        for xa, xb in zip(a, b):
+            np.testing.assert_array_equal(xa, xb)
 
 
 def test_automatic_layout_rule(monkeypatch):
