@@ -40,10 +40,10 @@ PEAK_HBM_GBPS = 8000.0
 # or drawing the samples again) and the device sources they were taken on
 # (sha256 of kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order);
 # otherwise the traffic is reported as null.
-TRAFFIC_SOURCES = "5ce9cc70fa4b4416b32d2c5c604810eb6dd7141faf946e54c4c9940bb068b7ae"
+TRAFFIC_SOURCES = "5110996d92cfe6c215cdf924be05ad137f4d79b2c004add7a8fda4b49be57ab8"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.3, 262144.0 / 262144.0
-TRAFFIC_KIB = {("k_rollout4", 0): (215.0, 12836.4), ("k_final", 0): (6577.5, 6.6),
-               ("k_rollout4", 1): (214.9, 38.0), ("k_final", 1): (195.3, 6.6)}
+TRAFFIC_KIB = {("k_rollout4", 0): (224.4, 12836.4), ("k_final", 0): (6578.0, 6.6),
+               ("k_rollout4", 1): (224.3, 38.0), ("k_final", 1): (195.2, 6.6)}
 TRAFFIC_WORKLOADS = {(8192, 100, "fp32", 0), (8192, 100, "fp32", 1)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
