@@ -175,7 +175,15 @@ typedef struct {
  * at element (k*K + m)*4), K costs, the per-tile cost minima and the
  * warm-start state.  stream is a hipStream_t (NULL: the library creates a non-blocking
  * stream of default priority that it owns).  The context starts cold with
- * target gate 0.  On failure *out is NULL. */
+ * target gate 0.  On failure *out is NULL.
+ *
+ * The rollout layout is chosen here from K, N and the precision and reported
+ * in mppi_info (rollout_waves, rollout_draw).  Two environment variables,
+ * read at creation, override the choice for testing and measurement:
+ * MPPI_ROLLOUT_WAVES (1..4: waves per 64-sample tile) and MPPI_ROLLOUT_DRAW
+ * (0 or 1: whether a binary32 one-wave rollout draws its own samples).  The
+ * results do not depend on the layout beyond rounding; rollout_draw changes
+ * no bit. */
 mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad,
                         const mppi_problem *problem, void *stream,
                         const mppi_allocator *allocator, mppi_ctx **out);
