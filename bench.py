@@ -303,6 +303,20 @@ def large_bench(steps: int = 5):
             "average_GBps": avg_bytes / (float(kern[2]) * 1e-3) / 1e9}
 
 
+def copy_calibration(mib: int, reps: int = 3):
+    """A plain device-to-device copy of a known size: the HBM byte counters
+    (FETCH_SIZE, WRITE_SIZE) read for it, divided by the bytes it moves, give
+    the scale applied to the same counters of the library's kernels."""
+    import torch
+    x = torch.ones(mib * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"MiB": mib, "copies": reps, "bytes_read_per_copy": mib * 2 ** 20, "bytes_written_per_copy": mib * 2 ** 20}
+
+
 def layout_sweep(steps: int = 30):
     """Device-driven solve time of every rollout layout (forced with
     MPPI_ROLLOUT_WAVES) around the automatic rule's crossover: the four-wave
@@ -364,12 +378,18 @@ def main():
     ap.add_argument("--large-only", action="store_true",
                     help="run only the large solve (K = 262144, N = 200) and print its figures; "
                          "for profiling its kernels")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device three times and exit: the known "
+                         "traffic that scales the HBM byte counters of a profile")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration > 0:
+        print(json.dumps({"copy_calibration": copy_calibration(args.copy_calibration)}), flush=True)
+        return
     if args.layout_sweep:
         import torch
         torch.cuda.set_stream(torch.cuda.Stream(torch.device("cuda:0")))

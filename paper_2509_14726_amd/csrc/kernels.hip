@@ -2503,6 +2503,8 @@ template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(
     __shared__ KArgs s_a;
     __shared__ int s_ctx;
     if (threadIdx.x == 0) s_ctx = -1;
+    // every thread reads s_ctx in stage_args before its first barrier
+    __syncthreads();
     const int n = b.desc->n, total = b.desc->n_steps;
     int item = 0;
     for (int u = blockIdx.x; u < total; u += gridDim.x) {

@@ -254,15 +254,6 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     c->fp64 = params->precision == MPPI_FP64;
     c->acc64 = c->fp64 || params->K >= 65536;
     if (allocator) { c->alloc = *allocator; c->have_alloc = true; }
-    if (stream) {
-        c->stream = (hipStream_t)stream;
-    } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-            release(c);
-            return fail(nullptr, MPPI_E_DEVICE, "hipStreamCreateWithFlags failed");
-        }
-        c->own_stream = true;
-    }
     c->G = params->objective == MPPI_OBJ_GATE ? problem->n_gates : 0;
     c->P = params->objective == MPPI_OBJ_CONTOUR ? problem->n_path : 0;
     c->R = params->objective == MPPI_OBJ_TRACK ? problem->n_ref : 0;
@@ -325,17 +316,28 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     }
     if (c->objective == MPPI_OBJ_CONTOUR) {
         path_d = dev_alloc(c, sizeof(double) * 6 * (size_t)c->P);
-        path_r = dev_alloc(c, rs * 8 * (size_t)c->P);
+        path_r = path_d ? dev_alloc(c, rs * 8 * (size_t)c->P) : nullptr;
         if (!path_d || !path_r) { release(c); return fail(nullptr, MPPI_E_NOMEM, "device allocation failed"); }
     }
     if (c->objective == MPPI_OBJ_GATE) {
         gates_d = dev_alloc(c, sizeof(double) * 12 * (size_t)c->G);  // G x 4 as given, G x 8 frames
-        gates_r = dev_alloc(c, rs * 8 * (size_t)c->G);
+        gates_r = gates_d ? dev_alloc(c, rs * 8 * (size_t)c->G) : nullptr;
         if (!gates_d || !gates_r) { release(c); return fail(nullptr, MPPI_E_NOMEM, "device allocation failed"); }
     }
     if (c->objective == MPPI_OBJ_TRACK) {
         xref_r = dev_alloc(c, rs * 16 * (size_t)c->R + sizeof(double) * 13 * (size_t)c->R);
         if (!xref_r) { release(c); return fail(nullptr, MPPI_E_NOMEM, "device allocation failed"); }
+    }
+    // the stream after the device memory: with an allocator callback, a failed
+    // allocation above returns before any HIP call
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            release(c);
+            return fail(nullptr, MPPI_E_DEVICE, "hipStreamCreateWithFlags failed");
+        }
+        c->own_stream = true;
     }
     if (hipHostMalloc((void **)&c->h_req, sizeof(double) * kReqDoubles, 0) != hipSuccess ||
         hipHostMalloc((void **)&c->h_res, sizeof(DevResult), 0) != hipSuccess ||

@@ -10,7 +10,9 @@ plant advances with the last control it received (RK4, substeps of at most
 1 km from the origin, or spinning faster than 1000 rad/s) is counted as a
 crash and respawned at its start (its solver keeps the warm state and
 re-converges from it).  Arrivals are paced
-in wall clock; latency = time the result is retired - arrival time.
+in wall clock; latency = time the result is retired - arrival time, where
+the retire time is the clock read just before the server call that found the
+solve finished.
 """
 from __future__ import annotations
 
@@ -90,6 +92,9 @@ def simulate(n_drones: int = 512, seconds: float = 60.0, rate_hz: float = 50.0,
                 u[d] = np.full(4, synth.hover_thrust(ws[d]["quad"]))
             server.submit(d, x[d], ta, ta)
             idx += 1
+        # the server stamps the solves it retires with this clock: read it
+        # after the plant steps and submissions above, not before them
+        now = time.perf_counter() - t0
         server.progress(now)
         for r in server.poll():
             lat.append(r["t_done"] - r["t_arrival"])

@@ -88,3 +88,66 @@ def test_plant_step_free_fall_and_hover():
     np.testing.assert_allclose(M.plant_step(q, x, np.full(4, h), 0.02, 1), x, atol=1e-14)
     with pytest.raises(M.MppiError):
         M.plant_step(q, x, np.zeros(4), 0.02, 0)
+
+
+def test_destroy_null_is_a_no_op():
+    M.lib.mppi_destroy(None)
+    M.lib.mppi_batch_destroy(None)
+    M.lib.mppi_server_destroy(None)
+
+
+# device blocks mppi_create asks its allocator for, gate objective: warm
+# state, warm U, warm V, head values, report, request record, per-solve
+# workspace, gate table (binary64 copy, device-precision copy)
+N_DEVICE_BLOCKS_GATE = 9
+
+
+@pytest.mark.parametrize("fail_at", range(1, N_DEVICE_BLOCKS_GATE + 1))
+def test_failing_allocator_gives_nomem_and_frees_what_it_got(fail_at):
+    """An allocator callback that fails on its fail_at-th call: mppi_create
+    returns MPPI_E_NOMEM, leaves *out NULL and hands back every block it was
+    given.  The allocations come before the first HIP call, so this runs on a
+    host without a GPU; the fake blocks are never dereferenced."""
+    w = synth.single_solve_workload(K=64, N=10)
+    calls, live, freed = [0], {}, []
+
+    def alloc(nbytes, user):
+        calls[0] += 1
+        if calls[0] == fail_at:
+            return None
+        buf = C.create_string_buffer(int(nbytes) + 256)
+        ptr = (C.addressof(buf) + 255) // 256 * 256
+        live[ptr] = buf
+        return ptr
+
+    def free(ptr, user):
+        freed.append(int(ptr))
+        live.pop(int(ptr))
+
+    af, ff = M.ALLOC_FN(alloc), M.FREE_FN(free)
+    al = M.mppi_allocator(af, ff, None)
+    quad = M.make_quad(w["quad"])
+    prm = M.make_params(w["params"], M.FP32)
+    pb = M.mppi_problem()
+    g = np.ascontiguousarray(w["gates"], dtype=np.float64)
+    pb.gates = g.ctypes.data_as(C.POINTER(C.c_double)); pb.n_gates = g.shape[0]; pb.gate_size = 1.5
+    out = C.c_void_p(1234)
+    st = M.lib.mppi_create(C.byref(prm), C.byref(quad), C.byref(pb), None, C.byref(al), C.byref(out))
+    assert st == M.E_NOMEM, (st, M.last_error(None))
+    assert out.value is None
+    assert calls[0] == fail_at
+    assert len(freed) == fail_at - 1 and not live
+    assert "allocation" in M.last_error(None)
+
+
+def test_allocator_needs_both_callbacks():
+    w = synth.single_solve_workload(K=64, N=10)
+    al = M.mppi_allocator(M.ALLOC_FN(lambda n, u: None), M.FREE_FN(), None)
+    quad = M.make_quad(w["quad"])
+    prm = M.make_params(w["params"], M.FP32)
+    pb = M.mppi_problem()
+    g = np.ascontiguousarray(w["gates"], dtype=np.float64)
+    pb.gates = g.ctypes.data_as(C.POINTER(C.c_double)); pb.n_gates = g.shape[0]; pb.gate_size = 1.5
+    out = C.c_void_p()
+    st = M.lib.mppi_create(C.byref(prm), C.byref(quad), C.byref(pb), None, C.byref(al), C.byref(out))
+    assert st == M.E_INVAL and out.value is None
