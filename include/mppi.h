@@ -93,8 +93,8 @@ typedef struct {
 
 /* The context allocates no per-solve workspace (sample tensor, costs,
  * per-tile cost minima); a server lends one to each admitted solve.  Such a
- * context is solved only through a server (mppi_solve, mppi_solve_device and
- * mppi_read_samples return MPPI_E_INVAL). */
+ * context is solved only through a server or mppi_solve_device_noalloc
+ * (mppi_solve, mppi_solve_device and mppi_read_samples return MPPI_E_INVAL). */
 #define MPPI_FLAG_EXTERNAL_WORKSPACE 1
 
 /* The weighted average of Eq. (5) draws every sample again from the
@@ -212,6 +212,29 @@ mppi_status mppi_solve(mppi_ctx *ctx, const double x0[13], double t_now, double 
  * writes NaN to d_u0.  The call sequence is fixed, so it may be captured in a
  * HIP graph and replayed with new contents of d_req. */
 mppi_status mppi_solve_device(mppi_ctx *ctx, const double *d_req, double *d_u0);
+
+/* Allocation-free variant of mppi_solve_device, for callers that cannot
+ * allocate device memory during a solve (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The same step with the
+ * same arguments, results and stream semantics, but the per-solve workspace
+ * (sample tensor, costs, per-tile cost minima, front flags) is a fixed
+ * library array of MPPI_SCRATCH_BYTES per GPU instead of the context's own,
+ * so it also runs contexts created with MPPI_FLAG_EXTERNAL_WORKSPACE.  The
+ * call allocates nothing: the array is a static device variable whose address
+ * is looked up once per device on the first call there.
+ *   - MPPI_E_INVAL when the context's workspace exceeds MPPI_SCRATCH_BYTES
+ *     (binary32 gate or tracking: about 16*K*N + 4*K bytes; contouring
+ *     20*K*N + 4*K; binary64 twice that), when the current device is not the
+ *     one the context was created on, or when d_req is NULL.
+ *   - Every call on a GPU shares that GPU's array.  Two calls whose work
+ *     overlaps on one GPU (different streams, no ordering between them) race
+ *     on it and their results are undefined; calls ordered on one stream are
+ *     safe.  Nothing in the array has to start at zero: a solve writes every
+ *     word of it that it reads.
+ *   - mppi_read_samples keeps reading the context's own workspace, so it does
+ *     not see the costs of a solve made through this entry point. */
+#define MPPI_SCRATCH_BYTES ((size_t)32 << 20)
+mppi_status mppi_solve_device_noalloc(mppi_ctx *ctx, const double *d_req, double *d_u0);
 
 /* Wait for the context stream and copy the report of the latest solve. */
 mppi_status mppi_read_info(mppi_ctx *ctx, mppi_info *info);

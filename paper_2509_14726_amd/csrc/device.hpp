@@ -21,6 +21,7 @@ constexpr int kMaskWords = 9;   // (kNMax + 1) bits
 constexpr int kGMax = 256;      // most gates (the pipelined rollouts stage the table in LDS)
 constexpr int kReqDoubles = 16;
 constexpr int kFinalThreads = 1024;  // threads of a block of the weighted-average kernel
+constexpr size_t kScratchBytes = (size_t)32 << 20;  // fixed workspace of the allocation-free solve
 
 enum Objective { OBJ_GATE = 0, OBJ_CONTOUR = 1, OBJ_TRACK = 2 };
 enum Status { ST_OK = 0, ST_INVAL = -1, ST_NOMEM = -2, ST_DEVICE = -3, ST_NONFINITE = -4 };

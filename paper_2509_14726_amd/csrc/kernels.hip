@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "device.hpp"
 #include "kernels.hpp"
 #include "noise.hpp"
@@ -2639,6 +2641,38 @@ hipError_t launch_solve(const KArgs &a, bool fp64, bool acc64, hipStream_t st, h
     case OBJ_TRACK: return launch_solve_t<float, OBJ_TRACK>(a, acc64, st, ev);
     default: return launch_solve_t<float, OBJ_GATE>(a, acc64, st, ev);
     }
+}
+
+// ------------------------------------------------------- fixed workspace
+
+// Workspace of the allocation-free solve: one array per GPU, held by the
+// library's code object until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// it resolves the device address per device and passes that.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_lock;
+void *g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_lock);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace mppi

@@ -16,6 +16,11 @@ hipError_t launch_setup(const KArgs &a, bool fp64, hipStream_t st);
 // average kernels and after the average kernel.
 hipError_t launch_solve(const KArgs &a, bool fp64, bool acc64, hipStream_t st, hipEvent_t *ev = nullptr);
 
+// Device address of the fixed solve workspace (kScratchBytes, 256-byte
+// aligned) on the current device.  The first call on a device resolves it
+// (with that device current) and later calls return the cached address.
+hipError_t scratch_address(void **ptr);
+
 // Launch shape of one batch group.
 struct BatchLaunch {
     int objective;

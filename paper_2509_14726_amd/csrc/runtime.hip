@@ -25,6 +25,7 @@ static_assert(MPPI_MASK_WORDS == kMaskWords, "mask width");
 static_assert(MPPI_N_MAX == kNMax, "horizon bound");
 static_assert(MPPI_G_MAX == kGMax, "gate bound");
 static_assert(MPPI_REQ_DOUBLES == kReqDoubles, "request record");
+static_assert(MPPI_SCRATCH_BYTES == kScratchBytes, "fixed workspace size");
 
 struct mppi_ctx {
     mppi_params prm;
@@ -49,6 +50,7 @@ struct mppi_ctx {
     int prof_count = 0;
     bool external_ws = false;   // per-solve scratch is lent by a server
     size_t ws_bytes = 0;        // size of that scratch
+    int device = 0;             // device current at creation
     std::string err;
 };
 
@@ -192,6 +194,7 @@ static void plan_layout(mppi_ctx *c)
     int n_cu = 0, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    c->device = dev;
     if (n_cu < 1) n_cu = 256;
     if (a.n_tiles <= n_cu) a.rollout_waves = 4;
     else if (a.n_tiles <= 2 * n_cu) a.rollout_waves = c->fp64 ? 2 : 4;
@@ -211,6 +214,19 @@ static void plan_layout(mppi_ctx *c)
     if (const char *e = getenv("MPPI_ROLLOUT_DRAW")) {
         if (e[0] == '0' || e[0] == '1') a.rollout_draw = (!c->fp64 && a.rollout_waves == 1) ? e[0] - '0' : 0;
     }
+}
+
+// Point the per-solve buffers of a at a workspace of ws_layout's size.
+static void bind_workspace(KArgs &a, char *w)
+{
+    const WsLayout wl = ws_layout(a.K, a.N, a.C, a.real_bytes);
+    a.ctrl = w + wl.ctrl;
+    a.vctrl = a.C == 5 ? w + wl.vctrl : nullptr;
+    a.nomU = w + wl.nomU;
+    a.nomV = w + wl.nomV;
+    a.J = w + wl.J;
+    a.tmin = w + wl.tmin;
+    a.front8 = (uint8_t *)(w + wl.front8);
 }
 
 extern "C" {
@@ -349,16 +365,7 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.path_d = (const double *)path_d; a.path_r = path_r; a.xref_r = xref_r;
     a.warm = (DevWarm *)warm; a.wU = (double *)wU; a.wV = (double *)wV;
     a.cur = (DevCur *)cur; a.res = (DevResult *)res;
-    if (ws) {
-        char *w = (char *)ws;
-        a.ctrl = w + wl.ctrl;
-        a.vctrl = c->C == 5 ? w + wl.vctrl : nullptr;
-        a.nomU = w + wl.nomU;
-        a.nomV = w + wl.nomV;
-        a.J = w + wl.J;
-        a.tmin = w + wl.tmin;
-        a.front8 = (uint8_t *)(w + wl.front8);
-    }
+    if (ws) bind_workspace(a, (char *)ws);
     c->warm = (DevWarm *)warm; c->res = (DevResult *)res; c->req = (double *)req;
 
     // problem data, initial (cold) warm state
@@ -398,6 +405,28 @@ mppi_status mppi_solve_device(mppi_ctx *ctx, const double *d_req, double *d_u0)
     if (ctx->external_ws) return fail(ctx, MPPI_E_INVAL, "context has no workspace of its own (server context)");
     ctx->err.clear();
     KArgs a = ctx->args;
+    a.req = d_req;
+    a.u0_out = d_u0;
+    HIP_TRY(ctx, launch_solve(a, ctx->fp64, ctx->acc64, ctx->stream, next_events(ctx)));
+    return MPPI_OK;
+}
+
+mppi_status mppi_solve_device_noalloc(mppi_ctx *ctx, const double *d_req, double *d_u0)
+{
+    if (!ctx) return fail(nullptr, MPPI_E_INVAL, "ctx is NULL");
+    if (!d_req) return fail(ctx, MPPI_E_INVAL, "d_req is NULL");
+    if (ctx->ws_bytes > kScratchBytes)
+        return fail(ctx, MPPI_E_INVAL, "solve workspace of %zu bytes exceeds the fixed workspace of %zu bytes",
+                    ctx->ws_bytes, kScratchBytes);
+    int dev = -1;
+    HIP_TRY(ctx, hipGetDevice(&dev));
+    if (dev != ctx->device)
+        return fail(ctx, MPPI_E_INVAL, "current device %d is not the context's device %d", dev, ctx->device);
+    ctx->err.clear();
+    void *base = nullptr;
+    HIP_TRY(ctx, scratch_address(&base));
+    KArgs a = ctx->args;
+    bind_workspace(a, (char *)base);
     a.req = d_req;
     a.u0_out = d_u0;
     HIP_TRY(ctx, launch_solve(a, ctx->fp64, ctx->acc64, ctx->stream, next_events(ctx)));

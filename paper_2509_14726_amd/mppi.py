@@ -20,11 +20,13 @@ K_MAX = 1 << 24
 G_MAX = 256
 MASK_WORDS = 9
 REQ_DOUBLES = 16
+SCRATCH_BYTES = 32 << 20
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE = 0, -1, -2, -3, -4
 OBJ_GATE, OBJ_CONTOUR, OBJ_TRACK = 0, 1, 2
 FP32, FP64 = 0, 1
 
-EXPORTS = ["mppi_create", "mppi_destroy", "mppi_solve", "mppi_solve_device", "mppi_read_info",
+EXPORTS = ["mppi_create", "mppi_destroy", "mppi_solve", "mppi_solve_device",
+           "mppi_solve_device_noalloc", "mppi_read_info",
            "mppi_read_samples", "mppi_get_warm", "mppi_set_warm", "mppi_last_error",
            "mppi_status_string", "mppi_plant_step", "mppi_set_profiling", "mppi_read_profile",
            "mppi_batch_create", "mppi_batch_solve_device", "mppi_batch_set_cfg", "mppi_batch_get_cfg",
@@ -147,6 +149,8 @@ def _load():
     L.mppi_solve.restype = C.c_int
     L.mppi_solve_device.argtypes = [_P, _P, _P]
     L.mppi_solve_device.restype = C.c_int
+    L.mppi_solve_device_noalloc.argtypes = [_P, _P, _P]
+    L.mppi_solve_device_noalloc.restype = C.c_int
     L.mppi_read_info.argtypes = [_P, C.POINTER(mppi_info)]
     L.mppi_read_info.restype = C.c_int
     L.mppi_read_samples.argtypes = [_P, _D, _D]
@@ -323,6 +327,10 @@ class Solver:
 
     def solve_device(self, d_req: int, d_u0: int):
         _check(lib.mppi_solve_device(self.ctx, _P(d_req), _P(d_u0)), self.ctx)
+
+    def solve_device_noalloc(self, d_req: int, d_u0: int):
+        """mppi_solve_device on the library's fixed per-GPU workspace."""
+        _check(lib.mppi_solve_device_noalloc(self.ctx, _P(d_req), _P(d_u0)), self.ctx)
 
     def read_info(self):
         info = mppi_info()
