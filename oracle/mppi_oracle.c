@@ -325,7 +325,8 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
     double x[13], xn[13];
     memcpy(x, x0, sizeof x);
     double J = 0.0;
-    double Jabs = 0.0; /* sum of the magnitudes of the terms added to J */
+    double Jabs = 0.0; /* sum of the magnitudes of the quantities added to or
+                          subtracted from J */
 #define ORC_ADD(t) do { const double t_ = (t); J += t_; Jabs += fabs(t_); } while (0)
     double mrg = INFINITY;
     int g = g0, passes = 0;
@@ -395,8 +396,12 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
 
         if (c->objective == ORC_OBJ_GATE) {
             const double *gc = c->gates + 4 * g;
-            /* progress term, Eq. (6), toward the gate targeted by state k */
-            ORC_ADD(sqdist3(xn, gc) - sqdist3(x, gc));
+            /* progress term, Eq. (6), toward the gate targeted by state k: a
+             * difference of two squared distances, whose rounding scales with
+             * the squares, so both count toward the magnitude sum */
+            const double dn = sqdist3(xn, gc), dp = sqdist3(x, gc);
+            J += dn - dp;
+            Jabs += dn + dp;
         }
         ORC_ADD(limit_cost(c, q, xn));
 

@@ -98,7 +98,8 @@ typedef struct {
     uint32_t allow[ORC_MASK_WORDS];     /* mask used by this solve                     */
     uint32_t front[ORC_MASK_WORDS];     /* nominal rollout states in front of gate g0  */
     uint32_t front_amb[ORC_MASK_WORDS]; /* front decisions within eps_dec of the plane */
-    double *absJ;    /* K   sum over a sample's cost terms of their magnitudes (may be NULL) */
+    double *absJ;    /* K   sum of the magnitudes of the quantities a sample's cost adds or
+                        subtracts (both squared distances of each Eq. (6) term; may be NULL) */
 } orc_out;
 
 /* ---- building blocks (exported for the pin tests) ---------------------- */

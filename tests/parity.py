@@ -2,25 +2,39 @@
 problem from one seeded workload, and compare their results with the
 tolerances stated here.
 
-Tolerances (derived in the design notes), with A = the sum of the
-magnitudes of a sample's cost terms (the oracle reports it):
-  FP64 device path, end to end:
-      costs |dJ| <= 1e-9 * max(A, |J|, 1), controls |dU| <= 1e-9 * max(|U|, sigma)
-  FP32 device path, stage by stage:
-      costs   |dJ| <= 1e-4 * max(A, |J|, 1) against the oracle's costs;
-      update  |dU| <= 1e-4 * max(|U|, sigma) against the oracle's weights and
-              average (Eq. (4)-(5)) formed from the device's costs.
-  The FP32 end-to-end control error (oracle costs in, oracle update out) is
-  reported, not gated: it is the cost error times the sensitivity of the
-  softmax average, (1/lambda) * sum_m w_m |dJ_m| |U_m - U|, which exceeds
-  1e-4 whenever near-tied samples meet small lambda.
+A is the sum of the magnitudes of the quantities a sample's cost adds or
+subtracts (the oracle reports it; both squared distances of each progress
+term of Eq. (6) count).  Rounding errors of a cost scale with A, not with the
+net sum, which can telescope to about zero.  sigma is the noise scale.
+
+  FP64 device path, end to end (oracle costs, oracle update):
+      costs    |dJ| <= 1e-9 * max(A, |J|)
+      controls |dU| <= 1e-9 * max(|U|, sigma)
+  FP32 device path:
+      costs    |dJ| <= 1e-4 * max(A, |J|) against the oracle's costs;
+      update   |dU| <= 1e-4 * max(|U|, sigma) against the oracle's Eq. (4)-(5)
+               formed from the device's costs (the stage check);
+      controls |dU| <= 1e-4 * max(|U|, sigma) end to end (oracle costs in,
+               oracle update out).  Where the case is not at the benchmark
+               parameters (lambda = 1, sigma = 1 N) the end-to-end bound is
+               widened by twice the first-order change of Eq. (5) under the
+               measured cost errors: dU/dJ_m = -(w_m / lambda)(U^m - U), so
+               |dU| <= (1/lambda) sum_m w_m |dJ_m| |U^m - U|.  Near-tied
+               samples at a small lambda turn FP32 cost rounding into control
+               changes above 1e-4; this bound is what such a tie allows.
 A sample whose oracle decision margin (distance of a gate-plane, aperture or
 near-radius test to its threshold) is below EPS_DEC of the precision is
 ambiguous: both outcomes are correct.  Such samples are excluded from the
 per-sample cost check and the oracle's weights are recomputed with the
 device's cost for them (decision replay); everything else must match as is.
+
+When the environment variable MPPI_PARITY_LOG names a file, every comparison
+appends one JSON line with the case and its errors.
 """
 from __future__ import annotations
+
+import json
+import os
 
 import numpy as np
 
@@ -58,56 +72,132 @@ def warm_to_oracle(wd: M.mppi_warm, orc: O.Problem) -> O.Warm:
     return o
 
 
+def sensitivity_bound(orc: O.Problem, ref: dict, dJ, s: int):
+    """First-order change of Eq. (5) under per-sample cost errors dJ:
+    (1/lambda) sum_m w_m |dJ_m| |U^m - U|, N x 4, with the oracle's weights
+    and samples (U^m drawn again by the oracle's own sampler)."""
+    lam = orc.cfg.lam
+    contrib = ref["w"] * np.abs(dJ)
+    B = np.zeros((orc.cfg.N, 4))
+    if not (contrib > 0).any():
+        return B
+    for m in np.nonzero(contrib > 1e-9 * contrib.max())[0]:
+        Um, _ = orc.sample(ref["Ustar"], ref["Vstar"], int(m), s)
+        B += contrib[m] * np.abs(Um - ref["U"])
+    return B / lam
+
+
+def _log(rec: dict):
+    path = os.environ.get("MPPI_PARITY_LOG")
+    if not path:
+        return
+    rec = dict(rec, case=os.environ.get("PYTEST_CURRENT_TEST", "").split(" ")[0])
+    with open(path, "a") as fh:
+        fh.write(json.dumps(rec) + "\n")
+
+
 def solve_and_compare(dev: M.Solver, orc: O.Problem, x0, t_now: float, precision: int,
-                      sigma: float = 1.0, check_warm: bool = True):
+                      sigma: float = 1.0, check_warm: bool = True, strict_e2e: bool | None = None):
     """Import the device's warm state into the oracle, solve on both sides,
-    compare (with decision replay), then check the warm states they hand on."""
-    tol = TOL[precision]
+    compare (with decision replay), then check the warm states they hand on.
+    strict_e2e: gate the FP32 end-to-end controls at 1e-4 without the
+    sensitivity allowance (default: at the benchmark parameters lambda = 1,
+    sigma = 1 N)."""
     wd = dev.get_warm()
-    ow = warm_to_oracle(wd, orc)
-    ow_replay = warm_to_oracle(wd, orc)
     u0, U, info = dev.solve(x0, t_now)
     Jd, _ = dev.read_samples()
+    wn = dev.get_warm() if check_warm else None
+    return compare_result(orc, wd, x0, t_now, precision, u0, U, info, Jd=Jd, wn=wn, sigma=sigma,
+                          strict_e2e=strict_e2e)
+
+
+def compare_result(orc: O.Problem, wd: M.mppi_warm, x0, t_now: float, precision: int, u0, U, info: dict,
+                   Jd=None, wn: M.mppi_warm | None = None, sigma: float = 1.0, strict_e2e: bool | None = None):
+    """Compare one device solve with the oracle's solve from the same warm
+    state wd (the state exported before the device solve).  u0, U, info: the
+    device's first input, solution and report; Jd: its sample costs, or None
+    when the workspace that held them is gone (served solves: then no sample
+    may be ambiguous, the costs are not compared one by one and the controls
+    are gated end to end at the tolerance); wn: the warm state the device
+    handed on, or None."""
+    tol = TOL[precision]
+    cfg = orc.cfg
+    if strict_e2e is None:
+        strict_e2e = cfg.lam == 1.0 and all(v == 1.0 for v in cfg.sigma)
+    ow = warm_to_oracle(wd, orc)
+    ow_stage = warm_to_oracle(wd, orc)
+    ow_e2e = warm_to_oracle(wd, orc)
+    U = np.asarray(U).reshape(cfg.N, 4)
     r = orc.solve(ow, x0, t_now)
     assert r["status"] == O.OK
     assert info["g0"] == r["g0"] and info["shift"] == r["shift"] and info["i0"] == r["i0"]
     assert info["solve_index"] == wd.solve_index
     amb = r["margin"] < EPS_DEC[precision]
-    # a cost is a sum of terms; its rounding error scales with the terms'
-    # magnitudes (absJ), not with the net sum, which can telescope to ~0
-    scale = np.maximum(np.maximum(np.abs(r["J"]), r["absJ"]), 1.0)
-    err_J = np.abs(Jd - r["J"]) / scale
+    scale = np.maximum(np.abs(r["J"]), r["absJ"])
+    if Jd is None:
+        assert not amb.any(), f"{int(amb.sum())} ambiguous samples: the case needs the device costs"
+        strict_e2e = True
+        Jd_cmp = r["J"]
+    else:
+        Jd_cmp = Jd
+    finite = np.isfinite(r["J"]) & np.isfinite(Jd_cmp)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        err_J = np.where(finite, np.abs(Jd_cmp - r["J"]) / np.where(scale > 0, scale, 1.0), 0.0)
+    both_inf = ~np.isfinite(r["J"]) & ~np.isfinite(Jd_cmp)
+    assert np.all(finite | both_inf | amb), "finite on one side only"
     bad = np.where((err_J > tol) & ~amb)[0]
     assert bad.size == 0, f"{bad.size} costs off, worst {err_J[bad].max():.3e} at m={bad[:5]}"
-    ref = r
-    e2e = float((np.abs(U - r["U"]) / np.maximum(np.abs(r["U"]), sigma)).max())
-    if precision == M.FP32:
+    # end to end: the oracle's own costs, the device's only where a decision is ambiguous
+    ref_e2e = r
+    if amb.any():
+        ref_e2e = orc.solve(ow_e2e, x0, t_now, J_rep=Jd, rep_mask=amb.astype(np.uint8))
+        assert ref_e2e["status"] == O.OK
+    scale_U = np.maximum(np.abs(ref_e2e["U"]), sigma)
+    dU = np.abs(U - ref_e2e["U"])
+    e2e = float((dU / scale_U).max())
+    bound = 0.0
+    if e2e > tol:
+        assert not strict_e2e, f"end-to-end controls off by {e2e:.3e} at the benchmark parameters"
+        dJ = np.where(finite & ~amb, Jd - r["J"], 0.0)
+        B = sensitivity_bound(orc, ref_e2e, dJ, wd.solve_index)
+        bound = float((B / scale_U).max())
+        excess = dU - (tol * scale_U + 2.0 * B)
+        assert (excess <= 0).all(), (f"end-to-end controls off by {e2e:.3e}, beyond 1e-4 plus twice the "
+                                     f"first-order bound {bound:.3e}")
+    ref = ref_e2e
+    if precision == M.FP32 and Jd is not None:
         # the update stage, fed with the device's costs
-        ref = orc.solve(ow_replay, x0, t_now, J_rep=Jd, rep_mask=np.ones(Jd.size, np.uint8))
-        assert ref["status"] == O.OK
-    elif amb.any():
-        ref = orc.solve(ow_replay, x0, t_now, J_rep=Jd, rep_mask=amb.astype(np.uint8))
+        ref = orc.solve(ow_stage, x0, t_now, J_rep=Jd, rep_mask=np.ones(Jd.size, np.uint8))
         assert ref["status"] == O.OK
     err_U = np.abs(U - ref["U"]) / np.maximum(np.abs(ref["U"]), sigma)
     assert err_U.max() <= tol, f"controls off by {err_U.max():.3e}"
     np.testing.assert_allclose(u0, ref["U"][0], rtol=0, atol=tol * max(np.abs(ref["U"][0]).max(), sigma))
-    err_min = abs(info["J_min"] - ref["J_min"]) / max(abs(ref["J_min"]), 1.0)
+    # J_min is a sample cost: the scale of the oracle's lowest-cost sample
+    m_min = int(np.argmin(np.where(np.isfinite(r["J"]), r["J"], np.inf)))
+    err_min = abs(info["J_min"] - ref["J_min"]) / max(abs(ref["J_min"]), scale[m_min], 1e-300)
     assert err_min <= tol, err_min
-    assert abs(info["ess"] - ref["ess"]) <= tol * max(ref["ess"], 1.0) * 10 + 1e-12, (info["ess"], ref["ess"])
+    err_ess = abs(info["ess"] - ref["ess"]) / ref["ess"]
+    assert err_ess <= tol, (info["ess"], ref["ess"])
     if np.isfinite(r["J_nom"]):
         assert abs(info["J_nom"] - r["J_nom"]) <= tol * max(abs(r["J_nom"]), 1.0)
-    if orc.cfg.objective == O.OBJ_CONTOUR:
-        assert abs(info["theta0"] - r["theta0"]) <= 1e-9 * max(orc.cfg.path_len, 1.0)
-    if check_warm:
-        wn = dev.get_warm()
+    if cfg.objective == O.OBJ_CONTOUR:
+        assert abs(info["theta0"] - r["theta0"]) <= 1e-9 * max(cfg.path_len, 1.0)
+    if wn is not None:
         assert wn.warm == 1 and wn.g0 == r["g0"] and wn.solve_index == wd.solve_index + 1
         # the pass mask handed on: bits whose nominal state lies within eps of
         # the gate plane may differ
-        n = orc.cfg.N + 1
+        n = cfg.N + 1
         dbits = O.mask_bits(list(wn.allow), n)
         obits = O.mask_bits(r["front"], n)
         famb = O.mask_bits(r["front_amb"], n)
         assert np.array_equal(dbits[~famb], obits[~famb])
-        np.testing.assert_allclose(np.array(wn.U[:4 * orc.cfg.N]).reshape(-1, 4), U, rtol=0, atol=0)
-    return dict(err_J=float(err_J[~amb].max()) if (~amb).any() else 0.0, err_U=float(err_U.max()),
-                err_U_e2e=e2e, n_amb=int(amb.sum()), info=info, ref=ref, J=Jd, U=U)
+        np.testing.assert_allclose(np.array(wn.U[:4 * cfg.N]).reshape(-1, 4), U, rtol=0, atol=0)
+    out = dict(err_J=float(err_J[~amb].max()) if (Jd is not None and (~amb).any()) else 0.0,
+               err_U=float(err_U.max()),
+               err_U_e2e=e2e, e2e_bound=bound, n_amb=int(amb.sum()), err_ess=float(err_ess),
+               err_J_min=float(err_min), info=info, ref=ref, J=Jd, U=U)
+    _log(dict(precision="fp64" if precision == M.FP64 else "fp32", K=cfg.K, N=cfg.N, objective=cfg.objective,
+              lam=cfg.lam, sigma=list(cfg.sigma), strict_e2e=bool(strict_e2e), err_J=out["err_J"],
+              err_U=out["err_U"], err_U_e2e=e2e, e2e_bound=bound, n_amb=out["n_amb"],
+              err_ess=out["err_ess"], waves=info["rollout_waves"]))
+    return out

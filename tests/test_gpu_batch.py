@@ -177,3 +177,64 @@ def test_chunk_sizes_give_the_same_bits(monkeypatch):
     B.close()
     for s in solo + bat:
         s.close()
+
+
+def _batch_slice():
+    """Instances of the 256-instance batch workload (K from {1024..16384},
+    N in [30, 150], 5..12 gates, lambda = 1, sigma = 1 N): the first 20, plus
+    the first instances with K = 16384 and with the longest horizons."""
+    spec = synth.batch_instances(256, seed=3)
+    pick = list(range(20))
+    pick += [i for i, s in enumerate(spec) if s["K"] == 16384 and i not in pick][:2]
+    longest = sorted(range(len(spec)), key=lambda i: -spec[i]["N"])
+    pick += [i for i in longest if i not in pick][:2]
+    out = []
+    for i in pick:
+        s = spec[i]
+        out.append((i, synth.single_solve_workload(K=s["K"], N=s["N"], seed=s["seed"], track_seed=s["track_seed"],
+                                                   n_gates=s["n_gates"])))
+    return out
+
+
+@pytest.mark.parametrize("waves", [0, 1], ids=["automatic", "one-wave"])
+def test_batch_against_the_oracle(waves):
+    """Batched binary32 solves of the benchmark's uneven instances, each
+    compared with the FP64 oracle solving from the same exported warm state:
+    a cold and a warm step under a captured graph."""
+    import torch
+    from tests.parity import compare_result
+    sl = _batch_slice()
+    say("batch vs oracle", "waves", waves, "instances", [i for i, _ in sl],
+        "K", [w["params"]["K"] for _, w in sl], "N", [w["params"]["N"] for _, w in sl])
+    assert max(w["params"]["K"] for _, w in sl) == 16384 and max(w["params"]["N"] for _, w in sl) >= 148
+    pairs = [build_pair(w, M.FP32) for _, w in sl]
+    B = M.Batch([d for d, _ in pairs], rollout_waves=waves, use_graph=True)
+    n = len(sl)
+    reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    u0s = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    xs = [w["x0"].copy() for _, w in sl]
+    worst = 0.0
+    for step in range(2):
+        wds = [d.get_warm() for d, _ in pairs]
+        for i, (_, w) in enumerate(sl):
+            reqs[i, :13] = torch.from_numpy(xs[i])
+            reqs[i, 13] = step * w["params"]["dt"]
+        torch.cuda.synchronize()
+        B.solve_device(reqs.data_ptr(), u0s.data_ptr())
+        torch.cuda.synchronize()
+        got = u0s.cpu().numpy()
+        for i, (idx, w) in enumerate(sl):
+            dev, orc = pairs[i]
+            st, info = dev.read_info()
+            assert st == M.OK
+            wn = dev.get_warm()
+            U = np.array(wn.U[:4 * w["params"]["N"]]).reshape(-1, 4)
+            assert np.array_equal(got[i], U[0])
+            Jd, _ = dev.read_samples()
+            r = compare_result(orc, wds[i], xs[i], step * w["params"]["dt"], M.FP32, got[i], U, info, Jd=Jd, wn=wn)
+            worst = max(worst, r["err_U_e2e"])
+            xs[i] = M.plant_step(w["quad"], xs[i], got[i], w["params"]["dt"], 2)
+        say("  step", step, "layout", B.get_cfg(), "worst end-to-end control error", worst)
+    B.close()
+    for d, _ in pairs:
+        d.close()

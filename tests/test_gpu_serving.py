@@ -92,3 +92,56 @@ def test_server_rejects_oversized_and_plain_contexts():
     S.close()
     with pytest.raises(M.MppiError):
         served[0].solve(ws[0]["x0"], 0.0)  # no workspace of its own
+
+
+def test_served_solves_against_the_oracle():
+    """Drones of the serving workload (K in {2048, 8192}, N in {50, 100},
+    gate or contouring objective, lambda = 1, sigma = 1 N): every served
+    solve over three rounds of requests compared with the FP64 oracle from
+    the drone's exported warm state.  A served solve's workspace is lent
+    back to the server when it retires, so its sample costs (needed to replay
+    a decision within the ambiguity margin) come from a twin context of the
+    same drone stepped alone, whose result must equal the served one bit for
+    bit."""
+    from oracle import oracle as O
+    from paper_2509_14726_amd import serving
+    from tests.parity import EPS_DEC, compare_result
+    ws = serving.drone_workloads(6)
+    shapes = [(w["params"]["K"], w["params"]["N"], w["params"]["objective"]) for w in ws]
+    say("served vs oracle", shapes)
+    assert {K for K, _, _ in shapes} == {2048, 8192} and {N for _, N, _ in shapes} == {50, 100}
+    served = [solver(w) for w in ws]
+    twins = [solver(dict(w, params=dict(w["params"], flags=0))) for w in ws]
+    orcs = [O.Problem(w["quad"], dict(w["params"], eps_dec=EPS_DEC[M.FP32], n_threads=8), gates=w["gates"],
+                      path=w.get("path"), path_len=w.get("path_len", 0.0)) for w in ws]
+    S = M.Server(served, budget_bytes=64 * 2 ** 20, n_slots=2, max_batch=3)
+    xs = [w["x0"].copy() for w in ws]
+    worst = 0.0
+    n_amb = 0
+    for k in range(3):
+        wds = [sv.get_warm() for sv in served]
+        t = k * 0.02
+        tick = {S.submit(d, xs[d], t, float(d)): d for d in range(len(ws))}
+        S.drain(1e9)
+        res = S.poll()
+        assert len(res) == len(ws)
+        for r in res:
+            d = tick[r["ticket"]]
+            assert r["status"] == M.OK
+            u0 = np.array(r["u0"])
+            st, info = served[d].read_info()
+            assert st == M.OK
+            wn = served[d].get_warm()
+            U = np.array(wn.U[:4 * ws[d]["params"]["N"]]).reshape(-1, 4)
+            assert np.array_equal(u0, U[0])
+            u0_t, U_t, _ = twins[d].solve(xs[d], t)
+            assert np.array_equal(u0, u0_t) and np.array_equal(U, U_t), (k, d)
+            Jd, _ = twins[d].read_samples()
+            c = compare_result(orcs[d], wds[d], xs[d], t, M.FP32, u0, U, info, Jd=Jd, wn=wn)
+            worst = max(worst, c["err_U_e2e"])
+            n_amb += c["n_amb"]
+            xs[d] = M.plant_step(ws[d]["quad"], xs[d], u0, 0.02, 4)
+        say("  round", k, "worst end-to-end control error", worst, "ambiguous samples so far", n_amb)
+    S.close()
+    for sv in served + twins:
+        sv.close()

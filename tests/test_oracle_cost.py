@@ -342,18 +342,28 @@ def _glide_absJ(gates):
     return r["J"][0], r["absJ"][0]
 
 
-def test_term_magnitude_sum_of_one_signed_terms_is_the_cost_magnitude():
-    # toward a gate 20 m ahead: every progress term is negative, J = 18^2 - 20^2
+def _progress_magnitude(d):
+    """Sum over the 20 steps of both squared distances of each Eq. (6) term,
+    for the distances d(k) of state k to the gate centre."""
+    return sum(d(k) ** 2 + d(k + 1) ** 2 for k in range(20))
+
+
+def test_term_magnitude_sum_of_one_signed_terms():
+    # toward a gate 20 m ahead: J = 18^2 - 20^2, each term a difference of the
+    # squared distances 20 - 0.1 k and 20 - 0.1 (k + 1)
     J, A = _glide_absJ([[20.0, 0.0, 2.0, 0.0], [40.0, 0.0, 2.0, 0.0]])
-    assert abs(J - (18.0 ** 2 - 20.0 ** 2)) < 1e-9 and abs(A + J) < 1e-9
-    # away from a gate 20 m behind: every term is positive, J = 22^2 - 20^2
+    assert abs(J - (18.0 ** 2 - 20.0 ** 2)) < 1e-9
+    assert abs(A - _progress_magnitude(lambda k: 20.0 - 0.1 * k)) < 1e-8
+    # away from a gate 20 m behind: J = 22^2 - 20^2
     J, A = _glide_absJ([[-20.0, 0.0, 2.0, math.pi], [40.0, 0.0, 2.0, 0.0]])
-    assert abs(J - (22.0 ** 2 - 20.0 ** 2)) < 1e-9 and abs(A - J) < 1e-9
+    assert abs(J - (22.0 ** 2 - 20.0 ** 2)) < 1e-9
+    assert abs(A - _progress_magnitude(lambda k: 20.0 + 0.1 * k)) < 1e-8
 
 
 def test_term_magnitude_sum_of_a_telescoped_cost():
     # past a gate 0.5 m to the side (its plane along x is never crossed): the
     # squared distance falls from 1.25 to 0.25 at x = 1 and rises back to
-    # 1.25, so J = 0 while the terms add up to 2 in magnitude
+    # 1.25, so J = 0 while the magnitude sum stays that of the squares
     J, A = _glide_absJ([[1.0, 0.5, 2.0, math.pi / 2], [40.0, 0.0, 2.0, 0.0]])
-    assert abs(J) < 1e-12 and abs(A - 2.0) < 1e-9
+    assert abs(J) < 1e-12
+    assert abs(A - _progress_magnitude(lambda k: math.hypot(0.1 * k - 1.0, 0.5))) < 1e-9
