@@ -22,10 +22,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of one rollout step of the gate objective, counted from the
-# method's definition (see the design notes): RK4 of Eq. (2) 437 flops, gate
-# cost (Eq. (6)-(7), switch test, rate penalty) 58 flops.
-FLOPS_PER_ROLLOUT_STEP = 495
+# Algorithmic work of one rollout step of the gate objective, counted by the
+# oracle's op-counting build (the oracle's own source with binary64 counted):
+# the mean over the first 256 samples of the cold benchmark solve of its
+# additions, multiplications, divisions and square roots per sample and step,
+# 24.0 for the sampling of Eq. (3) and 544.1 for RK4 of Eq. (2) with the gate
+# cost of Eq. (6)-(7), the switch test and the rate penalty.  A CPU test
+# recounts it.
+FLOPS_PER_ROLLOUT_STEP = 568.1
 # Peak FP32 vector throughput of MI355X (256 CUs, 2.4 GHz, packed FMA)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBPS = 8000.0
@@ -73,25 +77,107 @@ def traffic_bytes(kernel: str, workload=(8192, 100, "fp32", 0)):
     return (f * FETCH_SCALE + w * WRITE_SCALE) * 1024.0
 
 
-def cpu_baseline(w, seconds: float = 12.0):
-    """The FP64 oracle as it stands, on all host cores (at most 16), repeated
-    full solves of the benchmark workload for about `seconds` seconds."""
+def _cpu_info():
+    """Host CPU model, logical CPUs of the machine and of this process."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def _oracle_problem(w, cores, eps_dec=0.0):
     from oracle import oracle as O
-    cores = min(os.cpu_count() or 1, 16)
-    prm = dict(w["params"], eps_dec=0.0, n_threads=cores)
-    pb = O.Problem(w["quad"], prm, gates=w["gates"])
+    prm = dict(w["params"], eps_dec=eps_dec, n_threads=cores)
+    return O.Problem(w["quad"], prm, gates=w["gates"], path=w.get("path"), path_len=w.get("path_len", 0.0),
+                     xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0))
+
+
+def _time_oracle(w, cores, seconds):
+    from oracle import oracle as O
+    pb = _oracle_problem(w, cores)
     warm = pb.warm()
-    K, N = prm["K"], prm["N"]
+    K, N = pb.cfg.K, pb.cfg.N
     n, t0 = 0, time.perf_counter()
     while True:
-        r = pb.solve(warm, w["x0"], n * prm["dt"])
+        r = pb.solve(warm, w["x0"], n * pb.cfg.dt)
         assert r["status"] == O.OK
         n += 1
         el = time.perf_counter() - t0
         if el >= seconds or n >= 1000:
             break
-    return {"value": n * K * N / el, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} full solves of the benchmark workload (K={K}, N={N}) in {el:.1f} s, FP64"}
+    return n * K * N / el, n, el
+
+
+def oracle_errors(w, rec, cores):
+    """Error of one device solve against the FP64 oracle solving from the
+    device's exported warm state: the largest relative cost error (samples
+    whose decision lies within 1e-4 of a threshold excluded), the update
+    stage (the oracle's Eq. (4)-(5) fed with the device's costs) and the
+    controls end to end (the oracle's own costs; the device's only for those
+    ambiguous samples), relative to max(|U|, sigma); plus J_min and ESS."""
+    import numpy as np
+    from oracle import oracle as O
+    pb = _oracle_problem(w, cores, eps_dec=1e-4)
+
+    def warm():
+        wd = rec["warm"]
+        o = pb.warm(wd.g0)
+        o.warm = wd.warm
+        o.s = wd.solve_index
+        for j in range(O.MASK_WORDS):
+            o.allow[j] = wd.allow[j]
+        o.t_prev = wd.t_prev
+        o.x_prev[:] = list(wd.x_prev)
+        o.theta0 = wd.theta0
+        o.U[:] = list(wd.U)
+        o.V[:] = list(wd.V)
+        return o
+
+    t0 = time.perf_counter()
+    r = pb.solve(warm(), rec["x0"], rec["t"])
+    amb = r["margin"] < 1e-4
+    Jd = rec["J"]
+    fin = np.isfinite(r["J"]) & np.isfinite(Jd) & ~amb
+    scale = np.maximum(np.abs(r["J"]), r["absJ"])
+    err_J = float((np.abs(Jd - r["J"])[fin] / scale[fin]).max())
+    e2e = r if not amb.any() else pb.solve(warm(), rec["x0"], rec["t"], J_rep=Jd, rep_mask=amb.astype(np.uint8))
+    stage = pb.solve(warm(), rec["x0"], rec["t"], J_rep=Jd, rep_mask=np.ones(Jd.size, np.uint8))
+    sig = max(w["params"]["sigma"])
+    U = rec["U"]
+    return {"K": pb.cfg.K, "N": pb.cfg.N, "err_J": err_J,
+            "err_U": float((np.abs(U - stage["U"]) / np.maximum(np.abs(stage["U"]), sig)).max()),
+            "err_U_e2e": float((np.abs(U - e2e["U"]) / np.maximum(np.abs(e2e["U"]), sig)).max()),
+            "err_J_min": abs(rec["info"]["J_min"] - stage["J_min"]) / max(abs(stage["J_min"]), 1e-300),
+            "err_ess": abs(rec["info"]["ess"] - stage["ess"]) / stage["ess"],
+            "ambiguous_samples": int(amb.sum()), "oracle_s": time.perf_counter() - t0}
+
+
+def cpu_baseline(w, seconds: float = 12.0, single_seconds: float = 6.0):
+    """The FP64 oracle as it stands on the host cores, repeated full solves
+    of the benchmark workload for about `seconds` seconds with OpenMP over
+    the samples, and for about `single_seconds` on one thread.  The thread
+    count is the CPUs this process may run on, at most 16: the GPU host
+    allots 16 CPUs per GPU, whatever the machine has."""
+    model, nproc, usable = _cpu_info()
+    cores = min(usable, 16)
+    v, n, el = _time_oracle(w, cores, seconds)
+    v1, n1, el1 = _time_oracle(w, 1, single_seconds)
+    K, N = w["params"]["K"], w["params"]["N"]
+    return {"value": v, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} full solves of the benchmark workload (K={K}, N={N}) in {el:.1f} s, FP64, "
+                      f"{cores} threads; {n1} solves in {el1:.1f} s on one thread",
+            "single_thread_value": v1, "cpu_model": model, "nproc": nproc, "cpus_usable": usable,
+            "thread_cap": "16 threads: the CPU share of one GPU on the GPU host"}
 
 
 def batched_bench(steps: int = 20, n: int = 256):
@@ -292,15 +378,30 @@ def large_bench(steps: int = 5):
     ms = e0.elapsed_time(e1) / steps
     kern, _ = sv.read_profile()
     _, info = sv.read_info()
+    rec = _accuracy_record(sv, w["x0"], (steps + 1) * 0.01)
     sv.close()
     K, N = 262144, 200
-    avg_bytes = K * N * 16 + K * 4 * N  # sample tensor + costs re-read per step tile
+    # algorithmic bytes of the average: the sample tensor, the costs and the
+    # tile minima, each read once (the blocks of later steps find the costs
+    # in L2)
+    avg_bytes = K * N * 16 + K * 4 + ((K + 64) // 64) * 4
     # with the rollout drawing its samples the first slot times the head kernel
     return {"K": K, "N": N, "ms_per_solve": ms, "rollout_steps_per_s": K * N / (ms * 1e-3),
             "rollout_draws_samples": bool(info["rollout_draw"]),
             "kernels_ms": {"head" if info["rollout_draw"] else "sample": float(kern[0]),
                            "rollout": float(kern[1]), "average": float(kern[2])},
-            "average_GBps": avg_bytes / (float(kern[2]) * 1e-3) / 1e9}
+            "average_bytes_per_launch": avg_bytes,
+            "average_GBps": avg_bytes / (float(kern[2]) * 1e-3) / 1e9}, w, rec
+
+
+def _accuracy_record(sv, x0, t):
+    """One more solve through the host entry point, with the warm state it
+    started from and its sample costs: what the oracle comparison needs."""
+    import numpy as np
+    wd = sv.get_warm()
+    u0, U, info = sv.solve(x0, t)
+    J, _ = sv.read_samples()
+    return {"warm": wd, "x0": np.array(x0, dtype=np.float64), "t": t, "u0": u0, "U": U, "info": info, "J": J}
 
 
 def copy_calibration(mib: int, reps: int = 3):
@@ -399,7 +500,7 @@ def main():
         import torch
         # the extras time on the current stream: make it one of our own
         torch.cuda.set_stream(torch.cuda.Stream(torch.device("cuda:0")))
-        print(json.dumps({"large": large_bench(steps=2)}), flush=True)
+        print(json.dumps({"large": large_bench(steps=2)[0]}), flush=True)
         return
 
     import torch
@@ -459,9 +560,10 @@ def main():
     value = K * N / (ms_per_step * 1e-3)
     roll_ms = float(kern_ms[1])
     avg_ms = float(kern_ms[2])
-    # algorithmic bytes of the weighted average: the sample tensor and the
-    # costs (read once per step block), the tile minima
-    avg_bytes = K * N * 16 + K * 4 * N + ((K + 64) // 64) * 4 * N
+    # algorithmic bytes of the weighted average: the sample tensor, the costs
+    # and the tile minima, each read once (every horizon step's block reads
+    # all costs, but only the first reaches HBM: L2 serves the others)
+    avg_bytes = K * N * 16 + K * 4 + ((K + 64) // 64) * 4
     if info["regen_average"]:  # the samples are drawn again, not read
         avg_bytes -= K * N * 16
     flops = FLOPS_PER_ROLLOUT_STEP * K * N
@@ -500,12 +602,17 @@ def main():
         out["average_kernel"] = {"bound": "alu", "kernel": "k_final", "redraws_per_launch": K * N,
                                  "redraws_per_s": K * N / (avg_ms * 1e-3), "cus_used": min(N, 256),
                                  "bytes_per_launch": avg_bytes, "traffic": traffic_bytes("k_final", wl)}
+    acc_records = [(w, _accuracy_record(solver, w["x0"], total * prm["dt"]))]
     solver.close()
     if not args.no_extras:
         for name, fn in (("batched", batched_bench), ("large", large_bench), ("closed_loop", closed_loop_race),
                          ("paper_table_config", paper_table_config), ("fp64", fp64_solve)):
             try:
-                out[name] = fn()
+                res = fn()
+                if name == "large":
+                    res, w_large, rec_large = res
+                    acc_records.append((w_large, rec_large))
+                out[name] = res
             except Exception as e:  # reported, never silently dropped
                 out[name] = {"error": repr(e)}
         try:
@@ -516,6 +623,15 @@ def main():
             out["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        # the FP64 oracle from each measured solve's exported warm state
+        cores = out["cpu_baseline"]["cores"]
+        out["accuracy"] = {}
+        for wk, rec in acc_records:
+            key = "metric" if wk is w else "large"
+            try:
+                out["accuracy"][key] = oracle_errors(wk, rec, cores)
+            except Exception as e:
+                out["accuracy"][key] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

@@ -95,8 +95,9 @@ static void rot_matrix(const double q[4], double R[9])
 void orc_f(const orc_quad *qd, const double x[13], const double T[4], double xd[13])
 {
     const double *v = x + 3, *q = x + 6, *w = x + 10;
-    double R[9];
-    rot_matrix(q, R);
+    const double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+    /* third column of R(q): the body z axis in the world frame */
+    const double r3[3] = {2.0 * (qx * qz + qw * qy), 2.0 * (qy * qz - qw * qx), 1.0 - 2.0 * (qx * qx + qy * qy)};
 
     /* collective thrust along body z, T = [0, 0, sum T_s] */
     double F = T[0] + T[1] + T[2] + T[3];
@@ -109,14 +110,22 @@ void orc_f(const orc_quad *qd, const double x[13], const double T[4], double xd[
     /* p' = v */
     xd[0] = v[0]; xd[1] = v[1]; xd[2] = v[2];
 
-    /* v' = g + R T / m - R D R^T v */
-    double bv[3], dv[3];
-    for (int i = 0; i < 3; ++i) bv[i] = R[0 + i] * v[0] + R[3 + i] * v[1] + R[6 + i] * v[2]; /* R^T v */
-    for (int i = 0; i < 3; ++i) bv[i] *= qd->drag[i];                                        /* D R^T v */
-    for (int i = 0; i < 3; ++i) dv[i] = R[3 * i + 0] * bv[0] + R[3 * i + 1] * bv[1] + R[3 * i + 2] * bv[2];
-    xd[3] = R[2] * F / qd->mass - dv[0];
-    xd[4] = R[5] * F / qd->mass - dv[1];
-    xd[5] = R[8] * F / qd->mass - qd->gravity - dv[2];
+    /* v' = g + R T / m - R D R^T v; the drag term vanishes for D = 0 */
+    double dv[3] = {0.0, 0.0, 0.0};
+    if (qd->drag[0] != 0.0 || qd->drag[1] != 0.0 || qd->drag[2] != 0.0) {
+        double R[9], bv[3];
+        rot_matrix(q, R);
+        for (int i = 0; i < 3; ++i) bv[i] = R[0 + i] * v[0] + R[3 + i] * v[1] + R[6 + i] * v[2]; /* R^T v */
+        for (int i = 0; i < 3; ++i) bv[i] *= qd->drag[i];                                        /* D R^T v */
+        for (int i = 0; i < 3; ++i) dv[i] = R[3 * i + 0] * bv[0] + R[3 * i + 1] * bv[1] + R[3 * i + 2] * bv[2];
+        xd[3] = r3[0] * F / qd->mass - dv[0];
+        xd[4] = r3[1] * F / qd->mass - dv[1];
+        xd[5] = r3[2] * F / qd->mass - qd->gravity - dv[2];
+    } else {
+        xd[3] = r3[0] * F / qd->mass;
+        xd[4] = r3[1] * F / qd->mass;
+        xd[5] = r3[2] * F / qd->mass - qd->gravity;
+    }
 
     /* q' = 1/2 q (x) [0, w] */
     xd[6] = 0.5 * (-q[1] * w[0] - q[2] * w[1] - q[3] * w[2]);
@@ -140,14 +149,15 @@ void orc_f(const orc_quad *qd, const double x[13], const double T[4], double xd[
 void orc_rk4(const orc_quad *qd, const double x[13], const double T[4], double dt, double xn[13])
 {
     double k1[13], k2[13], k3[13], k4[13], xs[13];
+    const double h2 = 0.5 * dt, h6 = dt / 6.0;
     orc_f(qd, x, T, k1);
-    for (int i = 0; i < 13; ++i) xs[i] = x[i] + 0.5 * dt * k1[i];
+    for (int i = 0; i < 13; ++i) xs[i] = x[i] + h2 * k1[i];
     orc_f(qd, xs, T, k2);
-    for (int i = 0; i < 13; ++i) xs[i] = x[i] + 0.5 * dt * k2[i];
+    for (int i = 0; i < 13; ++i) xs[i] = x[i] + h2 * k2[i];
     orc_f(qd, xs, T, k3);
     for (int i = 0; i < 13; ++i) xs[i] = x[i] + dt * k3[i];
     orc_f(qd, xs, T, k4);
-    for (int i = 0; i < 13; ++i) xn[i] = x[i] + dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    for (int i = 0; i < 13; ++i) xn[i] = x[i] + h6 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
     double nq = sqrt(xn[6] * xn[6] + xn[7] * xn[7] + xn[8] * xn[8] + xn[9] * xn[9]);
     for (int i = 6; i < 10; ++i) xn[i] /= nq;
 }
@@ -179,11 +189,14 @@ int orc_gate_cross(const double pa[3], const double pb[3], const double gate[4],
     double half = 0.5 * size;
     double sa = (pa[0] - gate[0]) * nx + (pa[1] - gate[1]) * ny;
     double sb = (pb[0] - gate[0]) * nx + (pb[1] - gate[1]) * ny;
+    /* the margin is bookkeeping for the tests, computed only when asked for */
     double m = INFINITY;
-    double ma = fabs(sa), oa = outside_aperture(pa, gate, half);
-    double mb = fabs(sb), ob = outside_aperture(pb, gate, half);
-    if ((ma > oa ? ma : oa) < m) m = (ma > oa ? ma : oa);
-    if ((mb > ob ? mb : ob) < m) m = (mb > ob ? mb : ob);
+    if (margin) {
+        double ma = fabs(sa), oa = outside_aperture(pa, gate, half);
+        double mb = fabs(sb), ob = outside_aperture(pb, gate, half);
+        if ((ma > oa ? ma : oa) < m) m = (ma > oa ? ma : oa);
+        if ((mb > ob ? mb : ob) < m) m = (mb > ob ? mb : ob);
+    }
     int crossed = 0;
     if (sa < 0.0 && sb >= 0.0) {
         double t = sa / (sa - sb);
@@ -191,9 +204,11 @@ int orc_gate_cross(const double pa[3], const double pb[3], const double gate[4],
                        pa[2] + t * (pb[2] - pa[2])};
         double lat = (y[0] - gate[0]) * hx + (y[1] - gate[1]) * hy;
         double ver = y[2] - gate[2];
-        double el = fabs(fabs(lat) - half), ev = fabs(fabs(ver) - half);
-        if (el < m) m = el;
-        if (ev < m) m = ev;
+        if (margin) {
+            double el = fabs(fabs(lat) - half), ev = fabs(fabs(ver) - half);
+            if (el < m) m = el;
+            if (ev < m) m = ev;
+        }
         crossed = (fabs(lat) <= half) && (fabs(ver) <= half);
     }
     if (margin) *margin = m;
@@ -389,7 +404,7 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
             double d2 = sqdist3(x, gate0);
             double d = sqrt(d2);
             if (d < c->r_near) ORC_ADD(c->q_near * d2);
-            if (fabs(d - c->r_near) < mrg) mrg = fabs(d - c->r_near);
+            if (margin && fabs(d - c->r_near) < mrg) mrg = fabs(d - c->r_near);
         }
 
         orc_rk4(q, x, Uk, c->dt, xn);
@@ -407,8 +422,8 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
 
         if (c->objective == ORC_OBJ_GATE) {
             const double *gc = c->gates + 4 * g;
-            double mk;
-            int crossed = orc_gate_cross(x, xn, gc, c->gate_size, &mk);
+            double mk = INFINITY;
+            int crossed = orc_gate_cross(x, xn, gc, c->gate_size, margin ? &mk : NULL);
             if (mk < mrg) mrg = mk;
             if (crossed && (passes > 0 || get_bit(allow, k + 1))) {
                 g = (g + 1) % c->n_gates;

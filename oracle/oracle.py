@@ -16,6 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
 SRC = os.path.join(HERE, "mppi_oracle.c")
+COUNT_LIB_PATH = os.path.join(HERE, "liborc_count.so")
+COUNT_SRC = os.path.join(HERE, "opcount.cpp")
 
 NMAX = 256
 MASK_WORDS = 9
@@ -24,13 +26,20 @@ OK, EINVAL, ENONFINITE = 0, -1, -4
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C99, no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (plain C99, no fast-math, no FMA contraction),
+    and its op-counting build (the same source as C++ with binary64 counted)."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call([
             "gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-fopenmp",
             "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB_PATH)
+    if force or not os.path.exists(COUNT_LIB_PATH):
+        tmp = COUNT_LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "g++", "-O2", "-std=c++17", "-Wall", "-Wno-unknown-pragmas", "-Wno-unused-variable",
+            "-fPIC", "-shared", "-ffp-contract=off", "-o", tmp, COUNT_SRC, "-lm"])
+        os.replace(tmp, COUNT_LIB_PATH)
     return LIB_PATH
 
 
@@ -110,6 +119,50 @@ def lib():
         L.orc_warm_init.argtypes = [C.POINTER(Warm), C.c_int32]
         _lib = L
     return _lib
+
+
+_count_lib = None
+
+
+def count_lib():
+    """The op-counting build: the oracle's functions plus orc_ops_reset /
+    orc_ops_read (add, mul, div, sqrt, transcendental, other)."""
+    global _count_lib
+    if _count_lib is None:
+        if not os.path.exists(COUNT_LIB_PATH):
+            build(force=False)
+        L = C.CDLL(COUNT_LIB_PATH)
+        L.orc_ops_reset.argtypes = []
+        L.orc_ops_read.argtypes = [C.POINTER(C.c_int64)]
+        L.orc_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _D]
+        L.orc_f.argtypes = [C.POINTER(Quad), _D, _D, _D]
+        L.orc_rk4.argtypes = [C.POINTER(Quad), _D, _D, C.c_double, _D]
+        L.orc_sample.argtypes = [C.POINTER(Cfg), C.POINTER(Quad), _D, _D, C.c_uint32, C.c_uint32, _D, _D]
+        L.orc_rollout_cost.argtypes = [C.POINTER(Cfg), C.POINTER(Quad), _D, _D, _D, C.c_int32,
+                                       C.POINTER(C.c_uint32), _D, C.c_double, C.c_double,
+                                       C.c_int32, _D, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        L.orc_rollout_cost.restype = C.c_double
+        _count_lib = L
+    return _count_lib
+
+
+OP_CLASSES = ("add", "mul", "div", "sqrt", "trans", "other")
+
+
+def counted(call) -> dict:
+    """Run call(count_lib()) and return the operations it counted."""
+    L = count_lib()
+    L.orc_ops_reset()
+    call(L)
+    out = (C.c_int64 * 6)()
+    L.orc_ops_read(out)
+    return {k: int(v) for k, v in zip(OP_CLASSES, out)}
+
+
+def flops(ops: dict) -> int:
+    """Floating-point operations of a count: additions, multiplications,
+    divisions and square roots (transcendentals are counted apart)."""
+    return ops["add"] + ops["mul"] + ops["div"] + ops["sqrt"]
 
 
 def _dp(a):
@@ -246,6 +299,45 @@ class Problem:
         if nominal:
             return J, float(mg[0]), list(fr), list(fa)
         return J, float(mg[0])
+
+    def rollout_step_ops(self, x0, n_samples: int = 64, s: int = 0) -> dict:
+        """Operations per rollout step of a cold solve from x0 (nominal at
+        hover thrust), counted by the op-counting build over samples
+        0..n_samples-1: 'sample' (Eq. (3): normals, perturbation, clipping)
+        and 'rollout' (Eq. (2) integrated with the objective's cost), each the
+        mean count per sample and step, plus their flops."""
+        N = self.cfg.N
+        hover = self.quad_d["mass"] * self.quad_d["gravity"] / 4.0
+        Us = np.full(4 * N, hover)
+        Vs = np.zeros(N)
+        x0 = _arr(x0, 13)
+        theta0 = self.project(x0[:3]) if self.cfg.objective == OBJ_CONTOUR else 0.0
+        al = (C.c_uint32 * MASK_WORDS)(*([0xffffffff] * MASK_WORDS))
+        up = np.full(4, hover)
+        samples = []
+        for m in range(n_samples):
+            U = np.zeros(4 * N)
+            V = np.zeros(N)
+            samples.append((U, V))
+
+        def do_sample(L):
+            for m, (U, V) in enumerate(samples):
+                L.orc_sample(C.byref(self.cfg), C.byref(self.quad), _dp(Us), _dp(Vs), m, s, _dp(U), _dp(V))
+
+        def do_rollout(L):
+            for U, V in samples:
+                L.orc_rollout_cost(C.byref(self.cfg), C.byref(self.quad), _dp(x0), _dp(U), _dp(V), 0, al,
+                                   _dp(up), 0.0, float(theta0), 0, None, None, None)
+
+        per = float(n_samples * N)
+        out = {}
+        for name, fn in (("sample", do_sample), ("rollout", do_rollout)):
+            ops = counted(fn)
+            d = {k: v / per for k, v in ops.items()}
+            d["flops"] = flops(ops) / per
+            out[name] = d
+        out["flops_per_step"] = out["sample"]["flops"] + out["rollout"]["flops"]
+        return out
 
     def solve(self, warm: Warm, x0, t_now=0.0, J_rep=None, rep_mask=None):
         """One MPPI step; returns a dict of outputs.  warm is updated in place."""
