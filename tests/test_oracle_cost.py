@@ -190,6 +190,32 @@ def test_near_gate_term():
         assert abs(margin - min(abs(d - 1.0), d)) < 1e-12
 
 
+def test_near_term_stays_with_the_current_gate_after_a_switch():
+    """Eq. (7) is measured from the current gate g0 of the solve for every
+    state, also after a rollout has passed g0 and targets the next gate:
+    gliding through gate 0 at 10 m/s (q_near = 5, r_near = 1 m), the states
+    within 1 m of gate 0 on both sides of its plane are charged, and the
+    second gate, far away, charges nothing."""
+    N, dt = 20, 0.02
+    g0 = [0.0, 0.0, 2.0, 0.0]
+    g1 = [30.0, 0.0, 2.0, 0.0]
+    pb = gate_problem([g0, g1], N, q_near=5.0, r_near=1.0, w_lim=0.0)
+    x0, P = _fly_through(N, dt)
+    U = np.full((N, 4), HOVER)
+    J, _ = pb.rollout_cost(x0, U)
+    c0, c1 = np.array(g0[:3]), np.array(g1[:3])
+    t = int(np.argmax(P[:, 0] >= 0))
+    progress = (np.sum((P[t] - c0) ** 2) - np.sum((P[0] - c0) ** 2)
+                + np.sum((P[-1] - c1) ** 2) - np.sum((P[t] - c1) ** 2))
+    d = np.linalg.norm(P[:N] - c0, axis=1)
+    near = np.sum(np.where(d < 1.0, 5.0 * d * d, 0.0))
+    assert np.sum((d < 1.0) & (P[:N, 0] >= 0)) >= 3  # charged after the pass
+    assert abs(J - (progress + near)) < 1e-9
+    # with the second gate as the solve's current gate, nothing is near
+    J1, _ = pb.rollout_cost(x0, U, g0=1)
+    assert abs(J1 - (np.sum((P[-1] - c1) ** 2) - np.sum((P[0] - c1) ** 2))) < 1e-9
+
+
 def test_body_rate_penalty():
     # constant yaw spin at 12 rad/s with a 10 rad/s bound: w_lim (12-10)^2 per step
     N = 15
@@ -246,6 +272,51 @@ def test_tracking_offset_and_rate_terms():
     J2, _ = pb.rollout_cost(X[i0], U, u_prev=np.full(4, 2.0), i0=i0)
     R = synth.BASE["R_dT"][0]
     assert abs(J2 - J - 4 * R * (1.0 / dt) ** 2) < 1e-9
+
+
+def _glide_reference(rows, i_star, dt, v=3.0):
+    """Rows of a level glide at hover thrust along +x at v m/s, row i_star at
+    x = 0 (row r at time (r - i_star) dt)."""
+    X = np.zeros((rows, 13))
+    for r in range(rows):
+        X[r, 0] = v * (r - i_star) * dt
+        X[r, 2] = 2.0
+        X[r, 3] = v
+        X[r, 6] = 1.0
+    return X
+
+
+@pytest.mark.parametrize("t_over_dt,row", [(7.0, 7), (7.49, 7), (6.5, 7), (7.5, 8), (7.51, 8), (-3.0, 0)])
+def test_tracking_row_of_the_initial_state(t_over_dt, row):
+    """The reference row aligned with x0 is t_now / ref_dt rounded half up
+    (ref_dt = 0.25 s: the half-way times are exact), clamped at 0: a noise-free
+    solve from the glide's row-7 state costs nothing exactly when that row is
+    7 (the glide is an exact trajectory of the model)."""
+    N, dt = 12, 0.25
+    X = _glide_reference(60, 7, dt)
+    prm = synth.params(1, N, "track", 1, dt=dt, sigma=(0.0,) * 4, w_lim=0.0, eps_dec=0.0)
+    pb = O.Problem(QUAD, prm, xref=X, ref_dt=dt)
+    r = pb.solve(pb.warm(), X[7], t_over_dt * dt)
+    assert r["status"] == O.OK and r["i0"] == row
+    if row == 7:
+        assert abs(r["J"][0]) < 1e-12
+    else:
+        assert r["J"][0] > 1.0
+
+
+def test_tracking_row_past_the_end_of_the_table():
+    """Past the last row the index is the last row, and every later row of
+    the horizon is held at it: a hover at the last row's state costs nothing."""
+    N, dt = 12, 0.02
+    X = _glide_reference(10, 0, dt)
+    X[-1, 3] = 0.0  # the last row hovers
+    prm = synth.params(1, N, "track", 1, dt=dt, sigma=(0.0,) * 4, w_lim=0.0, eps_dec=0.0)
+    pb = O.Problem(QUAD, prm, xref=X, ref_dt=dt)
+    r = pb.solve(pb.warm(), X[-1], 1000.0)
+    assert r["status"] == O.OK and r["i0"] == 9
+    assert abs(r["J"][0]) < 1e-12
+    r = pb.solve(pb.warm(), X[-1], 8.0 * dt)  # row 8: the horizon runs off the end
+    assert r["i0"] == 8 and r["J"][0] > 1.0
 
 
 # ---------------------------------------------------------------- contouring

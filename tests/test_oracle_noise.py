@@ -93,3 +93,50 @@ def test_counter_words_select_independent_streams():
     assert not np.allclose(a, O.normals(1, 5, 6, 8, 0))  # solve counter
     assert not np.allclose(a, O.normals(1, 6, 5, 7, 0))  # m and k not symmetric
     assert not np.allclose(a, O.normals(2, 5, 6, 7, 0))  # seed
+
+
+def _python_normals(seed, m, k, s, ch):
+    """Box-Muller of the Philox words of counter (m, k, s, ch), evaluated
+    with Python's libm (the words themselves are pinned by the KAT above)."""
+    w = O.philox([m, k, s, ch], [seed & 0xFFFFFFFF, seed >> 32])
+    u = [(2 * (x >> 9) + 1) / 16777216.0 for x in w]
+    r0 = math.sqrt(-2.0 * math.log(u[0]))
+    r1 = math.sqrt(-2.0 * math.log(u[2]))
+    return [r0 * math.cos(2 * math.pi * u[1]), r0 * math.sin(2 * math.pi * u[1]),
+            r1 * math.cos(2 * math.pi * u[3]), r1 * math.sin(2 * math.pi * u[3])]
+
+
+@pytest.mark.parametrize("objective", ["gate", "contour"])
+def test_sampler_channel_map_and_clip_after_perturbation(objective):
+    """Eq. (3) with per-rotor sigma: U^m_k[i] = clip(U*_k[i] + sigma_i z_i) with
+    z_i the i-th normal of block (m, k, s, 0), each channel its own sigma
+    (distinct values, so a swapped channel shows), clipped after the noise is
+    added (U* sits at and next to the bounds, so clipping first would leave
+    values outside them); contouring's speed V^m_k = clip(V*_k + sigma_v z,
+    0, v_max) with z the first normal of block (m, k, s, 1)."""
+    from paper_2509_14726_amd import synth
+    N, seed, s = 9, 0x1234_5678_9ABC, 5
+    sig = (0.3, 1.1, 2.7, 0.05)
+    prm = synth.params(1, N, objective, seed, sigma=sig, sigma_v=3.0, v_max=4.0)
+    w = synth.single_solve_workload(K=1, N=N, objective=objective, seed=seed)
+    pb = O.Problem(synth.QUAD, prm, gates=w["gates"], path=w.get("path"), path_len=w.get("path_len", 0.0))
+    lo, hi = synth.QUAD["t_min"], synth.QUAD["t_max"]
+    Ustar = np.array([[hi, 6.9, 0.05, lo], [lo, 0.2, 3.0, hi], [3.5, hi, lo, 6.95]] * 3)[:N]
+    Vstar = np.array([0.0, 4.0, 2.0, 3.9, 0.1, 4.0, 0.0, 1.0, 2.5])[:N]
+    n_clipped = n_inside = 0
+    for m in (0, 1, 17, 1023, 65535):
+        U, V = pb.sample(Ustar.ravel(), Vstar, m, s)
+        for k in range(N):
+            z = _python_normals(seed, m, k, s, 0)
+            for i in range(4):
+                raw = Ustar[k, i] + sig[i] * z[i]
+                want = min(max(raw, lo), hi)
+                assert abs(U[k, i] - want) <= 1e-14 * max(1.0, abs(want)), (m, k, i)
+                if raw < lo or raw > hi:
+                    n_clipped += 1
+                else:
+                    n_inside += 1
+            if objective == "contour":
+                zv = _python_normals(seed, m, k, s, 1)[0]
+                assert abs(V[k] - min(max(Vstar[k] + 3.0 * zv, 0.0), 4.0)) <= 1e-14, (m, k)
+    assert n_clipped > 20 and n_inside > 20
