@@ -625,14 +625,15 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
     }
     uint32_t front[ORC_MASK_WORDS], front_amb[ORC_MASK_WORDS];
     for (int j = 0; j < ORC_MASK_WORDS; ++j) { front[j] = 0xffffffffu; front_amb[j] = 0u; }
-    double Jnom;
+    double Jnom, Anom = 0.0;
     if (c->objective == ORC_OBJ_GATE)
-        Jnom = orc_rollout_cost(c, q, x0, Un, Vn, g0, allow, u_prev, v_prev, theta0, i0, NULL,
-                                front, front_amb);
+        Jnom = orc_rollout_cost_ex(c, q, x0, Un, Vn, g0, allow, u_prev, v_prev, theta0, i0, NULL,
+                                   front, front_amb, &Anom);
     else
-        Jnom = orc_rollout_cost(c, q, x0, Un, Vn, g0, allow, u_prev, v_prev, theta0, i0, NULL,
-                                NULL, NULL);
+        Jnom = orc_rollout_cost_ex(c, q, x0, Un, Vn, g0, allow, u_prev, v_prev, theta0, i0, NULL,
+                                   NULL, NULL, &Anom);
     out->J_nom = Jnom;
+    out->absJ_nom = Anom;
     memcpy(out->front, front, sizeof front);
     memcpy(out->front_amb, front_amb, sizeof front_amb);
 

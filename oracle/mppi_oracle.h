@@ -100,6 +100,7 @@ typedef struct {
     uint32_t front_amb[ORC_MASK_WORDS]; /* front decisions within eps_dec of the plane */
     double *absJ;    /* K   sum of the magnitudes of the quantities a sample's cost adds or
                         subtracts (both squared distances of each Eq. (6) term; may be NULL) */
+    double absJ_nom; /* the same sum for the nominal rollout                           */
 } orc_out;
 
 /* ---- building blocks (exported for the pin tests) ---------------------- */

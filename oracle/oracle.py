@@ -82,7 +82,8 @@ class Out(C.Structure):
                 ("g0", C.c_int32), ("i0", C.c_int32), ("shift", C.c_int32), ("n_amb", C.c_int32),
                 ("status", C.c_int32), ("pad_", C.c_int32),
                 ("allow", C.c_uint32 * MASK_WORDS), ("front", C.c_uint32 * MASK_WORDS),
-                ("front_amb", C.c_uint32 * MASK_WORDS), ("absJ", C.POINTER(C.c_double))]
+                ("front_amb", C.c_uint32 * MASK_WORDS), ("absJ", C.POINTER(C.c_double)),
+                ("absJ_nom", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -358,7 +359,7 @@ class Problem:
                              C.byref(o))
         return dict(status=st, J=J, w=w, U=U.reshape(N, 4), V=V, margin=mg, absJ=A,
                     Ustar=Us.reshape(N, 4), Vstar=Vs, J_min=o.J_min, S=o.S, ess=o.ess,
-                    J_nom=o.J_nom, theta0=o.theta0, g0=o.g0, i0=o.i0, shift=o.shift,
+                    J_nom=o.J_nom, absJ_nom=o.absJ_nom, theta0=o.theta0, g0=o.g0, i0=o.i0, shift=o.shift,
                     n_amb=o.n_amb, allow=list(o.allow), front=list(o.front),
                     front_amb=list(o.front_amb))
 

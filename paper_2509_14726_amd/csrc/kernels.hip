@@ -2154,8 +2154,10 @@ template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
 // Eq. (4)-(5) for step k in one block of kFinalThreads threads:
 //   J_min = min over the tile minima,  w~_m = exp(-(J_m - J_min)/lambda)
 //   (0 for non-finite J_m),  S = sum_m w~_m,  U_k = sum_m w~_m U^m_k / S.
-// Thread t adds the samples t, t + kFinalThreads, ... in that order, the
-// waves are added by a fixed tree and the wave totals in wave order.  S and
+// Thread t adds the samples t, t + kFinalThreads, ... in that order.  The
+// thread sums go to LDS; lane l of wave i then adds value i of threads l,
+// l + 64, ..., l + kFinalThreads - 64 in that order and the lanes are added
+// by a fixed tree, one value per wave, all values at once.  S and
 // sum_m w~_m^2 come out of the same loop in every block, bit for bit, so no
 // block waits for another.  The block of step 0 also writes the first input,
 // the report, the nominal's pass mask for the next solve and the warm-start
@@ -2175,8 +2177,9 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     constexpr int NV = C + 2;
     constexpr int NT = kFinalThreads, NWV = NT / 64, UR = 4;
     typedef typename Vec4<Real>::T R4;
+    static_assert(NV <= NWV, "one wave per reduced value");
     __shared__ Real s_min[NWV];
-    __shared__ Acc s_red[NWV][NV];
+    __shared__ Acc s_part[NV][NT];
     __shared__ Acc s_tot[NV];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -2261,20 +2264,24 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
 #pragma unroll
     for (int i = 1; i < NWV; ++i) jmin = s_min[i] < jmin ? s_min[i] : jmin;
 
-    // weighted sums, UR samples per round in sample order
+    // weighted sums, UR samples per round in sample order; the next round's
+    // loads are issued before this round's arithmetic
     Acc v[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = Acc(0);
     for (int m0 = tid; m0 < K; m0 += NT * UR) {
-        if (m0 != tid) {
+        Real Jn[UR], vn[UR];
+        R4 un[UR];
+        const int m1 = m0 + NT * UR;
+        if (m1 < K) {
 #pragma unroll
             for (int i = 0; i < UR; ++i) {
-                const int m = m0 + NT * i;
+                const int m = m1 + NT * i;
                 if (m < K) {
-                    Jm[i] = J[m];
+                    Jn[i] = J[m];
                     if (!REGEN) {
-                        u[i] = ctrl[m];
-                        if (HAS_V) vm[i] = vctrl[m];
+                        un[i] = ctrl[m];
+                        if (HAS_V) vn[i] = vctrl[m];
                     }
                 }
             }
@@ -2294,18 +2301,26 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
                 v[C + 1] += wa * wa;
             }
         }
+        if (m1 < K) {
+#pragma unroll
+            for (int i = 0; i < UR; ++i) {
+                Jm[i] = Jn[i];
+                if (!REGEN) {
+                    u[i] = un[i];
+                    if (HAS_V) vm[i] = vn[i];
+                }
+            }
+        }
     }
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const Acc r = wave_sum(v[i]);
-        if (lane == 0) s_red[wv][i] = r;
-    }
+    for (int i = 0; i < NV; ++i) s_part[i][tid] = v[i];
     __syncthreads();
-    if (tid < NV) {
-        Acc t = s_red[0][tid];
+    if (wv < NV) {
+        Acc t = s_part[wv][lane];
 #pragma unroll
-        for (int i = 1; i < NWV; ++i) t += s_red[i][tid];
-        s_tot[tid] = t;
+        for (int j = 1; j < NWV; ++j) t += s_part[wv][64 * j + lane];
+        t = wave_sum(t);
+        if (lane == 0) s_tot[wv] = t;
     }
     __syncthreads();
     const Acc den = s_tot[C], den2 = s_tot[C + 1];

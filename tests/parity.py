@@ -179,7 +179,9 @@ def compare_result(orc: O.Problem, wd: M.mppi_warm, x0, t_now: float, precision:
     err_ess = abs(info["ess"] - ref["ess"]) / ref["ess"]
     assert err_ess <= tol, (info["ess"], ref["ess"])
     if np.isfinite(r["J_nom"]):
-        assert abs(info["J_nom"] - r["J_nom"]) <= tol * max(abs(r["J_nom"]), 1.0)
+        # the nominal's cost on the same scale as the samples' costs
+        assert abs(info["J_nom"] - r["J_nom"]) <= tol * max(abs(r["J_nom"]), r["absJ_nom"]), \
+            (info["J_nom"], r["J_nom"], r["absJ_nom"])
     if cfg.objective == O.OBJ_CONTOUR:
         assert abs(info["theta0"] - r["theta0"]) <= 1e-9 * max(cfg.path_len, 1.0)
     if wn is not None:
