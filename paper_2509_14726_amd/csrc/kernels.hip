@@ -130,9 +130,9 @@ struct HeadVals {
 // Run by all threads of one block (any size up to 256); h is in LDS.
 __device__ void compute_head(const KArgs &a, HeadVals &h)
 {
-    __shared__ double s_d2[256];
-    __shared__ double s_th[256];
-    __shared__ int s_j[256];
+    __shared__ double s_d2[512];   // one entry per thread, up to 512 threads
+    __shared__ double s_th[512];
+    __shared__ int s_j[512];
     const int tid = threadIdx.x;
     const DevWarm *w = a.warm;
     const int warm = w->warm;
@@ -168,7 +168,7 @@ __device__ void compute_head(const KArgs &a, HeadVals &h)
         s_d2[tid] = best; s_th[tid] = best_th; s_j[tid] = best_j;
         __syncthreads();
         // smallest distance, ties to the first candidate in search order
-        for (int st = 128; st > 0; st >>= 1) {
+        for (int st = 256; st > 0; st >>= 1) {
             if (tid < st && tid + st < (int)blockDim.x) {
                 const double d_o = s_d2[tid + st];
                 const int j_o = s_j[tid + st];
@@ -478,12 +478,12 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
             // ---- stage terms at state k
             Real ax = 0, ay = 0, az = 0;  // p_k - c_g (gate)
             if (OBJ == OBJ_GATE) {
-                ax = (st.x[0] - gt.cx) + lo_of(st, 0);
-                ay = (st.x[1] - gt.cy) + lo_of(st, 1);
-                az = (st.x[2] - gt.cz) + lo_of(st, 2);
-                const Real bx = (st.x[0] - g0r.cx) + lo_of(st, 0);
-                const Real by = (st.x[1] - g0r.cy) + lo_of(st, 1);
-                const Real bz = (st.x[2] - g0r.cz) + lo_of(st, 2);
+                ax = st.x[0] - gt.cx;
+                ay = st.x[1] - gt.cy;
+                az = st.x[2] - gt.cz;
+                const Real bx = st.x[0] - g0r.cx;
+                const Real by = st.x[1] - g0r.cy;
+                const Real bz = st.x[2] - g0r.cz;
                 const Real d2 = bx * bx + by * by + bz * bz;
                 if (d2 < r_near2) term += q_near * d2;  // Eq. (7), current gate
                 if (nominal) a.front8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
@@ -493,7 +493,7 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
                 const Real *xr = xref + 16 * r;
 #pragma unroll
                 for (int i = 0; i < 13; ++i) {
-                    const Real e = (st.x[i] - xr[i]) + lo_of(st, i);
+                    const Real e = st.x[i] - xr[i];
                     term += (Real)a.Q[i] * e * e;
                 }
                 const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
@@ -510,9 +510,9 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
                 Real tx = g1 * A[3] + f * B[3], ty = g1 * A[4] + f * B[4], tz = g1 * A[5] + f * B[5];
                 const Real tn = inv_sqrt(tx * tx + ty * ty + tz * tz);
                 tx *= tn; ty *= tn; tz *= tn;
-                const Real ex = (st.x[0] - px) + lo_of(st, 0);
-                const Real ey = (st.x[1] - py) + lo_of(st, 1);
-                const Real ez = (st.x[2] - pz) + lo_of(st, 2);
+                const Real ex = st.x[0] - px;
+                const Real ey = st.x[1] - py;
+                const Real ez = st.x[2] - pz;
                 const Real et = ex * tx + ey * ty + ez * tz;
                 const Real lx = et * tx, ly = et * ty, lz = et * tz;
                 const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
@@ -581,14 +581,14 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
             Real term = 0;
 #pragma unroll
             for (int i = 0; i < 13; ++i) {
-                const Real e = (st.x[i] - xr[i]) + lo_of(st, i);
+                const Real e = st.x[i] - xr[i];
                 term += (Real)a.QN[i] * e * e;
             }
             J.add(term);
         }
         if (OBJ == OBJ_GATE && nominal) {
-            const Real bx = (st.x[0] - g0r.cx) + lo_of(st, 0);
-            const Real by = (st.x[1] - g0r.cy) + lo_of(st, 1);
+            const Real bx = st.x[0] - g0r.cx;
+            const Real by = st.x[1] - g0r.cy;
             a.front8[N] = (bx * g0r.nx + by * g0r.ny) < Real(0);
         }
         Jfinal = J.value();
@@ -649,9 +649,9 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
 
     KSum<Real> J;
     // ---- wave 0: attitude and body rates (hi + lo parts in binary32)
-    Real q[4], ql[4], w[3], wl[3], up[4];
+    Real q[4], w[3], up[4];
     // ---- wave 1: position and velocity
-    Real p[3], pl[3], v[3], vl[3];
+    Real p[3], v[3];
     GateRegs<Real> gt, g0r;
     int g = 0, passes = 0;
     Real vp = 0, th_hi = 0, th_lo = 0, ds = 0, inv_ds = 0, L = 0;
@@ -662,15 +662,11 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
         const double *x0 = cur->x0;
         for (int i = 0; i < 4; ++i) {
             q[i] = (Real)x0[6 + i];
-            ql[i] = sizeof(Real) == 4 ? (Real)(x0[6 + i] - (double)q[i]) : Real(0);
         }
         for (int i = 0; i < 3; ++i) {
             w[i] = (Real)x0[10 + i];
-            wl[i] = sizeof(Real) == 4 ? (Real)(x0[10 + i] - (double)w[i]) : Real(0);
             p[i] = (Real)x0[i];
-            pl[i] = sizeof(Real) == 4 ? (Real)(x0[i] - (double)p[i]) : Real(0);
             v[i] = (Real)x0[3 + i];
-            vl[i] = sizeof(Real) == 4 ? (Real)(x0[3 + i] - (double)v[i]) : Real(0);
         }
         for (int i = 0; i < 4; ++i) up[i] = (Real)cur->u_prev[i];
     }
@@ -711,12 +707,12 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                     const Real *xr = xref + 16 * r;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const Real e = (q[i] - xr[6 + i]) + ql[i];
+                        const Real e = q[i] - xr[6 + i];
                         term += (Real)a.Q[6 + i] * e * e;
                     }
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (w[i] - xr[10 + i]) + wl[i];
+                        const Real e = w[i] - xr[10 + i];
                         term += (Real)a.Q[10 + i] * e * e;
                     }
                 }
@@ -773,41 +769,12 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                         for (int i = 0; i < 4; ++i) qs[i] = q[i] + hq * kq[i];
                     }
                 }
-                // commit the step (compensated in binary32), unit quaternion
-                if (sizeof(Real) == 4) {
+                // commit the step, unit quaternion
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const Real y = dw[i] + wl[i];
-                        const Real t = w[i] + y;
-                        wl[i] = y - (t - w[i]);
-                        w[i] = t;
-                    }
+                for (int i = 0; i < 3; ++i) w[i] += dw[i];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const Real y = dq[i] + ql[i];
-                        const Real t = q[i] + y;
-                        ql[i] = y - (t - q[i]);
-                        q[i] = t;
-                    }
-                    const Real n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-                    const Real r = inv_sqrt(n2);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const Real ph = q[i] * r;
-                        const Real pl2 = fma(q[i], r, -ph) + ql[i] * r;
-                        const Real hsum = ph + pl2;
-                        ql[i] = pl2 - (hsum - ph);
-                        q[i] = hsum;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) w[i] += dw[i];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) q[i] += dq[i];
-                    const Real nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) q[i] /= nq;
-                }
+                for (int i = 0; i < 4; ++i) q[i] += dq[i];
+                renormalize(q);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const Real e = fmax(fabs(w[i]) - w_max, Real(0));
@@ -829,12 +796,12 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                 Real term = Real(0);
                 Real ax = 0, ay = 0, az = 0;
                 if (OBJ == OBJ_GATE) {
-                    ax = (p[0] - gt.cx) + pl[0];
-                    ay = (p[1] - gt.cy) + pl[1];
-                    az = (p[2] - gt.cz) + pl[2];
-                    const Real bx = (p[0] - g0r.cx) + pl[0];
-                    const Real by = (p[1] - g0r.cy) + pl[1];
-                    const Real bz = (p[2] - g0r.cz) + pl[2];
+                    ax = p[0] - gt.cx;
+                    ay = p[1] - gt.cy;
+                    az = p[2] - gt.cz;
+                    const Real bx = p[0] - g0r.cx;
+                    const Real by = p[1] - g0r.cy;
+                    const Real bz = p[2] - g0r.cz;
                     const Real d2 = bx * bx + by * by + bz * bz;
                     if (d2 < r_near2) term += q_near * d2;
                     if (nominal) a.front8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
@@ -844,12 +811,12 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                     const Real *xr = xref + 16 * r;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (p[i] - xr[i]) + pl[i];
+                        const Real e = p[i] - xr[i];
                         term += (Real)a.Q[i] * e * e;
                     }
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (v[i] - xr[3 + i]) + vl[i];
+                        const Real e = v[i] - xr[3 + i];
                         term += (Real)a.Q[3 + i] * e * e;
                     }
                 } else {
@@ -863,9 +830,9 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                     Real tx = g1 * A[3] + f * Bp[3], ty = g1 * A[4] + f * Bp[4], tz = g1 * A[5] + f * Bp[5];
                     const Real tn = inv_sqrt(tx * tx + ty * ty + tz * tz);
                     tx *= tn; ty *= tn; tz *= tn;
-                    const Real ex = (p[0] - px) + pl[0];
-                    const Real ey = (p[1] - py) + pl[1];
-                    const Real ez = (p[2] - pz) + pl[2];
+                    const Real ex = p[0] - px;
+                    const Real ey = p[1] - py;
+                    const Real ez = p[2] - pz;
                     const Real et = ex * tx + ey * ty + ez * tz;
                     const Real lx = et * tx, ly = et * ty, lz = et * tz;
                     const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
@@ -926,19 +893,8 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
                 }
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    if (sizeof(Real) == 4) {
-                        Real y = dpv[i] + pl[i];
-                        Real t = p[i] + y;
-                        pl[i] = y - (t - p[i]);
-                        p[i] = t;
-                        y = dvv[i] + vl[i];
-                        t = v[i] + y;
-                        vl[i] = y - (t - v[i]);
-                        v[i] = t;
-                    } else {
-                        p[i] += dpv[i];
-                        v[i] += dvv[i];
-                    }
+                    p[i] += dpv[i];
+                    v[i] += dvv[i];
                 }
                 if (OBJ == OBJ_GATE) {
                     term += dpv[0] * (Real(2) * ax + dpv[0]) + dpv[1] * (Real(2) * ay + dpv[1]) +
@@ -974,20 +930,20 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
         if (wave == 0) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const Real e = (q[i] - xr[6 + i]) + ql[i];
+                const Real e = q[i] - xr[6 + i];
                 term += (Real)a.QN[6 + i] * e * e;
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const Real e = (w[i] - xr[10 + i]) + wl[i];
+                const Real e = w[i] - xr[10 + i];
                 term += (Real)a.QN[10 + i] * e * e;
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const Real e = (p[i] - xr[i]) + pl[i];
+                const Real e = p[i] - xr[i];
                 term += (Real)a.QN[i] * e * e;
-                const Real f = (v[i] - xr[3 + i]) + vl[i];
+                const Real f = v[i] - xr[3 + i];
                 term += (Real)a.QN[3 + i] * f * f;
             }
         }
@@ -1000,8 +956,8 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
         if (active) {
             Jfinal = J.value() + s_jr[lane];
             if (OBJ == OBJ_GATE && nominal) {
-                const Real bx = (p[0] - g0r.cx) + pl[0];
-                const Real by = (p[1] - g0r.cy) + pl[1];
+                const Real bx = p[0] - g0r.cx;
+                const Real by = p[1] - g0r.cy;
                 a.front8[N] = (bx * g0r.nx + by * g0r.ny) < Real(0);
             }
             if (nominal) a.cur->J_nom = (double)Jfinal;
@@ -1071,18 +1027,14 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
     Real up[4], vp = (Real)h.v_prev;
     for (int i = 0; i < 4; ++i) up[i] = (Real)h.u_prev[i];
     // wave 1: attitude and body rates; wave 2: position and velocity
-    Real q[4], ql[4], w[3], wl[3], p[3], pl[3], v[3], vl[3];
+    Real q[4], w[3], p[3], v[3];
     for (int i = 0; i < 4; ++i) {
         q[i] = (Real)h.x0[6 + i];
-        ql[i] = sizeof(Real) == 4 ? (Real)(h.x0[6 + i] - (double)q[i]) : Real(0);
     }
     for (int i = 0; i < 3; ++i) {
         w[i] = (Real)h.x0[10 + i];
-        wl[i] = sizeof(Real) == 4 ? (Real)(h.x0[10 + i] - (double)w[i]) : Real(0);
         p[i] = (Real)h.x0[i];
-        pl[i] = sizeof(Real) == 4 ? (Real)(h.x0[i] - (double)p[i]) : Real(0);
         v[i] = (Real)h.x0[3 + i];
-        vl[i] = sizeof(Real) == 4 ? (Real)(h.x0[3 + i] - (double)v[i]) : Real(0);
     }
     GateRegs<Real> gt, g0r;
     int g = 0, passes = 0;
@@ -1200,12 +1152,12 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     const Real *xr = xref + 16 * r;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const Real e = (q[i] - xr[6 + i]) + ql[i];
+                        const Real e = q[i] - xr[6 + i];
                         term += (Real)a.Q[6 + i] * e * e;
                     }
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (w[i] - xr[10 + i]) + wl[i];
+                        const Real e = w[i] - xr[10 + i];
                         term += (Real)a.Q[10 + i] * e * e;
                     }
                 }
@@ -1256,40 +1208,11 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                         for (int i = 0; i < 4; ++i) qs[i] = q[i] + hq * kq[i];
                     }
                 }
-                if (sizeof(Real) == 4) {
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const Real y = dw[i] + wl[i];
-                        const Real t = w[i] + y;
-                        wl[i] = y - (t - w[i]);
-                        w[i] = t;
-                    }
+                for (int i = 0; i < 3; ++i) w[i] += dw[i];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const Real y = dq[i] + ql[i];
-                        const Real t = q[i] + y;
-                        ql[i] = y - (t - q[i]);
-                        q[i] = t;
-                    }
-                    const Real n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-                    const Real r = inv_sqrt(n2);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const Real ph = q[i] * r;
-                        const Real pl2 = fma(q[i], r, -ph) + ql[i] * r;
-                        const Real hs = ph + pl2;
-                        ql[i] = pl2 - (hs - ph);
-                        q[i] = hs;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) w[i] += dw[i];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) q[i] += dq[i];
-                    const Real nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) q[i] /= nq;
-                }
+                for (int i = 0; i < 4; ++i) q[i] += dq[i];
+                renormalize(q);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const Real e = fmax(fabs(w[i]) - w_max, Real(0));
@@ -1314,12 +1237,12 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                 Real term = Real(0);
                 Real ax = 0, ay = 0, az = 0;
                 if (OBJ == OBJ_GATE) {
-                    ax = (p[0] - gt.cx) + pl[0];
-                    ay = (p[1] - gt.cy) + pl[1];
-                    az = (p[2] - gt.cz) + pl[2];
-                    const Real bx = (p[0] - g0r.cx) + pl[0];
-                    const Real by = (p[1] - g0r.cy) + pl[1];
-                    const Real bz = (p[2] - g0r.cz) + pl[2];
+                    ax = p[0] - gt.cx;
+                    ay = p[1] - gt.cy;
+                    az = p[2] - gt.cz;
+                    const Real bx = p[0] - g0r.cx;
+                    const Real by = p[1] - g0r.cy;
+                    const Real bz = p[2] - g0r.cz;
                     const Real d2 = bx * bx + by * by + bz * bz;
                     if (d2 < r_near2) term += q_near * d2;
                     if (nominal) s_f8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
@@ -1329,12 +1252,12 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     const Real *xr = xref + 16 * r;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (p[i] - xr[i]) + pl[i];
+                        const Real e = p[i] - xr[i];
                         term += (Real)a.Q[i] * e * e;
                     }
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (v[i] - xr[3 + i]) + vl[i];
+                        const Real e = v[i] - xr[3 + i];
                         term += (Real)a.Q[3 + i] * e * e;
                     }
                 } else {
@@ -1349,9 +1272,9 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                     Real tx = g1 * A[3] + f * Bp[3], ty = g1 * A[4] + f * Bp[4], tz = g1 * A[5] + f * Bp[5];
                     const Real tn = inv_sqrt(tx * tx + ty * ty + tz * tz);
                     tx *= tn; ty *= tn; tz *= tn;
-                    const Real ex = (p[0] - px) + pl[0];
-                    const Real ey = (p[1] - py) + pl[1];
-                    const Real ez = (p[2] - pz) + pl[2];
+                    const Real ex = p[0] - px;
+                    const Real ey = p[1] - py;
+                    const Real ez = p[2] - pz;
                     const Real et = ex * tx + ey * ty + ez * tz;
                     const Real lx = et * tx, ly = et * ty, lz = et * tz;
                     const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
@@ -1405,19 +1328,8 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
                 }
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    if (sizeof(Real) == 4) {
-                        Real y = dpv[i] + pl[i];
-                        Real t = p[i] + y;
-                        pl[i] = y - (t - p[i]);
-                        p[i] = t;
-                        y = dvv[i] + vl[i];
-                        t = v[i] + y;
-                        vl[i] = y - (t - v[i]);
-                        v[i] = t;
-                    } else {
-                        p[i] += dpv[i];
-                        v[i] += dvv[i];
-                    }
+                    p[i] += dpv[i];
+                    v[i] += dvv[i];
                 }
                 if (OBJ == OBJ_GATE) {
                     term += dpv[0] * (Real(2) * ax + dpv[0]) + dpv[1] * (Real(2) * ay + dpv[1]) +
@@ -1458,20 +1370,20 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
         if (wave == 1) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const Real e = (q[i] - xr[6 + i]) + ql[i];
+                const Real e = q[i] - xr[6 + i];
                 term += (Real)a.QN[6 + i] * e * e;
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const Real e = (w[i] - xr[10 + i]) + wl[i];
+                const Real e = w[i] - xr[10 + i];
                 term += (Real)a.QN[10 + i] * e * e;
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const Real e = (p[i] - xr[i]) + pl[i];
+                const Real e = p[i] - xr[i];
                 term += (Real)a.QN[i] * e * e;
-                const Real f = (v[i] - xr[3 + i]) + vl[i];
+                const Real f = v[i] - xr[3 + i];
                 term += (Real)a.QN[3 + i] * f * f;
             }
         }
@@ -1484,8 +1396,8 @@ __device__ __forceinline__ void rollout3_body(const KArgs &a, int blk, const Hea
         if (active) {
             Jfinal = (s_jp[0][lane] + s_jp[1][lane]) + J.value();
             if (OBJ == OBJ_GATE && nominal) {
-                const Real bx = (p[0] - g0r.cx) + pl[0];
-                const Real by = (p[1] - g0r.cy) + pl[1];
+                const Real bx = p[0] - g0r.cx;
+                const Real by = p[1] - g0r.cy;
                 a.front8[N] = (bx * g0r.nx + by * g0r.ny) < Real(0);
             }
             if (nominal) a.cur->J_nom = (double)Jfinal;
@@ -1529,13 +1441,13 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
     __shared__ R4 s_in[4][B][64];                  // (F/m, tau_x/J_x, tau_y/J_y, tau_z/J_z), chunk c at c % 4
     __shared__ R4 s_w[2][B][4][64];                // stage body rates, chunk c at c % 2
     __shared__ R4 s_q[2][B][4][64];                // stage quaternions, chunk c at c % 2
-    __shared__ R4 s_p[POS ? 2 : 1][B][3][64];      // p_k hi, p_k lo, increment; chunk c at c % 2
+    __shared__ R4 s_p[POS ? 2 : 1][B][2][64];      // p_k and its increment; chunk c at c % 2
     __shared__ R4 s_u[RATE ? 5 : 1][B][64];        // clipped inputs, chunk c at c % 5
     __shared__ Real s_v[HAS_V ? 5 : 1][B][64];     // progress speed, chunk c at c % 5
     __shared__ R4 s_us[kNMax];                     // shifted warm-start thrusts per step
     __shared__ Real s_vs[HAS_V ? kNMax : 1];       // shifted warm-start progress speed
     __shared__ Real s_jp[3][64];                   // partial costs of waves 0, 1, 2
-    __shared__ R4 s_pN[2][64];                     // p_N hi and lo (front flag of the nominal)
+    __shared__ R4 s_pN[64];                        // p_N (front flag of the nominal)
     __shared__ Real s_gtab[OBJ == OBJ_GATE ? 8 * kGMax : 1];   // the gate table, staged once
     __shared__ uint8_t s_f8[OBJ == OBJ_GATE ? kNMax : 1];      // front flags of the nominal, steps 0..N-1
 
@@ -1561,18 +1473,14 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
     KSum<Real> J;
     Real up[4], vp = (Real)h.v_prev;
     for (int i = 0; i < 4; ++i) up[i] = (Real)h.u_prev[i];
-    Real q[4], ql[4], w[3], wl[3], p[3], pl[3], v[3], vl[3];
+    Real q[4], w[3], p[3], v[3];
     for (int i = 0; i < 4; ++i) {
         q[i] = (Real)h.x0[6 + i];
-        ql[i] = sizeof(Real) == 4 ? (Real)(h.x0[6 + i] - (double)q[i]) : Real(0);
     }
     for (int i = 0; i < 3; ++i) {
         w[i] = (Real)h.x0[10 + i];
-        wl[i] = sizeof(Real) == 4 ? (Real)(h.x0[10 + i] - (double)w[i]) : Real(0);
         p[i] = (Real)h.x0[i];
-        pl[i] = sizeof(Real) == 4 ? (Real)(h.x0[i] - (double)p[i]) : Real(0);
         v[i] = (Real)h.x0[3 + i];
-        vl[i] = sizeof(Real) == 4 ? (Real)(h.x0[3 + i] - (double)v[i]) : Real(0);
     }
     GateRegs<Real> gt, g0r;
     int g = 0, passes = 0;
@@ -1624,10 +1532,21 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
 
     const int nch = (N + B - 1) / B;
     for (int c = 0; c <= nch + 3; ++c) {
-        if ((wave == 0 || wave == 3) && c < nch) {
+        // The draws.  With eight waves (one workgroup per CU), waves 4-7 draw
+        // one step of each chunk each and share the SIMDs with the four
+        // integration waves: the Philox products and the Box-Muller
+        // transcendentals run at a quarter of the vector rate and fill issue
+        // slots the latency-bound integration leaves free.  With four waves,
+        // waves 0 and 3 draw every second step.
+        const bool eight = blockDim.x == 8 * 64;
+        constexpr int ND8 = B >= 4 ? 4 : 2;
+        const int ND = eight ? ND8 : 2;
+        const int dslot = eight ? (wave >= 4 && wave - 4 < ND8 ? wave - 4 : -1)
+                                : (wave == 3 ? 1 : (wave == 0 ? 0 : -1));
+        if (dslot >= 0 && c < nch) {
             // noise, clipped inputs and the per-step thrust and torques
             const int kb = c * B, ke = min(N, kb + B);
-            const int k_first = wave == 3 ? 1 : 0;
+            const int k_first = dslot;
             // a step's draw: the clipped inputs (u, V) of sample m at step k;
             // every lane draws (no branch around the arithmetic, so the steps
             // of a chunk interleave), the noise-free nominal and the idle
@@ -1664,8 +1583,8 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                 o.x = in.fm; o.y = in.tx; o.z = in.ty; o.w = in.tz;
                 s_in[c % 4][j][lane] = o;
             };
-            if (ke - kb == B) {
-                static_assert(B % 2 == 0, "each sampling wave takes B / 2 steps of a chunk");
+            if (ke - kb == B && !eight) {
+                static_assert(B % 2 == 0, "each of two drawing waves takes B / 2 steps of a chunk");
                 constexpr int NS = B / 2;
                 R4 uu[NS];
                 Real vv[NS];
@@ -1673,8 +1592,16 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                 for (int i = 0; i < NS; ++i) draw(kb + k_first + 2 * i, uu[i], vv[i]);
 #pragma unroll
                 for (int i = 0; i < NS; ++i) put(kb + k_first + 2 * i, k_first + 2 * i, uu[i], vv[i]);
+            } else if (ke - kb == B) {
+                constexpr int NS = B / ND8;
+                R4 uu[NS];
+                Real vv[NS];
+#pragma unroll
+                for (int i = 0; i < NS; ++i) draw(kb + k_first + ND8 * i, uu[i], vv[i]);
+#pragma unroll
+                for (int i = 0; i < NS; ++i) put(kb + k_first + ND8 * i, k_first + ND8 * i, uu[i], vv[i]);
             } else {
-                for (int k = kb + k_first; k < ke; k += 2) {
+                for (int k = kb + k_first; k < ke; k += ND) {
                     R4 u1;
                     Real v1;
                     draw(k, u1, v1);
@@ -1694,7 +1621,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                     const Real *xr = xref + 16 * r;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (w[i] - xr[10 + i]) + wl[i];
+                        const Real e = w[i] - xr[10 + i];
                         term += (Real)a.Q[10 + i] * e * e;
                     }
                 }
@@ -1727,18 +1654,8 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                         for (int i = 0; i < 3; ++i) ws[i] = w[i] + hh * kw[i];
                     }
                 }
-                if (sizeof(Real) == 4) {
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const Real y = dw[i] + wl[i];
-                        const Real t = w[i] + y;
-                        wl[i] = y - (t - w[i]);
-                        w[i] = t;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) w[i] += dw[i];
-                }
+                for (int i = 0; i < 3; ++i) w[i] += dw[i];
                 // the body rates after the step ride in the free fourth
                 // component of stages 1-3: the attitude wave adds their
                 // rate-limit term
@@ -1772,7 +1689,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                     Real term = Real(0);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const Real e = (q[i] - xr[6 + i]) + ql[i];
+                        const Real e = q[i] - xr[6 + i];
                         term += (Real)a.Q[6 + i] * e * e;
                     }
                     J.add(term);
@@ -1808,31 +1725,9 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                         for (int i = 0; i < 4; ++i) qs[i] = q[i] + hq * kq[i];
                     }
                 }
-                if (sizeof(Real) == 4) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const Real y = dq[i] + ql[i];
-                        const Real t = q[i] + y;
-                        ql[i] = y - (t - q[i]);
-                        q[i] = t;
-                    }
-                    const Real n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-                    const Real r = inv_sqrt(n2);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const Real ph = q[i] * r;
-                        const Real pl2 = fma(q[i], r, -ph) + ql[i] * r;
-                        const Real hs = ph + pl2;
-                        ql[i] = pl2 - (hs - ph);
-                        q[i] = hs;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) q[i] += dq[i];
-                    const Real nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) q[i] /= nq;
-                }
+                for (int i = 0; i < 4; ++i) q[i] += dq[i];
+                renormalize(q);
                 // rate limit on the body rates after the step
                 Real term = Real(0);
 #pragma unroll
@@ -1869,12 +1764,12 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                     Real term = Real(0);
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (p[i] - xr[i]) + pl[i];
+                        const Real e = p[i] - xr[i];
                         term += (Real)a.Q[i] * e * e;
                     }
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const Real e = (v[i] - xr[3 + i]) + vl[i];
+                        const Real e = v[i] - xr[3 + i];
                         term += (Real)a.Q[3 + i] * e * e;
                     }
                     J.add(term);
@@ -1927,26 +1822,13 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                     R4 o;
                     o.x = p[0]; o.y = p[1]; o.z = p[2]; o.w = Real(0);
                     ps[0][lane] = o;
-                    o.x = pl[0]; o.y = pl[1]; o.z = pl[2];
-                    ps[1][lane] = o;
                     o.x = dpv[0]; o.y = dpv[1]; o.z = dpv[2];
-                    ps[2][lane] = o;
+                    ps[1][lane] = o;
                 }
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    if (sizeof(Real) == 4) {
-                        Real y = dpv[i] + pl[i];
-                        Real t = p[i] + y;
-                        pl[i] = y - (t - p[i]);
-                        p[i] = t;
-                        y = dvv[i] + vl[i];
-                        t = v[i] + y;
-                        vl[i] = y - (t - v[i]);
-                        v[i] = t;
-                    } else {
-                        p[i] += dpv[i];
-                        v[i] += dvv[i];
-                    }
+                    p[i] += dpv[i];
+                    v[i] += dvv[i];
                 }
             };
             if (ke - kb == B) {
@@ -1971,9 +1853,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
             if (POS && c == nch + 2) {
                 R4 o;
                 o.x = p[0]; o.y = p[1]; o.z = p[2]; o.w = Real(0);
-                s_pN[0][lane] = o;
-                o.x = pl[0]; o.y = pl[1]; o.z = pl[2];
-                s_pN[1][lane] = o;
+                s_pN[lane] = o;
             }
         }
         if (wave == 3 && c >= 4) {
@@ -1995,17 +1875,17 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                     vp = V;
                 }
                 if (POS) {
-                    const R4 ph = pr[0], plo = pr[1];
-                    const Real pk[3] = {ph.x, ph.y, ph.z}, pkl[3] = {plo.x, plo.y, plo.z};
+                    const R4 ph = pr[0];
+                    const Real pk[3] = {ph.x, ph.y, ph.z};
                     if (OBJ == OBJ_GATE) {
-                        const R4 dp4 = pr[2];
+                        const R4 dp4 = pr[1];
                         const Real dpv[3] = {dp4.x, dp4.y, dp4.z};
-                        const Real ax = (pk[0] - gt.cx) + pkl[0];
-                        const Real ay = (pk[1] - gt.cy) + pkl[1];
-                        const Real az = (pk[2] - gt.cz) + pkl[2];
-                        const Real bx = (pk[0] - g0r.cx) + pkl[0];
-                        const Real by = (pk[1] - g0r.cy) + pkl[1];
-                        const Real bz = (pk[2] - g0r.cz) + pkl[2];
+                        const Real ax = pk[0] - gt.cx;
+                        const Real ay = pk[1] - gt.cy;
+                        const Real az = pk[2] - gt.cz;
+                        const Real bx = pk[0] - g0r.cx;
+                        const Real by = pk[1] - g0r.cy;
+                        const Real bz = pk[2] - g0r.cz;
                         const Real d2 = bx * bx + by * by + bz * bz;
                         if (d2 < r_near2) term += q_near * d2;
                         if (nominal) s_f8[k] = (bx * g0r.nx + by * g0r.ny) < Real(0);
@@ -2037,9 +1917,9 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                         Real tx = g1 * A[3] + f * Bp[3], ty = g1 * A[4] + f * Bp[4], tz = g1 * A[5] + f * Bp[5];
                         const Real tn = inv_sqrt(tx * tx + ty * ty + tz * tz);
                         tx *= tn; ty *= tn; tz *= tn;
-                        const Real ex = (pk[0] - px) + pkl[0];
-                        const Real ey = (pk[1] - py) + pkl[1];
-                        const Real ez = (pk[2] - pz) + pkl[2];
+                        const Real ex = pk[0] - px;
+                        const Real ey = pk[1] - py;
+                        const Real ez = pk[2] - pz;
                         const Real et = ex * tx + ey * ty + ez * tz;
                         const Real lx = et * tx, ly = et * ty, lz = et * tz;
                         const Real cxe = ex - lx, cye = ey - ly, cze = ez - lz;
@@ -2056,18 +1936,18 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                 J.add(term);
             };
             if (ke - kb == B) {
-                R4 ppre[B][3];
+                R4 ppre[B][2];
 #pragma unroll
                 for (int j = 0; j < B; ++j)
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) ppre[j][i] = POS ? s_p[(c - 4) & 1][j][i][lane] : R4{};
+                    for (int i = 0; i < 2; ++i) ppre[j][i] = POS ? s_p[(c - 4) & 1][j][i][lane] : R4{};
 #pragma unroll
                 for (int j = 0; j < B; ++j) cost_step(kb + j, j, ppre[j]);
             } else {
                 for (int k = kb; k < ke; ++k) {
-                    R4 pr[3];
+                    R4 pr[2];
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) pr[i] = POS ? s_p[(c - 4) & 1][k - kb][i][lane] : R4{};
+                    for (int i = 0; i < 2; ++i) pr[i] = POS ? s_p[(c - 4) & 1][k - kb][i][lane] : R4{};
                     cost_step(k, k - kb, pr);
                 }
             }
@@ -2084,21 +1964,21 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
         if (wave == 0) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const Real e = (w[i] - xr[10 + i]) + wl[i];
+                const Real e = w[i] - xr[10 + i];
                 term += (Real)a.QN[10 + i] * e * e;
             }
         } else if (wave == 1) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const Real e = (q[i] - xr[6 + i]) + ql[i];
+                const Real e = q[i] - xr[6 + i];
                 term += (Real)a.QN[6 + i] * e * e;
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const Real e = (p[i] - xr[i]) + pl[i];
+                const Real e = p[i] - xr[i];
                 term += (Real)a.QN[i] * e * e;
-                const Real f = (v[i] - xr[3 + i]) + vl[i];
+                const Real f = v[i] - xr[3 + i];
                 term += (Real)a.QN[3 + i] * f * f;
             }
         }
@@ -2111,9 +1991,9 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
         if (active) {
             Jfinal = ((s_jp[0][lane] + s_jp[1][lane]) + s_jp[2][lane]) + J.value();
             if (OBJ == OBJ_GATE && nominal) {
-                const R4 ph = s_pN[0][lane], plo = s_pN[1][lane];
-                const Real bx = (ph.x - g0r.cx) + plo.x;
-                const Real by = (ph.y - g0r.cy) + plo.y;
+                const R4 ph = s_pN[lane];
+                const Real bx = ph.x - g0r.cx;
+                const Real by = ph.y - g0r.cy;
                 a.front8[N] = (bx * g0r.nx + by * g0r.ny) < Real(0);
             }
             if (nominal) a.cur->J_nom = (double)Jfinal;
@@ -2127,7 +2007,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
     __syncthreads();
 }
 
-template <int OBJ, typename Real, int B> __global__ __launch_bounds__(256) void k_rollout4(KArgs a)
+template <int OBJ, typename Real, int B> __global__ __launch_bounds__(512) void k_rollout4(KArgs a)
 {
     __shared__ HeadVals h;
     compute_head(a, h);
@@ -2620,7 +2500,7 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     if (a.rollout_waves == 4) {
         if constexpr (sizeof(Real) == 4) {
             if (a.ring4_b == 4)
-                hipLaunchKernelGGL((k_rollout4<OBJ, Real, 4>), gt, dim3(256), 0, st, a);
+                hipLaunchKernelGGL((k_rollout4<OBJ, Real, 4>), gt, dim3(512), 0, st, a);
             else
                 hipLaunchKernelGGL((k_rollout4<OBJ, Real, 2>), gt, dim3(256), 0, st, a);
         } else {

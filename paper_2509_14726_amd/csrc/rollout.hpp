@@ -1,12 +1,10 @@
 // Quadrotor dynamics (Sec. III-A, Eq. (2)) and one RK4 step in registers.
 //
 // State x = [p, v, q = (w, x, y, z), omega]; input = four rotor thrusts held
-// over the step.  In binary32 every state component is carried as an
-// unevaluated sum hi + lo: the stage evaluations use hi, the step increment
-// is added with a compensated (Fast2Sum) update and the quaternion is scaled
-// back to unit norm with an exact product, so the rounding of 100-step
-// rollouts stays near that of a single step.  In binary64 the lo parts are
-// compiled out.
+// over the step.  The quaternion is scaled back to unit norm after every
+// step.  Binary32 rollouts carry the state in plain binary32: over horizons
+// of up to 256 steps their cost errors stay near 1e-6 of the cost scale (the
+// magnitudes of the terms), and the cost sums themselves are compensated.
 #pragma once
 
 #include "device.hpp"
@@ -83,63 +81,37 @@ __device__ __forceinline__ void deriv(const Model<Real> &M, const StepInput<Real
     d[12] = in.tz - M.gz * wx * wy;
 }
 
-// State with optional low-order parts.
+// Scale a quaternion back to unit norm: the hardware reciprocal square root
+// in binary32, the correctly rounded square root and division in binary64.
+__device__ __forceinline__ void renormalize(float *q)
+{
+    const float r = inv_sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] *= r;
+}
+__device__ __forceinline__ void renormalize(double *q)
+{
+    const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] /= nq;
+}
+
 template <typename Real> struct State {
     Real x[13];
-    Real lo[13];
 };
-template <> struct State<double> {
-    double x[13];
-};
-
-template <typename Real> __device__ __forceinline__ Real lo_of(const State<Real> &s, int i)
-{
-    return s.lo[i];
-}
-template <> __device__ __forceinline__ double lo_of(const State<double> &, int) { return 0.0; }
 
 template <typename Real> __device__ __forceinline__ void load_state(State<Real> &s, const double *x0)
 {
 #pragma unroll
-    for (int i = 0; i < 13; ++i) {
-        s.x[i] = (float)x0[i];
-        s.lo[i] = (float)(x0[i] - (double)s.x[i]);
-    }
-}
-template <> __device__ __forceinline__ void load_state(State<double> &s, const double *x0)
-{
-#pragma unroll
-    for (int i = 0; i < 13; ++i) s.x[i] = x0[i];
+    for (int i = 0; i < 13; ++i) s.x[i] = (Real)x0[i];
 }
 
 // Add the increment of one step, then renormalise the quaternion.
 template <typename Real> __device__ __forceinline__ void commit(State<Real> &s, const Real *dx)
 {
 #pragma unroll
-    for (int i = 0; i < 13; ++i) {
-        const Real y = dx[i] + s.lo[i];
-        const Real t = s.x[i] + y;
-        s.lo[i] = y - (t - s.x[i]);
-        s.x[i] = t;
-    }
-    const Real n2 = s.x[6] * s.x[6] + s.x[7] * s.x[7] + s.x[8] * s.x[8] + s.x[9] * s.x[9];
-    const Real r = inv_sqrt(n2);
-#pragma unroll
-    for (int i = 6; i < 10; ++i) {
-        const Real ph = s.x[i] * r;
-        const Real pl = fmaf(s.x[i], r, -ph) + s.lo[i] * r;
-        const Real h = ph + pl;
-        s.lo[i] = pl - (h - ph);
-        s.x[i] = h;
-    }
-}
-template <> __device__ __forceinline__ void commit(State<double> &s, const double *dx)
-{
-#pragma unroll
     for (int i = 0; i < 13; ++i) s.x[i] += dx[i];
-    const double nq = sqrt(s.x[6] * s.x[6] + s.x[7] * s.x[7] + s.x[8] * s.x[8] + s.x[9] * s.x[9]);
-#pragma unroll
-    for (int i = 6; i < 10; ++i) s.x[i] /= nq;
+    renormalize(s.x + 6);
 }
 
 // dx = dt/6 (k1 + 2 k2 + 2 k3 + k4) for the input held over the step.
