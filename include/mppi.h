@@ -70,7 +70,7 @@ typedef struct {
     int32_t K;            /* samples, 1..MPPI_K_MAX                            */
     int32_t N;            /* horizon steps, 1..MPPI_N_MAX                      */
     int32_t objective;    /* MPPI_OBJ_*                                        */
-    int32_t precision;    /* MPPI_FP32 (compensated) or MPPI_FP64              */
+    int32_t precision;    /* MPPI_FP32 (Kahan cost sums) or MPPI_FP64          */
     double dt;            /* integration and prediction step, s, > 0          */
     double lambda;        /* softmax temperature, > 0                          */
     double sigma[4];      /* per-rotor noise standard deviation, N, >= 0       */

@@ -648,7 +648,7 @@ template <int OBJ, typename Real> __device__ __forceinline__ void rollout2_body(
     for (int i = 0; i < 4; ++i) rdt[i] = (Real)(a.R_dT[i] / (a.dt * a.dt));
 
     KSum<Real> J;
-    // ---- wave 0: attitude and body rates (hi + lo parts in binary32)
+    // ---- wave 0: attitude and body rates
     Real q[4], w[3], up[4];
     // ---- wave 1: position and velocity
     Real p[3], v[3];
