@@ -2032,7 +2032,7 @@ template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
 }
 
 // Eq. (4)-(5) for step k in one block of kFinalThreads threads:
-//   J_min = min over the tile minima,  w~_m = exp(-(J_m - J_min)/lambda)
+//   J_min = min over the tile minima (each wave reduces them all),  w~_m = exp(-(J_m - J_min)/lambda)
 //   (0 for non-finite J_m),  S = sum_m w~_m,  U_k = sum_m w~_m U^m_k / S.
 // Thread t adds the samples t, t + kFinalThreads, ... in that order.  The
 // thread sums go to LDS; lane l of wave i then adds value i of threads l,
@@ -2058,7 +2058,6 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     constexpr int NT = kFinalThreads, NWV = NT / 64, UR = 4;
     typedef typename Vec4<Real>::T R4;
     static_assert(NV <= NWV, "one wave per reduced value");
-    __shared__ Real s_min[NWV];
     __shared__ Acc s_part[NV][NT];
     __shared__ Acc s_tot[NV];
 
@@ -2096,9 +2095,10 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
         }
     };
 
-    // loads: tile minima, the first UR samples of this thread
+    // loads: tile minima (every wave reads all of them), the first UR samples
+    // of this thread
     Real mn = Real(INFINITY);
-    for (int t = tid; t < a.n_tiles; t += NT) {
+    for (int t = lane; t < a.n_tiles; t += 64) {
         const Real v = ((const Real *)a.tmin)[t];
         mn = v < mn ? v : mn;
     }
@@ -2133,16 +2133,13 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
         rep_s = cur->s;
     }
     if (head && tid >= 7 && tid < 20) rep_x = cur->x0[tid - 7];
-    // J_min
+    // J_min within each wave (a minimum does not depend on the grouping, so
+    // every wave of every block finds the same value without a block barrier)
     for (int off = 32; off > 0; off >>= 1) {
         const Real o = __shfl_xor(mn, off, 64);
         mn = o < mn ? o : mn;
     }
-    if (lane == 0) s_min[wv] = mn;
-    __syncthreads();
-    Real jmin = s_min[0];
-#pragma unroll
-    for (int i = 1; i < NWV; ++i) jmin = s_min[i] < jmin ? s_min[i] : jmin;
+    const Real jmin = mn;
 
     // weighted sums, UR samples per round in sample order; the next round's
     // loads are issued before this round's arithmetic
