@@ -470,6 +470,7 @@ static int cfg_valid(const orc_quad *q, const orc_cfg *c)
     if (c->K < 1 || c->N < 1 || c->N > ORC_NMAX) return 0;
     if (!(c->dt > 0.0) || !(c->lambda > 0.0)) return 0;
     for (int i = 0; i < 4; ++i) if (!(c->sigma[i] >= 0.0)) return 0;
+    if (c->n_iter < 0 || c->n_iter > 64 || !(c->ctrl_cost >= 0.0) || !isfinite(c->ctrl_cost)) return 0;
     if (!(q->mass > 0.0) || !(q->t_max >= q->t_min)) return 0;
     for (int i = 0; i < 3; ++i) if (!(q->inertia[i] > 0.0)) return 0;
     if (c->objective == ORC_OBJ_GATE) {
@@ -484,12 +485,44 @@ static int cfg_valid(const orc_quad *q, const orc_cfg *c)
     return 1;
 }
 
-int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double x0[13],
-              double t_now, const double *J_rep, const uint8_t *rep_mask, orc_out *out)
+/* The control-cost term of information-theoretic MPPI (Williams et al., the
+ * MPPI line of work the paper builds on, Sec. II-A): gamma times
+ * sum_k sum_i U*_k,i (U^m_k,i - U*_k,i) / sigma_i^2 over the channels with
+ * sigma_i > 0 (the four thrusts, then the contouring speed), summed in step
+ * order with the channels inside.  The perturbation is the one applied, after
+ * clipping.  abs_sum receives the sum of the magnitudes of the products. */
+static double control_cost(const orc_cfg *c, const double *Ustar, const double *Vstar, const double *U,
+                           const double *V, double *abs_sum)
 {
-    if (!cfg_valid(q, c) || !warm || !x0 || !out || !out->J || !isfinite(t_now)) return ORC_EINVAL;
-    if ((J_rep == NULL) != (rep_mask == NULL)) return ORC_EINVAL;
-    for (int i = 0; i < 13; ++i) if (!isfinite(x0[i])) return ORC_EINVAL;
+    double C = 0.0, A = 0.0;
+    for (int k = 0; k < c->N; ++k) {
+        for (int i = 0; i < 4; ++i) {
+            if (!(c->sigma[i] > 0.0)) continue;
+            const double t = c->ctrl_cost * Ustar[4 * k + i] * (U[4 * k + i] - Ustar[4 * k + i]) /
+                             (c->sigma[i] * c->sigma[i]);
+            C += t;
+            A += fabs(t);
+        }
+        if (c->objective == ORC_OBJ_CONTOUR && c->sigma_v > 0.0) {
+            const double t = c->ctrl_cost * Vstar[k] * (V[k] - Vstar[k]) / (c->sigma_v * c->sigma_v);
+            C += t;
+            A += fabs(t);
+        }
+    }
+    *abs_sum = A;
+    return C;
+}
+
+/* One MPPI iteration from the inherited state (Sec. III-B, Alg. 1).  An inner
+ * iteration (the second and later of one control step, same x0 and t_now)
+ * samples around the previous iteration's solution without shifting it and
+ * keeps the last applied input (u_keep, v_keep) of the first iteration for
+ * the rate terms; *u_used / *v_used return the ones this iteration used. */
+static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double x0[13],
+                           double t_now, const double *J_rep, const uint8_t *rep_mask, orc_out *out,
+                           int inner, const double u_keep[4], double v_keep, double u_used[4],
+                           double *v_used)
+{
     const int K = c->K, N = c->N;
     const double hover = q->mass * q->gravity / 4.0;
 
@@ -498,6 +531,7 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
     uint32_t allow[ORC_MASK_WORDS];
     int32_t g0 = warm->g0, shift = 0;
     double theta0 = 0.0;
+    const int same_step = inner && warm->warm && warm->t_prev == t_now;
     if (warm->warm) {
         /* shift the previous solution by the elapsed steps, repeat its tail */
         double el = (t_now - warm->t_prev) / c->dt;
@@ -505,13 +539,14 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
         if (el < 0.0) el = 0.0;
         shift = (int32_t)floor(el + 0.5);
         if (shift < 1) shift = 1;
+        if (same_step) shift = 0;
         for (int k = 0; k < N; ++k) {
             int src = k + shift < N ? k + shift : N - 1;
             for (int i = 0; i < 4; ++i) Ustar[4 * k + i] = warm->U[4 * src + i];
             Vstar[k] = warm->V[src];
         }
-        for (int i = 0; i < 4; ++i) u_prev[i] = warm->U[i];
-        v_prev = warm->V[0];
+        for (int i = 0; i < 4; ++i) u_prev[i] = same_step ? u_keep[i] : warm->U[i];
+        v_prev = same_step ? v_keep : warm->V[0];
         memcpy(allow, warm->allow, sizeof allow);
         /* the measured motion since the previous solve passed gate g0 */
         if (c->objective == ORC_OBJ_GATE &&
@@ -530,6 +565,8 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
         for (int j = 0; j < ORC_MASK_WORDS; ++j) allow[j] = 0xffffffffu;
         if (c->objective == ORC_OBJ_CONTOUR) theta0 = orc_project(c, x0, 0.0, 1);
     }
+    for (int i = 0; i < 4; ++i) u_used[i] = u_prev[i];
+    *v_used = v_prev;
     if (c->objective == ORC_OBJ_GATE && (g0 < 0 || g0 >= c->n_gates)) return ORC_EINVAL;
     /* reference row of x0, held at the last row past the end of the table */
     int32_t i0 = 0;
@@ -555,6 +592,11 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
             double mg, am;
             double Jm = orc_rollout_cost_ex(c, q, x0, Um, Vm, g0, allow, u_prev, v_prev, theta0, i0,
                                             &mg, NULL, NULL, &am);
+            if (c->ctrl_cost != 0.0) {
+                double ac;
+                Jm += control_cost(c, Ustar, Vstar, Um, Vm, &ac);
+                am += ac;
+            }
             if (Jv) Jv[m] = Jm;
             if (Mv) Mv[m] = mg;
             if (Av) Av[m] = am;
@@ -654,4 +696,29 @@ int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double 
     memcpy(warm->V, Vbar, sizeof(double) * N);
     out->status = ORC_OK;
     return ORC_OK;
+}
+
+int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double x0[13],
+              double t_now, const double *J_rep, const uint8_t *rep_mask, orc_out *out)
+{
+    if (!cfg_valid(q, c) || !warm || !x0 || !out || !out->J || !isfinite(t_now)) return ORC_EINVAL;
+    if ((J_rep == NULL) != (rep_mask == NULL)) return ORC_EINVAL;
+    for (int i = 0; i < 13; ++i) if (!isfinite(x0[i])) return ORC_EINVAL;
+    /* several iterations per control step; the replayed costs belong to the last */
+    const int n_iter = c->n_iter > 1 ? c->n_iter : 1;
+    double u_keep[4] = {0.0, 0.0, 0.0, 0.0}, v_keep = 0.0;
+    int n_amb_earlier = 0, st = ORC_OK;
+    for (int it = 0; it < n_iter; ++it) {
+        const int last = it == n_iter - 1;
+        double u_used[4], v_used;
+        st = solve_iteration(q, c, warm, x0, t_now, last ? J_rep : NULL, last ? rep_mask : NULL, out, it > 0,
+                             u_keep, v_keep, u_used, &v_used);
+        if (it == 0) {
+            memcpy(u_keep, u_used, sizeof u_keep);
+            v_keep = v_used;
+        }
+        if (!last) n_amb_earlier += out->n_amb;
+    }
+    out->n_amb_earlier = n_amb_earlier;
+    return st;
 }

@@ -16,6 +16,9 @@
  *   - contouring cost ............................................. Sec. IV-B-2, Eq. (9)
  *   - softmax weights and weighted update ......................... Eq. (4), Eq. (5)
  *   - receding horizon / warm start ............................... Sec. III-B, Alg. 1
+ *   - two standard MPPI variants the paper does not use, off by default:
+ *     several iterations per control step, and the information-theoretic
+ *     control-cost term (Williams et al.)  ........................ cited in Sec. II-A
  * The noise source (Philox4x32-10, Salmon et al., SC'11, with Box-Muller) is a
  * design choice of this project; the paper only requires Gaussian noise.
  *
@@ -66,7 +69,9 @@ typedef struct {
     const double *path;  int32_t n_path;  double path_len;    /* P x 6: p, unit tangent */
     const double *xref;  int32_t n_ref;   double ref_dt;      /* R x 13 */
     int32_t proj_window;  /* +- points searched around the previous arc length */
-    int32_t pad_;
+    /* standard MPPI variants the paper does not use (0 = off) */
+    int32_t n_iter;       /* MPPI iterations per control step (0 or 1: one)      */
+    double ctrl_cost;     /* gamma of the control-cost term gamma u*^T Sigma^-1 e */
 } orc_cfg;
 
 /* Everything the next solve inherits from this one (receding horizon). */
@@ -101,6 +106,8 @@ typedef struct {
     double *absJ;    /* K   sum of the magnitudes of the quantities a sample's cost adds or
                         subtracts (both squared distances of each Eq. (6) term; may be NULL) */
     double absJ_nom; /* the same sum for the nominal rollout                           */
+    int32_t n_amb_earlier; /* ambiguous samples in the iterations before the last  */
+    int32_t pad2_;
 } orc_out;
 
 /* ---- building blocks (exported for the pin tests) ---------------------- */

@@ -62,7 +62,7 @@ class Cfg(C.Structure):
                 ("gates", C.POINTER(C.c_double)), ("n_gates", C.c_int32), ("gate_size", C.c_double),
                 ("path", C.POINTER(C.c_double)), ("n_path", C.c_int32), ("path_len", C.c_double),
                 ("xref", C.POINTER(C.c_double)), ("n_ref", C.c_int32), ("ref_dt", C.c_double),
-                ("proj_window", C.c_int32), ("pad_", C.c_int32)]
+                ("proj_window", C.c_int32), ("n_iter", C.c_int32), ("ctrl_cost", C.c_double)]
 
 
 class Warm(C.Structure):
@@ -83,7 +83,7 @@ class Out(C.Structure):
                 ("status", C.c_int32), ("pad_", C.c_int32),
                 ("allow", C.c_uint32 * MASK_WORDS), ("front", C.c_uint32 * MASK_WORDS),
                 ("front_amb", C.c_uint32 * MASK_WORDS), ("absJ", C.POINTER(C.c_double)),
-                ("absJ_nom", C.c_double)]
+                ("absJ_nom", C.c_double), ("n_amb_earlier", C.c_int32), ("pad2_", C.c_int32)]
 
 
 _D = C.POINTER(C.c_double)
@@ -252,6 +252,8 @@ class Problem:
         c.Q_w[:] = list(prm.get("Q_w", [0.0] * 3))
         c.r_dv = prm.get("r_dv", 0.0); c.mu = prm.get("mu", 0.0); c.v_max = prm.get("v_max", 0.0)
         c.proj_window = prm.get("proj_window", 64)
+        c.n_iter = prm.get("n_iter", 1)
+        c.ctrl_cost = prm.get("ctrl_cost", 0.0)
         self.gates = None if gates is None else _arr(gates).reshape(-1, 4).copy()
         self.path = None if path is None else _arr(path).reshape(-1, 6).copy()
         self.xref = None if xref is None else _arr(xref).reshape(-1, 13).copy()
@@ -360,7 +362,7 @@ class Problem:
         return dict(status=st, J=J, w=w, U=U.reshape(N, 4), V=V, margin=mg, absJ=A,
                     Ustar=Us.reshape(N, 4), Vstar=Vs, J_min=o.J_min, S=o.S, ess=o.ess,
                     J_nom=o.J_nom, absJ_nom=o.absJ_nom, theta0=o.theta0, g0=o.g0, i0=o.i0, shift=o.shift,
-                    n_amb=o.n_amb, allow=list(o.allow), front=list(o.front),
+                    n_amb=o.n_amb, n_amb_earlier=o.n_amb_earlier, allow=list(o.allow), front=list(o.front),
                     front_amb=list(o.front_amb))
 
 
