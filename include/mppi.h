@@ -89,6 +89,23 @@ typedef struct {
     double v_max;         /* contouring: progress-speed bound, m/s             */
     int32_t proj_window;  /* contouring: +- table points searched for theta0   */
     int32_t flags;        /* MPPI_FLAG_* (0 for a stand-alone context)          */
+    /* Two standard MPPI variants the paper does not use; zero keeps the
+     * paper's method (one iteration, cost of Eq. (6)-(9) alone). */
+    int32_t n_iter;       /* MPPI iterations per solve, 0..64 (0 and 1: one).
+                             Iterations after the first sample around the
+                             previous iteration's solution from the same x0
+                             and t_now without shifting it, keep the first
+                             iteration's last applied input for the rate
+                             terms and draw with the next solve counter; the
+                             solve reports the last iteration.            */
+    double ctrl_cost;     /* gamma >= 0 of the information-theoretic control
+                             cost gamma * sum_k sum_i U*_ki (U_ki - U*_ki) /
+                             sigma_i^2 added to each sample's cost (channels
+                             with sigma_i > 0, contouring speed included),
+                             U* the shifted warm start, U the clipped sample;
+                             0: off.  A nonzero gamma needs the sample
+                             tensor, so it switches the regenerating average
+                             off.                                          */
 } mppi_params;
 
 /* The context allocates no per-solve workspace (sample tensor, costs,
@@ -293,7 +310,8 @@ typedef struct {
 } mppi_batch_cfg;
 
 /* Register ctxs[0..n-1] (distinct, same precision, each used by no other
- * batch or call while the batch runs).  stream: hipStream_t of the batch's
+ * batch or call while the batch runs; one iteration per solve and no
+ * control-cost term: MPPI_E_INVAL otherwise).  stream: hipStream_t of the batch's
  * launches (NULL: one owned by the batch).  cfg NULL: all automatic, graph on.
  * The contexts must outlive the batch. */
 mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, const mppi_batch_cfg *cfg,
@@ -325,7 +343,8 @@ const char *mppi_batch_last_error(const mppi_batch *b);
 /* ---- Serving: continuous batching of solves from many drones ----
  *
  * The server owns no drone state: it registers contexts created with
- * MPPI_FLAG_EXTERNAL_WORKSPACE (one per drone, all of one precision; each
+ * MPPI_FLAG_EXTERNAL_WORKSPACE (one per drone, all of one precision, one
+ * iteration per solve and no control-cost term; each
  * keeps its warm-start state, gate index and problem data resident on the
  * device).  Requests queue per drone in arrival order; a drone has at most
  * one solve in flight, since each solve starts from the previous one's warm

@@ -69,7 +69,8 @@ struct KArgs {
     int32_t regen;              // 1: no sample tensor; the weighted average draws the samples again
                                 // (three- and four-wave layouts, whose rollout draws them)
     int32_t rollout_draw;       // 1: the one-wave rollout draws its samples (no sample kernel)
-    int32_t pad_;
+    int32_t inner;              // 1: an inner iteration of a control step (no shift, the first
+                                // iteration's last applied input)
     uint32_t seed_lo, seed_hi;
     // model
     double inv_mass, gravity, arm_s, c_tau;
@@ -80,6 +81,8 @@ struct KArgs {
     double dt, lambda, sigma[4], sigma_v;
     // costs
     double w_lim, q_near, r_near, gate_half;
+    double ctrl_cost;           // gamma of the control-cost term (0: off)
+    double inv_sig2[5];         // 1/sigma_i^2 of the four thrusts and the speed, 0 where sigma_i = 0
     double Q[13], QN[13], R_dT[4];
     double q_l, q_c, Q_w[3], r_dv, mu, v_max;
     double path_len, ref_dt;

@@ -127,7 +127,16 @@ struct HeadVals {
     double x0[13];
 };
 
-// Run by all threads of one block (any size up to 256); h is in LDS.
+// Steps the warm start is shifted by: none in an inner iteration of the same
+// control step (the previous iteration ran at this time), else
+// max(1, round(elapsed / dt)).
+__device__ __forceinline__ int warm_shift(const KArgs &a, int warm, double t_now, double t_prev)
+{
+    if (a.inner && warm && t_prev == t_now) return 0;
+    return solve_shift(warm, t_now, t_prev, a.dt);
+}
+
+// Run by all threads of one block (any size up to 512); h is in LDS.
 __device__ void compute_head(const KArgs &a, HeadVals &h)
 {
     __shared__ double s_d2[512];   // one entry per thread, up to 512 threads
@@ -200,14 +209,17 @@ __device__ void compute_head(const KArgs &a, HeadVals &h)
         }
         h.g0 = g0;
         h.i0 = i0;
-        h.shift = solve_shift(warm, t_now, w->t_prev, a.dt);
+        h.shift = warm_shift(a, warm, t_now, w->t_prev);
         h.warm = warm;
         h.s = w->s;
         for (int j = 0; j < kMaskWords; ++j) h.allow[j] = allow[j];
         h.theta0 = theta0;
         h.t_now = t_now;
-        for (int i = 0; i < 4; ++i) h.u_prev[i] = warm ? a.wU[i] : a.hover;
-        h.v_prev = warm ? a.wV[0] : 0.0;
+        // an inner iteration keeps the last applied input of the control step,
+        // which the previous iteration published
+        const bool same_step = a.inner && warm && w->t_prev == t_now;
+        for (int i = 0; i < 4; ++i) h.u_prev[i] = same_step ? a.cur->u_prev[i] : (warm ? a.wU[i] : a.hover);
+        h.v_prev = same_step ? a.cur->v_prev : (warm ? a.wV[0] : 0.0);
         for (int i = 0; i < 13; ++i) h.x0[i] = a.req[i];
     }
     __syncthreads();
@@ -255,7 +267,7 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
     // nominal of this solve: the previous solution shifted, or hover (cold)
     const DevWarm *w = a.warm;
     const int warm = w->warm;
-    const int shift = solve_shift(warm, a.req[13], w->t_prev, a.dt);
+    const int shift = warm_shift(a, warm, a.req[13], w->t_prev);
     const uint32_t s = w->s;
     const int N = a.N, K = a.K;
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
@@ -2023,6 +2035,51 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(192) void k_rollo
     rollout3_body<OBJ, Real>(a, blockIdx.x, h);
 }
 
+// ---------------------------------------------------------------- control cost
+
+// The control-cost term of information-theoretic MPPI added to every sample's
+// cost: gamma * sum_k sum_i U*_k,i (U^m_k,i - U*_k,i) / sigma_i^2 over the
+// channels with sigma_i > 0 (thrusts, then the contouring speed), U* the
+// shifted warm start of the solve and U^m the stored clipped sample, summed in
+// step order.  One wave per 64-sample tile reads its samples step by step
+// (64 consecutive records per step) and rewrites the tile's smallest finite
+// cost.
+template <typename Real, bool HAS_V> __global__ __launch_bounds__(64) void k_ctrl_cost(KArgs a)
+{
+    typedef typename Vec4<Real>::T R4;
+    const int tile = blockIdx.x, m = tile * 64 + (int)threadIdx.x;
+    const int K = a.K, N = a.N;
+    const DevCur *cur = a.cur;
+    const int shift = cur->shift;
+    const bool warm = cur->warm != 0;
+    const Real gam = (Real)a.ctrl_cost, hover = (Real)a.hover;
+    const Real is0 = (Real)a.inv_sig2[0], is1 = (Real)a.inv_sig2[1], is2 = (Real)a.inv_sig2[2];
+    const Real is3 = (Real)a.inv_sig2[3], isv = (Real)a.inv_sig2[4];
+    Real Jm = Real(INFINITY);
+    if (m < K) {
+        const R4 *ctrl = (const R4 *)a.ctrl;
+        const Real *vctrl = (const Real *)a.vctrl;
+        Real C = Real(0);
+        for (int k = 0; k < N; ++k) {
+            const int src = k + shift < N ? k + shift : N - 1;
+            const Real u0 = warm ? (Real)a.wU[4 * src + 0] : hover, u1 = warm ? (Real)a.wU[4 * src + 1] : hover;
+            const Real u2 = warm ? (Real)a.wU[4 * src + 2] : hover, u3 = warm ? (Real)a.wU[4 * src + 3] : hover;
+            const R4 u = ctrl[(size_t)k * (size_t)K + (size_t)m];
+            C += gam * u0 * (u.x - u0) * is0;
+            C += gam * u1 * (u.y - u1) * is1;
+            C += gam * u2 * (u.z - u2) * is2;
+            C += gam * u3 * (u.w - u3) * is3;
+            if (HAS_V) {
+                const Real vs = warm ? (Real)a.wV[src] : Real(0);
+                C += gam * vs * (vctrl[(size_t)k * (size_t)K + (size_t)m] - vs) * isv;
+            }
+        }
+        Jm = ((Real *)a.J)[m] + C;
+        ((Real *)a.J)[m] = Jm;
+    }
+    store_tile_min(Jm, m < K && isfinite(Jm), a.tmin, tile);
+}
+
 // ---------------------------------------------------------------- weighted average
 
 template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
@@ -2512,6 +2569,8 @@ static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hip
     } else {
         hipLaunchKernelGGL((k_rollout<OBJ, Real, false>), gt, dim3(64), 0, st, a);
     }
+    if (a.ctrl_cost != 0.0)
+        hipLaunchKernelGGL((k_ctrl_cost<Real, HAS_V>), dim3(a.n_tiles), dim3(64), 0, st, a);
     if (ev) (void)hipEventRecord(ev[2], st);
     hipError_t e = (acc64 || sizeof(Real) == 8) ? launch_average_t<Real, double, HAS_V>(a, st)
                                                 : launch_average_t<Real, float, HAS_V>(a, st);

@@ -51,6 +51,7 @@ struct mppi_ctx {
     bool external_ws = false;   // per-solve scratch is lent by a server
     size_t ws_bytes = 0;        // size of that scratch
     int device = 0;             // device current at creation
+    int n_iter = 1;             // MPPI iterations per solve
     std::string err;
 };
 
@@ -139,6 +140,9 @@ static mppi_status validate(const mppi_params *p, const mppi_quad *q, const mppi
         if (!(p->sigma[i] >= 0.0) || !isfinite(p->sigma[i]))
             return fail(nullptr, MPPI_E_INVAL, "sigma[%d] must be finite and >= 0", i);
     if (!(p->sigma_v >= 0.0) || !isfinite(p->sigma_v)) return fail(nullptr, MPPI_E_INVAL, "sigma_v must be >= 0");
+    if (p->n_iter < 0 || p->n_iter > 64) return fail(nullptr, MPPI_E_INVAL, "n_iter=%d outside [0, 64]", p->n_iter);
+    if (!(p->ctrl_cost >= 0.0) || !isfinite(p->ctrl_cost))
+        return fail(nullptr, MPPI_E_INVAL, "ctrl_cost must be finite and >= 0");
     const double sc[] = {p->w_lim, p->q_near, p->r_near, p->q_l, p->q_c, p->r_dv, p->mu, p->v_max};
     if (!finite_all(sc, 8) || !finite_all(p->Q, 13) || !finite_all(p->QN, 13) || !finite_all(p->R_dT, 4) ||
         !finite_all(p->Q_w, 3))
@@ -229,6 +233,17 @@ static void bind_workspace(KArgs &a, char *w)
     a.front8 = (uint8_t *)(w + wl.front8);
 }
 
+// The launch sequence of one solve: n_iter MPPI iterations, the later ones
+// marked inner (no shift, the first iteration's last applied input).
+static mppi_status launch_iterations(mppi_ctx *ctx, KArgs a)
+{
+    for (int it = 0; it < ctx->n_iter; ++it) {
+        a.inner = it > 0 ? 1 : 0;
+        HIP_TRY(ctx, launch_solve(a, ctx->fp64, ctx->acc64, ctx->stream, next_events(ctx)));
+    }
+    return MPPI_OK;
+}
+
 extern "C" {
 
 const char *mppi_status_string(mppi_status s)
@@ -295,6 +310,10 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.dt = p.dt; a.lambda = p.lambda;
     for (int i = 0; i < 4; ++i) { a.sigma[i] = p.sigma[i]; a.R_dT[i] = p.R_dT[i]; }
     a.sigma_v = p.sigma_v;
+    a.ctrl_cost = p.ctrl_cost;
+    for (int i = 0; i < 4; ++i) a.inv_sig2[i] = p.sigma[i] > 0.0 ? 1.0 / (p.sigma[i] * p.sigma[i]) : 0.0;
+    a.inv_sig2[4] = p.sigma_v > 0.0 ? 1.0 / (p.sigma_v * p.sigma_v) : 0.0;
+    c->n_iter = p.n_iter > 1 ? p.n_iter : 1;
     a.w_lim = p.w_lim; a.q_near = p.q_near; a.r_near = p.r_near;
     a.gate_half = 0.5 * problem->gate_size;
     for (int i = 0; i < 13; ++i) { a.Q[i] = p.Q[i]; a.QN[i] = p.QN[i]; }
@@ -309,8 +328,10 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.C = c->C;
     a.real_bytes = (int32_t)rs;
     c->external_ws = (params->flags & MPPI_FLAG_EXTERNAL_WORKSPACE) != 0;
-    // the average can draw the samples again only where the rollout draws them
-    a.regen = ((params->flags & MPPI_FLAG_REGEN_AVERAGE) != 0 && a.rollout_waves >= 3) ? 1 : 0;
+    // the average can draw the samples again only where the rollout draws them,
+    // and not when the control-cost term reads the sample tensor
+    a.regen = ((params->flags & MPPI_FLAG_REGEN_AVERAGE) != 0 && a.rollout_waves >= 3 && p.ctrl_cost == 0.0)
+                  ? 1 : 0;
     struct Want { void **dst; size_t bytes; };
     void *gates_d = nullptr, *gates_r = nullptr, *path_d = nullptr, *path_r = nullptr, *xref_r = nullptr;
     void *warm = nullptr, *wU = nullptr, *wV = nullptr, *cur = nullptr, *res = nullptr, *req = nullptr;
@@ -407,8 +428,7 @@ mppi_status mppi_solve_device(mppi_ctx *ctx, const double *d_req, double *d_u0)
     KArgs a = ctx->args;
     a.req = d_req;
     a.u0_out = d_u0;
-    HIP_TRY(ctx, launch_solve(a, ctx->fp64, ctx->acc64, ctx->stream, next_events(ctx)));
-    return MPPI_OK;
+    return launch_iterations(ctx, a);
 }
 
 mppi_status mppi_solve_device_noalloc(mppi_ctx *ctx, const double *d_req, double *d_u0)
@@ -429,8 +449,7 @@ mppi_status mppi_solve_device_noalloc(mppi_ctx *ctx, const double *d_req, double
     bind_workspace(a, (char *)base);
     a.req = d_req;
     a.u0_out = d_u0;
-    HIP_TRY(ctx, launch_solve(a, ctx->fp64, ctx->acc64, ctx->stream, next_events(ctx)));
-    return MPPI_OK;
+    return launch_iterations(ctx, a);
 }
 
 mppi_status mppi_set_profiling(mppi_ctx *ctx, int32_t enable)
@@ -506,7 +525,8 @@ mppi_status mppi_solve(mppi_ctx *ctx, const double x0[13], double t_now, double 
     KArgs a = ctx->args;
     a.req = ctx->req;
     a.u0_out = nullptr;
-    HIP_TRY(ctx, launch_solve(a, ctx->fp64, ctx->acc64, ctx->stream, next_events(ctx)));
+    mppi_status ls = launch_iterations(ctx, a);
+    if (ls != MPPI_OK) return ls;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_res, ctx->res, sizeof(DevResult), hipMemcpyDeviceToHost, ctx->stream));
     if (U_out)
         HIP_TRY(ctx, hipMemcpyAsync(ctx->h_U, ctx->args.wU, sizeof(double) * 4 * ctx->N, hipMemcpyDeviceToHost,
@@ -791,6 +811,9 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d is NULL", i);
         if (ctxs[i]->fp64 != ctxs[0]->fp64) return bfail(nullptr, MPPI_E_INVAL, "contexts differ in precision");
+        if (ctxs[i]->n_iter != 1 || ctxs[i]->args.ctrl_cost != 0.0)
+            return bfail(nullptr, MPPI_E_INVAL, "context %d: batches run one iteration without the control-cost term",
+                         i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d registered twice", i);
     }
@@ -1266,9 +1289,13 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
     if (!drones || n < 1 || !cfg) return sfail(nullptr, MPPI_E_INVAL, "drones and cfg are required");
     if (!(cfg->budget_bytes > 0.0) || cfg->n_slots < 1 || cfg->n_slots > 16 || cfg->max_batch < 0)
         return sfail(nullptr, MPPI_E_INVAL, "invalid server configuration");
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (!drones[i] || !drones[i]->external_ws)
             return sfail(nullptr, MPPI_E_INVAL, "drone %d: context must be created with MPPI_FLAG_EXTERNAL_WORKSPACE", i);
+        if (drones[i]->n_iter != 1 || drones[i]->args.ctrl_cost != 0.0)
+            return sfail(nullptr, MPPI_E_INVAL, "drone %d: served solves run one iteration without the control-cost term",
+                         i);
+    }
     mppi_server *s = new (std::nothrow) mppi_server();
     if (!s) return sfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
     s->drones.assign(drones, drones + n);

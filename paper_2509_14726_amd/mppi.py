@@ -55,7 +55,8 @@ class mppi_params(C.Structure):
                 ("Q", C.c_double * 13), ("QN", C.c_double * 13), ("R_dT", C.c_double * 4),
                 ("q_l", C.c_double), ("q_c", C.c_double), ("Q_w", C.c_double * 3),
                 ("r_dv", C.c_double), ("mu", C.c_double), ("v_max", C.c_double),
-                ("proj_window", C.c_int32), ("flags", C.c_int32)]
+                ("proj_window", C.c_int32), ("flags", C.c_int32), ("n_iter", C.c_int32),
+                ("ctrl_cost", C.c_double)]
 
 
 FLAG_EXTERNAL_WORKSPACE = 1
@@ -239,6 +240,8 @@ def make_params(p: dict, precision: int) -> mppi_params:
     s.r_dv = p.get("r_dv", 0.0); s.mu = p.get("mu", 0.0); s.v_max = p.get("v_max", 0.0)
     s.proj_window = p.get("proj_window", 64)
     s.flags = p.get("flags", 0)
+    s.n_iter = p.get("n_iter", 1)
+    s.ctrl_cost = p.get("ctrl_cost", 0.0)
     return s
 
 

@@ -97,7 +97,8 @@ def _log(rec: dict):
 
 
 def solve_and_compare(dev: M.Solver, orc: O.Problem, x0, t_now: float, precision: int,
-                      sigma: float = 1.0, check_warm: bool = True, strict_e2e: bool | None = None):
+                      sigma: float = 1.0, check_warm: bool = True, strict_e2e: bool | None = None,
+                      skip_ambiguous_earlier: bool = False):
     """Import the device's warm state into the oracle, solve on both sides,
     compare (with decision replay), then check the warm states they hand on.
     strict_e2e: gate the FP32 end-to-end controls at 1e-4 without the
@@ -108,18 +109,22 @@ def solve_and_compare(dev: M.Solver, orc: O.Problem, x0, t_now: float, precision
     Jd, _ = dev.read_samples()
     wn = dev.get_warm() if check_warm else None
     return compare_result(orc, wd, x0, t_now, precision, u0, U, info, Jd=Jd, wn=wn, sigma=sigma,
-                          strict_e2e=strict_e2e)
+                          strict_e2e=strict_e2e, skip_ambiguous_earlier=skip_ambiguous_earlier)
 
 
 def compare_result(orc: O.Problem, wd: M.mppi_warm, x0, t_now: float, precision: int, u0, U, info: dict,
-                   Jd=None, wn: M.mppi_warm | None = None, sigma: float = 1.0, strict_e2e: bool | None = None):
+                   Jd=None, wn: M.mppi_warm | None = None, sigma: float = 1.0, strict_e2e: bool | None = None,
+                   skip_ambiguous_earlier: bool = False):
     """Compare one device solve with the oracle's solve from the same warm
     state wd (the state exported before the device solve).  u0, U, info: the
     device's first input, solution and report; Jd: its sample costs, or None
     when the workspace that held them is gone (served solves: then no sample
     may be ambiguous, the costs are not compared one by one and the controls
     are gated end to end at the tolerance); wn: the warm state the device
-    handed on, or None."""
+    handed on, or None.  With several iterations per solve only the last
+    iteration's costs can be replayed: a solve whose earlier iterations hold
+    an ambiguous sample fails, or with skip_ambiguous_earlier returns after
+    the integer outputs with skipped=True."""
     tol = TOL[precision]
     cfg = orc.cfg
     if strict_e2e is None:
@@ -130,8 +135,13 @@ def compare_result(orc: O.Problem, wd: M.mppi_warm, x0, t_now: float, precision:
     U = np.asarray(U).reshape(cfg.N, 4)
     r = orc.solve(ow, x0, t_now)
     assert r["status"] == O.OK
+    n_iter = max(cfg.n_iter, 1)
+    assert info["solve_index"] == wd.solve_index + n_iter - 1
+    # only the last iteration's costs can be replayed: earlier ones must be unambiguous
+    if r["n_amb_earlier"] > 0:
+        assert skip_ambiguous_earlier, f"{r['n_amb_earlier']} ambiguous samples before the last iteration"
+        return dict(skipped=True, n_amb_earlier=int(r["n_amb_earlier"]), info=info, U=U)
     assert info["g0"] == r["g0"] and info["shift"] == r["shift"] and info["i0"] == r["i0"]
-    assert info["solve_index"] == wd.solve_index
     amb = r["margin"] < EPS_DEC[precision]
     scale = np.maximum(np.abs(r["J"]), r["absJ"])
     if Jd is None:
@@ -185,7 +195,7 @@ def compare_result(orc: O.Problem, wd: M.mppi_warm, x0, t_now: float, precision:
     if cfg.objective == O.OBJ_CONTOUR:
         assert abs(info["theta0"] - r["theta0"]) <= 1e-9 * max(cfg.path_len, 1.0)
     if wn is not None:
-        assert wn.warm == 1 and wn.g0 == r["g0"] and wn.solve_index == wd.solve_index + 1
+        assert wn.warm == 1 and wn.g0 == r["g0"] and wn.solve_index == wd.solve_index + n_iter
         # the pass mask handed on: bits whose nominal state lies within eps of
         # the gate plane may differ
         n = cfg.N + 1
@@ -194,7 +204,7 @@ def compare_result(orc: O.Problem, wd: M.mppi_warm, x0, t_now: float, precision:
         famb = O.mask_bits(r["front_amb"], n)
         assert np.array_equal(dbits[~famb], obits[~famb])
         np.testing.assert_allclose(np.array(wn.U[:4 * cfg.N]).reshape(-1, 4), U, rtol=0, atol=0)
-    out = dict(err_J=float(err_J[~amb].max()) if (Jd is not None and (~amb).any()) else 0.0,
+    out = dict(skipped=False, err_J=float(err_J[~amb].max()) if (Jd is not None and (~amb).any()) else 0.0,
                err_U=float(err_U.max()),
                err_U_e2e=e2e, e2e_bound=bound, n_amb=int(amb.sum()), err_ess=float(err_ess),
                err_J_min=float(err_min), info=info, ref=ref, J=Jd, U=U)
