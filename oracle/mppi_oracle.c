@@ -6,6 +6,9 @@
  * one listed in the project's design notes; the ones that shape the numbers
  * are repeated next to the code that implements them.
  *
+ * Two input models: the four rotor thrusts (13 states), or the paper's thrust
+ * rates with the thrusts as states (17 states, Sec. III-A).
+ *
  * Build: gcc -O2 -std=c99 -fPIC -shared -fopenmp -ffp-contract=off
  * (no fast-math, no FMA contraction: the arithmetic is exactly what is written).
  */
@@ -80,9 +83,9 @@ void orc_normals(uint64_t seed, uint32_t m, uint32_t k, uint32_t s, uint32_t ch,
 
 /* ------------------------------------------------------------------------ */
 /* Dynamics, Sec. III-A, Eq. (2).  State x = [p(3), v(3), q(4), w(3)] with the
- * quaternion q = (qw, qx, qy, qz), Hamilton convention, body-to-world.  The
- * input is the vector of the four rotor thrusts T (this project feeds thrusts,
- * not their derivatives, as the input).                                      */
+ * quaternion q = (qw, qx, qy, qz), Hamilton convention, body-to-world, driven
+ * by the four rotor thrusts T: the input of the thrust model, or four more
+ * states whose derivatives are the input in the paper's rate model.        */
 
 static void rot_matrix(const double q[4], double R[9])
 {
@@ -158,6 +161,33 @@ void orc_rk4(const orc_quad *qd, const double x[13], const double T[4], double d
     for (int i = 0; i < 13; ++i) xs[i] = x[i] + dt * k3[i];
     orc_f(qd, xs, T, k4);
     for (int i = 0; i < 13; ++i) xn[i] = x[i] + h6 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    double nq = sqrt(xn[6] * xn[6] + xn[7] * xn[7] + xn[8] * xn[8] + xn[9] * xn[9]);
+    for (int i = 6; i < 10; ++i) xn[i] /= nq;
+}
+
+/* The paper's input model (Sec. III-A): the rotor thrusts are states and the
+ * input is their time derivative.  f of the 13 states is Eq. (2) at the
+ * current thrusts; the thrusts' own derivative is the input. */
+void orc_f_rate(const orc_quad *qd, const double x[17], const double Tdot[4], double xd[17])
+{
+    orc_f(qd, x, x + 13, xd);
+    for (int i = 0; i < 4; ++i) xd[13 + i] = Tdot[i];
+}
+
+/* Classical RK4 of the 17-state system with the rate held over the step, then
+ * the quaternion scaled back to unit norm. */
+void orc_rk4_rate(const orc_quad *qd, const double x[17], const double Tdot[4], double dt, double xn[17])
+{
+    double k1[17], k2[17], k3[17], k4[17], xs[17];
+    const double h2 = 0.5 * dt, h6 = dt / 6.0;
+    orc_f_rate(qd, x, Tdot, k1);
+    for (int i = 0; i < 17; ++i) xs[i] = x[i] + h2 * k1[i];
+    orc_f_rate(qd, xs, Tdot, k2);
+    for (int i = 0; i < 17; ++i) xs[i] = x[i] + h2 * k2[i];
+    orc_f_rate(qd, xs, Tdot, k3);
+    for (int i = 0; i < 17; ++i) xs[i] = x[i] + dt * k3[i];
+    orc_f_rate(qd, xs, Tdot, k4);
+    for (int i = 0; i < 17; ++i) xn[i] = x[i] + h6 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
     double nq = sqrt(xn[6] * xn[6] + xn[7] * xn[7] + xn[8] * xn[8] + xn[9] * xn[9]);
     for (int i = 6; i < 10; ++i) xn[i] /= nq;
 }
@@ -284,6 +314,42 @@ void orc_sample(const orc_cfg *c, const orc_quad *q, const double *Ustar, const 
     }
 }
 
+/* Rate-model sampling, Eq. (3) with the paper's input u = dT/dt: each sampled
+ * rate is clipped to the rate bounds (Table I) and then to the range that keeps
+ * the thrust within its bounds at the end of the step (the thrust is linear
+ * over the step, so it stays within them throughout); the thrust chain starts
+ * at the measured T0.  Contouring samples the progress acceleration, clipped
+ * to its bounds and to the range that keeps the progress speed in
+ * [0, v_max].  The clipped values are the ones rolled out and averaged. */
+void orc_sample_rate(const orc_cfg *c, const orc_quad *q, const double *Ustar, const double *Vstar,
+                     uint32_t m, uint32_t s, int noisy, const double T0[4], double v0, double *U, double *V)
+{
+    double T[4] = {T0[0], T0[1], T0[2], T0[3]}, v = v0;
+    for (int k = 0; k < c->N; ++k) {
+        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (noisy) orc_normals(c->seed, m, (uint32_t)k, s, 0u, z);
+        for (int i = 0; i < 4; ++i) {
+            const double raw = noisy ? Ustar[4 * k + i] + c->sigma[i] * z[i] : Ustar[4 * k + i];
+            const double r = clampd(raw, c->rate_lim[0], c->rate_lim[1]);
+            const double u = clampd(r, (q->t_min - T[i]) / c->dt, (q->t_max - T[i]) / c->dt);
+            U[4 * k + i] = u;
+            T[i] = T[i] + c->dt * u;
+        }
+        if (c->objective == ORC_OBJ_CONTOUR && V) {
+            double zv = 0.0;
+            if (noisy) {
+                orc_normals(c->seed, m, (uint32_t)k, s, 1u, z);
+                zv = z[0];
+            }
+            const double raw = noisy ? Vstar[k] + c->sigma_v * zv : Vstar[k];
+            const double r = clampd(raw, c->dv_lim[0], c->dv_lim[1]);
+            const double a = clampd(r, (0.0 - v) / c->dt, (c->v_max - v) / c->dt);
+            V[k] = a;
+            v = v + c->dt * a;
+        }
+    }
+}
+
 /* Feasibility penalty (Sec. III-B: states outside their limits are charged an
  * extra cost): quadratic hinge on each body rate beyond w_max. */
 static double limit_cost(const orc_cfg *c, const orc_quad *q, const double x[13])
@@ -332,13 +398,16 @@ static int get_bit(const uint32_t *mask, int j)
  *              theta_{k+1} = theta_k + V_k dt (mod L).
  * When front is non-NULL the rollout is the nominal one and bit j of front is
  * set when state j (j = 0..N) is in front of gate g0.                        */
-double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[13],
+double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double *x0,
                            const double *U, const double *V, int32_t g0, const uint32_t *allow,
                            const double u_prev[4], double v_prev, double theta0, int32_t i0,
                            double *margin, uint32_t *front, uint32_t *front_amb, double *abs_sum)
 {
-    double x[13], xn[13];
-    memcpy(x, x0, sizeof x);
+    const int rate = c->input_model == ORC_INPUT_RATE;
+    const int nx = rate ? 17 : 13;
+    double x[17], xn[17];
+    memcpy(x, x0, sizeof(double) * nx);
+    double vth = v_prev; /* rate model, contouring: the progress speed state */
     double J = 0.0;
     double Jabs = 0.0; /* sum of the magnitudes of the quantities added to or
                           subtracted from J */
@@ -364,10 +433,15 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
             int r = i0 + k < c->n_ref ? i0 + k : c->n_ref - 1;
             const double *xr = c->xref + 13 * r;
             for (int i = 0; i < 13; ++i) ORC_ADD(c->Q[i] * (x[i] - xr[i]) * (x[i] - xr[i]));
-            const double *Up = k > 0 ? U + 4 * (k - 1) : u_prev;
-            for (int i = 0; i < 4; ++i) {
-                double d = (Uk[i] - Up[i]) / c->dt;
-                ORC_ADD(c->R_dT[i] * d * d);
+            if (rate) {
+                /* the input itself is the thrust rate of Eq. (8)'s u_k */
+                for (int i = 0; i < 4; ++i) ORC_ADD(c->R_dT[i] * Uk[i] * Uk[i]);
+            } else {
+                const double *Up = k > 0 ? U + 4 * (k - 1) : u_prev;
+                for (int i = 0; i < 4; ++i) {
+                    double d = (Uk[i] - Up[i]) / c->dt;
+                    ORC_ADD(c->R_dT[i] * d * d);
+                }
             }
         } else if (c->objective == ORC_OBJ_CONTOUR) {
             double sr = theta / ds;
@@ -389,16 +463,27 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
             ORC_ADD(c->q_l * (el[0] * el[0] + el[1] * el[1] + el[2] * el[2]));
             ORC_ADD(c->q_c * (ec[0] * ec[0] + ec[1] * ec[1] + ec[2] * ec[2]));
             for (int d = 0; d < 3; ++d) ORC_ADD(c->Q_w[d] * x[10 + d] * x[10 + d]);
-            double Vp = k > 0 ? V[k - 1] : v_prev;
-            double dv = (V[k] - Vp) / c->dt;
-            ORC_ADD(c->r_dv * dv * dv);
-            const double *Up = k > 0 ? U + 4 * (k - 1) : u_prev;
-            for (int d = 0; d < 4; ++d) {
-                double dT = (Uk[d] - Up[d]) / c->dt;
-                ORC_ADD(c->R_dT[d] * dT * dT);
+            if (rate) {
+                /* Eq. (9) literally: the sampled progress acceleration, the
+                 * thrust rates, and the progress speed state v_theta,k */
+                ORC_ADD(c->r_dv * V[k] * V[k]);
+                for (int d = 0; d < 4; ++d) ORC_ADD(c->R_dT[d] * Uk[d] * Uk[d]);
+                ORC_ADD(-c->mu * vth);
+                const double vn = vth + c->dt * V[k];
+                theta = wrap_len(theta + 0.5 * c->dt * (vth + vn), c->path_len);
+                vth = vn;
+            } else {
+                double Vp = k > 0 ? V[k - 1] : v_prev;
+                double dv = (V[k] - Vp) / c->dt;
+                ORC_ADD(c->r_dv * dv * dv);
+                const double *Up = k > 0 ? U + 4 * (k - 1) : u_prev;
+                for (int d = 0; d < 4; ++d) {
+                    double dT = (Uk[d] - Up[d]) / c->dt;
+                    ORC_ADD(c->R_dT[d] * dT * dT);
+                }
+                ORC_ADD(-c->mu * V[k]);
+                theta = wrap_len(theta + V[k] * c->dt, c->path_len);
             }
-            ORC_ADD(-c->mu * V[k]);
-            theta = wrap_len(theta + V[k] * c->dt, c->path_len);
         } else {
             /* near-gate term, Eq. (7), w.r.t. the current gate g0 */
             double d2 = sqdist3(x, gate0);
@@ -407,7 +492,8 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
             if (margin && fabs(d - c->r_near) < mrg) mrg = fabs(d - c->r_near);
         }
 
-        orc_rk4(q, x, Uk, c->dt, xn);
+        if (rate) orc_rk4_rate(q, x, Uk, c->dt, xn);
+        else orc_rk4(q, x, Uk, c->dt, xn);
 
         if (c->objective == ORC_OBJ_GATE) {
             const double *gc = c->gates + 4 * g;
@@ -430,7 +516,7 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
                 ++passes;
             }
         }
-        memcpy(x, xn, sizeof x);
+        memcpy(x, xn, sizeof(double) * nx);
     }
     if (c->objective == ORC_OBJ_TRACK) {
         int r = i0 + c->N < c->n_ref ? i0 + c->N : c->n_ref - 1;
@@ -448,7 +534,7 @@ double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[
     return J;
 }
 
-double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13],
+double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double *x0,
                         const double *U, const double *V, int32_t g0, const uint32_t *allow,
                         const double u_prev[4], double v_prev, double theta0, int32_t i0,
                         double *margin, uint32_t *front, uint32_t *front_amb)
@@ -471,6 +557,10 @@ static int cfg_valid(const orc_quad *q, const orc_cfg *c)
     if (!(c->dt > 0.0) || !(c->lambda > 0.0)) return 0;
     for (int i = 0; i < 4; ++i) if (!(c->sigma[i] >= 0.0)) return 0;
     if (c->n_iter < 0 || c->n_iter > 64 || !(c->ctrl_cost >= 0.0) || !isfinite(c->ctrl_cost)) return 0;
+    if (c->input_model != ORC_INPUT_THRUST && c->input_model != ORC_INPUT_RATE) return 0;
+    if (c->input_model == ORC_INPUT_RATE &&
+        (!(c->rate_lim[0] <= 0.0) || !(c->rate_lim[1] >= 0.0) || !(c->dv_lim[0] <= 0.0) || !(c->dv_lim[1] >= 0.0)))
+        return 0;
     if (!(q->mass > 0.0) || !(q->t_max >= q->t_min)) return 0;
     for (int i = 0; i < 3; ++i) if (!(q->inertia[i] > 0.0)) return 0;
     if (c->objective == ORC_OBJ_GATE) {
@@ -518,13 +608,16 @@ static double control_cost(const orc_cfg *c, const double *Ustar, const double *
  * samples around the previous iteration's solution without shifting it and
  * keeps the last applied input (u_keep, v_keep) of the first iteration for
  * the rate terms; *u_used / *v_used return the ones this iteration used. */
-static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double x0[13],
+static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double *x0,
                            double t_now, const double *J_rep, const uint8_t *rep_mask, orc_out *out,
                            int inner, const double u_keep[4], double v_keep, double u_used[4],
                            double *v_used)
 {
     const int K = c->K, N = c->N;
-    const double hover = q->mass * q->gravity / 4.0;
+    const int rate = c->input_model == ORC_INPUT_RATE;
+    /* cold start: hover thrust for the thrust input; for the rate input the
+     * zero sequence of Alg. 1 (it holds the measured thrusts) */
+    const double hover = rate ? 0.0 : q->mass * q->gravity / 4.0;
 
     /* ---- inherited state (receding horizon, Sec. III-B / Alg. 1) ---- */
     double Ustar[ORC_NMAX * 4], Vstar[ORC_NMAX], u_prev[4], v_prev;
@@ -565,6 +658,15 @@ static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, 
         for (int j = 0; j < ORC_MASK_WORDS; ++j) allow[j] = 0xffffffffu;
         if (c->objective == ORC_OBJ_CONTOUR) theta0 = orc_project(c, x0, 0.0, 1);
     }
+    /* rate model, contouring: the progress speed state.  The previous solve's
+     * initial speed advanced over the shift by its averaged accelerations
+     * (clamped to [0, v_max] at each step); an inner iteration keeps it. */
+    double v0 = 0.0;
+    if (rate && warm->warm) {
+        v0 = warm->vtheta;
+        for (int j = 0; j < shift; ++j) v0 = clampd(v0 + c->dt * warm->V[j < N ? j : N - 1], 0.0, c->v_max);
+    }
+    if (rate) v_prev = v0;
     for (int i = 0; i < 4; ++i) u_used[i] = u_prev[i];
     *v_used = v_prev;
     if (c->objective == ORC_OBJ_GATE && (g0 < 0 || g0 >= c->n_gates)) return ORC_EINVAL;
@@ -588,7 +690,8 @@ static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, 
         double Um[ORC_NMAX * 4], Vm[ORC_NMAX];
 #pragma omp for schedule(dynamic, 16)
         for (int m = 0; m < K; ++m) {
-            orc_sample(c, q, Ustar, Vstar, (uint32_t)m, s, Um, Vm);
+            if (rate) orc_sample_rate(c, q, Ustar, Vstar, (uint32_t)m, s, 1, x0 + 13, v0, Um, Vm);
+            else orc_sample(c, q, Ustar, Vstar, (uint32_t)m, s, Um, Vm);
             double mg, am;
             double Jm = orc_rollout_cost_ex(c, q, x0, Um, Vm, g0, allow, u_prev, v_prev, theta0, i0,
                                             &mg, NULL, NULL, &am);
@@ -638,6 +741,22 @@ static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, 
 
     /* ---- update, Eq. (5): U = sum_m w_m U^m, index order over m ---- */
     double Ubar[ORC_NMAX * 4], Vbar[ORC_NMAX];
+    if (rate) {
+        /* a rate sample follows its thrust chain along the horizon: draw each
+         * sample whole; every element still adds the samples in index order */
+        for (int i = 0; i < 4 * N; ++i) Ubar[i] = 0.0;
+        for (int k = 0; k < N; ++k) Vbar[k] = 0.0;
+        double Um[ORC_NMAX * 4], Vm[ORC_NMAX];
+        for (int m = 0; m < K; ++m) {
+            double Je = (rep_mask && rep_mask[m]) ? J_rep[m] : Jv[m];
+            if (!isfinite(Je)) Je = INFINITY;
+            const double wm = exp(-(Je - Jmin) / c->lambda) / S;
+            orc_sample_rate(c, q, Ustar, Vstar, (uint32_t)m, s, 1, x0 + 13, v0, Um, Vm);
+            for (int i = 0; i < 4 * N; ++i) Ubar[i] += wm * Um[i];
+            if (c->objective == ORC_OBJ_CONTOUR)
+                for (int k = 0; k < N; ++k) Vbar[k] += wm * Vm[k];
+        }
+    } else
 #pragma omp parallel for num_threads(nt) schedule(static)
     for (int k = 0; k < N; ++k) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0}, accv = 0.0;
@@ -661,9 +780,13 @@ static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, 
     /* ---- nominal rollout (noise-free sample of U*), whose states in front of
      *      gate g0 become the next solve's temporal-consistency mask ---- */
     double Un[ORC_NMAX * 4], Vn[ORC_NMAX];
-    for (int k = 0; k < N; ++k) {
-        for (int i = 0; i < 4; ++i) Un[4 * k + i] = clampd(Ustar[4 * k + i], q->t_min, q->t_max);
-        Vn[k] = clampd(Vstar[k], 0.0, c->v_max);
+    if (rate) {
+        orc_sample_rate(c, q, Ustar, Vstar, 0u, s, 0, x0 + 13, v0, Un, Vn);
+    } else {
+        for (int k = 0; k < N; ++k) {
+            for (int i = 0; i < 4; ++i) Un[4 * k + i] = clampd(Ustar[4 * k + i], q->t_min, q->t_max);
+            Vn[k] = clampd(Vstar[k], 0.0, c->v_max);
+        }
     }
     uint32_t front[ORC_MASK_WORDS], front_amb[ORC_MASK_WORDS];
     for (int j = 0; j < ORC_MASK_WORDS; ++j) { front[j] = 0xffffffffu; front_amb[j] = 0u; }
@@ -692,18 +815,20 @@ static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, 
     warm->t_prev = t_now;
     memcpy(warm->x_prev, x0, sizeof warm->x_prev);
     warm->theta0 = theta0;
+    warm->vtheta = rate ? v0 : 0.0;
     memcpy(warm->U, Ubar, sizeof(double) * 4 * N);
     memcpy(warm->V, Vbar, sizeof(double) * N);
     out->status = ORC_OK;
     return ORC_OK;
 }
 
-int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double x0[13],
+int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double *x0,
               double t_now, const double *J_rep, const uint8_t *rep_mask, orc_out *out)
 {
     if (!cfg_valid(q, c) || !warm || !x0 || !out || !out->J || !isfinite(t_now)) return ORC_EINVAL;
     if ((J_rep == NULL) != (rep_mask == NULL)) return ORC_EINVAL;
-    for (int i = 0; i < 13; ++i) if (!isfinite(x0[i])) return ORC_EINVAL;
+    for (int i = 0; i < (c->input_model == ORC_INPUT_RATE ? 17 : 13); ++i)
+        if (!isfinite(x0[i])) return ORC_EINVAL;
     /* several iterations per control step; the replayed costs belong to the last */
     const int n_iter = c->n_iter > 1 ? c->n_iter : 1;
     double u_keep[4] = {0.0, 0.0, 0.0, 0.0}, v_keep = 0.0;

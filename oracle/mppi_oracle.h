@@ -37,6 +37,11 @@ extern "C" {
 #define ORC_MASK_WORDS 9      /* holds (ORC_NMAX + 1) bits of per-state flags   */
 
 enum { ORC_OBJ_GATE = 0, ORC_OBJ_CONTOUR = 1, ORC_OBJ_TRACK = 2 };
+/* Input models: the four rotor thrusts (13-state model), or their time
+ * derivatives with the thrusts as four more states (the paper's model,
+ * Sec. III-A: u = dT/dt, 17 states; contouring then samples the progress
+ * acceleration and carries the progress speed as a state, Sec. IV-B-2). */
+enum { ORC_INPUT_THRUST = 0, ORC_INPUT_RATE = 1 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENONFINITE = -4 };
 
 typedef struct {
@@ -72,6 +77,10 @@ typedef struct {
     /* standard MPPI variants the paper does not use (0 = off) */
     int32_t n_iter;       /* MPPI iterations per control step (0 or 1: one)      */
     double ctrl_cost;     /* gamma of the control-cost term gamma u*^T Sigma^-1 e */
+    /* input model (ORC_INPUT_RATE: x0 has 17 entries, thrusts last) */
+    int32_t input_model, pad3_;
+    double rate_lim[2];   /* bounds of the sampled thrust rate, N/s              */
+    double dv_lim[2];     /* bounds of the sampled progress acceleration, m/s^2  */
 } orc_cfg;
 
 /* Everything the next solve inherits from this one (receding horizon). */
@@ -85,7 +94,9 @@ typedef struct {
     double x_prev[13];
     double theta0;                 /* arc length of the previous solve            */
     double U[ORC_NMAX * 4];        /* previous solution, N x 4                    */
-    double V[ORC_NMAX];            /* previous progress-speed solution, N         */
+    double V[ORC_NMAX];            /* previous progress-speed (or acceleration) solution, N */
+    double vtheta;                 /* rate model, contouring: progress speed state at the
+                                      previous solve's initial time                   */
 } orc_warm;
 
 typedef struct {
@@ -116,29 +127,40 @@ double orc_u01(uint32_t word);
 void   orc_normals(uint64_t seed, uint32_t m, uint32_t k, uint32_t s, uint32_t ch, double z[4]);
 void   orc_f(const orc_quad *q, const double x[13], const double T[4], double xd[13]);
 void   orc_rk4(const orc_quad *q, const double x[13], const double T[4], double dt, double xn[13]);
+/* The paper's model: x = (13 states, thrusts T[4]), input dT/dt held over the
+ * step, RK4 of the 17-state system (the thrusts vary linearly over the step). */
+void   orc_f_rate(const orc_quad *q, const double x[17], const double Tdot[4], double xd[17]);
+void   orc_rk4_rate(const orc_quad *q, const double x[17], const double Tdot[4], double dt, double xn[17]);
+/* Rate-model samples: the sampled rates are clipped to the rate bounds and then
+ * to the range that keeps each thrust (speed) within its bounds over the step,
+ * following the thrust (speed) chain from T0 (v0); z == NULL: no noise. */
+void   orc_sample_rate(const orc_cfg *c, const orc_quad *q, const double *Ustar, const double *Vstar,
+                       uint32_t m, uint32_t s, int noisy, const double T0[4], double v0, double *U,
+                       double *V);
 int    orc_gate_cross(const double pa[3], const double pb[3], const double gate[4],
                       double size, double *margin);
 double orc_project(const orc_cfg *c, const double p[3], double theta_prev, int global);
 void   orc_sample(const orc_cfg *c, const orc_quad *q, const double *Ustar, const double *Vstar,
                   uint32_t m, uint32_t s, double *U, double *V);
-double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double x0[13],
+double orc_rollout_cost(const orc_cfg *c, const orc_quad *q, const double *x0,
                         const double *U, const double *V, int32_t g0, const uint32_t *allow,
                         const double u_prev[4], double v_prev, double theta0, int32_t i0,
                         double *margin, uint32_t *front, uint32_t *front_amb);
 /* The same, also returning the sum of the magnitudes of the terms added to
  * the cost (the scale of its rounding error). */
-double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double x0[13],
+double orc_rollout_cost_ex(const orc_cfg *c, const orc_quad *q, const double *x0,
                            const double *U, const double *V, int32_t g0, const uint32_t *allow,
                            const double u_prev[4], double v_prev, double theta0, int32_t i0,
                            double *margin, uint32_t *front, uint32_t *front_amb, double *abs_sum);
 
 /* ---- one MPPI step --------------------------------------------------------
+ * x0 holds 13 states (17 for ORC_INPUT_RATE: the thrusts appended).
  * warm is read (inherited state) and, on success, replaced by the state the
  * next solve inherits.  J_rep/rep_mask (both NULL or both K long) substitute
  * the given cost for every sample whose mask byte is non-zero before the
  * weights are formed; they let a test resolve a decision that lies within
  * rounding distance of its threshold the way the device resolved it. */
-int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double x0[13],
+int orc_solve(const orc_quad *q, const orc_cfg *c, orc_warm *warm, const double *x0,
               double t_now, const double *J_rep, const uint8_t *rep_mask, orc_out *out);
 
 void orc_warm_init(orc_warm *w, int32_t g0);

@@ -22,6 +22,7 @@ COUNT_SRC = os.path.join(HERE, "opcount.cpp")
 NMAX = 256
 MASK_WORDS = 9
 OBJ_GATE, OBJ_CONTOUR, OBJ_TRACK = 0, 1, 2
+INPUT_THRUST, INPUT_RATE = 0, 1
 OK, EINVAL, ENONFINITE = 0, -1, -4
 
 
@@ -62,14 +63,16 @@ class Cfg(C.Structure):
                 ("gates", C.POINTER(C.c_double)), ("n_gates", C.c_int32), ("gate_size", C.c_double),
                 ("path", C.POINTER(C.c_double)), ("n_path", C.c_int32), ("path_len", C.c_double),
                 ("xref", C.POINTER(C.c_double)), ("n_ref", C.c_int32), ("ref_dt", C.c_double),
-                ("proj_window", C.c_int32), ("n_iter", C.c_int32), ("ctrl_cost", C.c_double)]
+                ("proj_window", C.c_int32), ("n_iter", C.c_int32), ("ctrl_cost", C.c_double),
+                ("input_model", C.c_int32), ("pad3_", C.c_int32), ("rate_lim", C.c_double * 2),
+                ("dv_lim", C.c_double * 2)]
 
 
 class Warm(C.Structure):
     _fields_ = [("warm", C.c_int32), ("g0", C.c_int32), ("s", C.c_uint32), ("pad_", C.c_int32),
                 ("allow", C.c_uint32 * MASK_WORDS), ("t_prev", C.c_double),
                 ("x_prev", C.c_double * 13), ("theta0", C.c_double),
-                ("U", C.c_double * (NMAX * 4)), ("V", C.c_double * NMAX)]
+                ("U", C.c_double * (NMAX * 4)), ("V", C.c_double * NMAX), ("vtheta", C.c_double)]
 
 
 class Out(C.Structure):
@@ -103,6 +106,10 @@ def lib():
         L.orc_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _D]
         L.orc_f.argtypes = [C.POINTER(Quad), _D, _D, _D]
         L.orc_rk4.argtypes = [C.POINTER(Quad), _D, _D, C.c_double, _D]
+        L.orc_f_rate.argtypes = [C.POINTER(Quad), _D, _D, _D]
+        L.orc_rk4_rate.argtypes = [C.POINTER(Quad), _D, _D, C.c_double, _D]
+        L.orc_sample_rate.argtypes = [C.POINTER(Cfg), C.POINTER(Quad), _D, _D, C.c_uint32, C.c_uint32,
+                                      C.c_int, _D, C.c_double, _D, _D]
         L.orc_gate_cross.argtypes = [_D, _D, _D, C.c_double, _D]
         L.orc_gate_cross.restype = C.c_int
         L.orc_project.argtypes = [C.POINTER(Cfg), _D, C.c_double, C.c_int]
@@ -222,6 +229,14 @@ def rk4(quad: dict, x, T, dt):
     return xn
 
 
+def rk4_rate(quad: dict, x, Tdot, dt):
+    """One RK4 step of the paper's 17-state model (thrusts last), rate held."""
+    x = _arr(x, 17); Td = _arr(Tdot, 4); xn = np.zeros(17)
+    q = make_quad(quad)
+    lib().orc_rk4_rate(C.byref(q), _dp(x), _dp(Td), float(dt), _dp(xn))
+    return xn
+
+
 def gate_cross(pa, pb, gate, size):
     pa = _arr(pa, 3); pb = _arr(pb, 3); g = _arr(gate, 4); m = np.zeros(1)
     r = lib().orc_gate_cross(_dp(pa), _dp(pb), _dp(g), float(size), _dp(m))
@@ -254,6 +269,10 @@ class Problem:
         c.proj_window = prm.get("proj_window", 64)
         c.n_iter = prm.get("n_iter", 1)
         c.ctrl_cost = prm.get("ctrl_cost", 0.0)
+        c.input_model = prm.get("input_model", INPUT_THRUST)
+        c.rate_lim[:] = list(prm.get("rate_lim", (-10.0, 10.0)))
+        c.dv_lim[:] = list(prm.get("dv_lim", (-20.0, 20.0)))
+        self.nx = 17 if c.input_model == INPUT_RATE else 13
         self.gates = None if gates is None else _arr(gates).reshape(-1, 4).copy()
         self.path = None if path is None else _arr(path).reshape(-1, 6).copy()
         self.xref = None if xref is None else _arr(xref).reshape(-1, 13).copy()
@@ -275,6 +294,15 @@ class Problem:
         p = _arr(p, 3)
         return lib().orc_project(C.byref(self.cfg), _dp(p), float(theta_prev), int(global_search))
 
+    def sample_rate(self, Ustar, Vstar, m, s, T0, v0=0.0, noisy=True):
+        """Rate-model samples (clipped rates) of sample m from thrusts T0."""
+        N = self.cfg.N
+        Us = _arr(Ustar, 4 * N); Vs = _arr(Vstar, N); T0 = _arr(T0, 4)
+        U = np.zeros(4 * N); V = np.zeros(N)
+        lib().orc_sample_rate(C.byref(self.cfg), C.byref(self.quad), _dp(Us), _dp(Vs), int(m), int(s),
+                              1 if noisy else 0, _dp(T0), float(v0), _dp(U), _dp(V))
+        return U.reshape(N, 4), V
+
     def sample(self, Ustar, Vstar, m, s):
         N = self.cfg.N
         Us = _arr(Ustar, 4 * N); Vs = _arr(Vstar, N)
@@ -286,7 +314,7 @@ class Problem:
     def rollout_cost(self, x0, U, V=None, g0=0, allow=None, u_prev=None, v_prev=0.0, theta0=0.0,
                      i0=0, nominal=False):
         N = self.cfg.N
-        x0 = _arr(x0, 13); U = _arr(U, 4 * N)
+        x0 = _arr(x0, self.nx); U = _arr(U, 4 * N)
         V = _arr(np.zeros(N) if V is None else V, N)
         if allow is None:
             allow = [0xffffffff] * MASK_WORDS
@@ -351,7 +379,7 @@ class Problem:
         A = np.zeros(K)
         o.J = _dp(J); o.w = _dp(w); o.U = _dp(U); o.V = _dp(V); o.margin = _dp(mg); o.absJ = _dp(A)
         o.Ustar = _dp(Us); o.Vstar = _dp(Vs)
-        x0 = _arr(x0, 13)
+        x0 = _arr(x0, self.nx)
         jr = _arr(J_rep, K) if J_rep is not None else None
         rm = (np.ascontiguousarray(np.asarray(rep_mask, dtype=np.uint8))
               if rep_mask is not None else None)
