@@ -38,7 +38,7 @@ extern "C" {
 #define MPPI_K_MAX (1 << 24)      /* most samples per solve                   */
 #define MPPI_MASK_WORDS 9         /* (MPPI_N_MAX + 1) bits of per-state flags */
 #define MPPI_G_MAX 256            /* most gates of a gate track               */
-#define MPPI_REQ_DOUBLES 16       /* device request record, see mppi_solve_device */
+#define MPPI_REQ_DOUBLES 24       /* device request record, see mppi_solve_device */
 
 typedef struct mppi_ctx mppi_ctx;
 
@@ -52,6 +52,12 @@ typedef enum {
 
 enum { MPPI_OBJ_GATE = 0, MPPI_OBJ_CONTOUR = 1, MPPI_OBJ_TRACK = 2 };
 enum { MPPI_FP32 = 0, MPPI_FP64 = 1 };
+/* Input models.  MPPI_INPUT_THRUST: the four rotor thrusts are the input (13
+ * states).  MPPI_INPUT_RATE: the paper's model (Sec. III-A): the input is the
+ * thrusts' time derivative and the thrusts are four more states (17: the 13
+ * above, then T[4]); contouring then samples the progress acceleration and
+ * carries the progress speed as a state (Sec. IV-B-2, Eq. (9)). */
+enum { MPPI_INPUT_THRUST = 0, MPPI_INPUT_RATE = 1 };
 
 /* Quadrotor model of Eq. (2). */
 typedef struct {
@@ -106,6 +112,16 @@ typedef struct {
                              0: off.  A nonzero gamma needs the sample
                              tensor, so it switches the regenerating average
                              off.                                          */
+    /* Input model (MPPI_INPUT_*).  With MPPI_INPUT_RATE each sampled rate is
+     * clipped to rate_lim and then to the range that keeps its thrust within
+     * [t_min, t_max] over the step; the contouring acceleration likewise to
+     * dv_lim and to the range that keeps the progress speed within
+     * [0, v_max].  The rate model runs the one-wave rollout with a separate
+     * sampling kernel, and batches and servers refuse it. */
+    int32_t input_model;
+    int32_t pad_;
+    double rate_lim[2];   /* thrust-rate bounds, N/s (lower <= 0 <= upper)    */
+    double dv_lim[2];     /* progress-acceleration bounds, m/s^2 (contouring) */
 } mppi_params;
 
 /* The context allocates no per-solve workspace (sample tensor, costs,
@@ -182,7 +198,10 @@ typedef struct {
     double x_prev[13];                 /* state of the previous solve            */
     double theta0;                     /* previous arc length (contouring)       */
     double U[MPPI_N_MAX * 4];          /* previous solution, N x 4               */
-    double V[MPPI_N_MAX];              /* previous progress-speed solution, N    */
+    double V[MPPI_N_MAX];              /* previous progress-speed (rate model:
+                                          progress-acceleration) solution, N    */
+    double vtheta;                     /* rate model, contouring: progress speed
+                                          at the previous solve's time          */
 } mppi_warm;
 
 /* Create a solver context.  Validates every argument (K, N, dt, lambda, sigma,
@@ -209,7 +228,8 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad,
 void mppi_destroy(mppi_ctx *ctx);
 
 /* One MPPI step from host memory, synchronous on the context stream.
- * x0: current state (finite, |q| > 0).  t_now: time of x0 in s; the previous
+ * x0: current state (finite, |q| > 0): 13 doubles, or 17 for MPPI_INPUT_RATE
+ * (the measured rotor thrusts appended).  t_now: time of x0 in s; the previous
  * solution is shifted by max(1, round((t_now - t_prev)/dt)) steps and, for
  * tracking, the reference row round(t_now / ref_dt) is aligned with x0.
  * u0_out: 4 doubles, the first input of the new solution (required).
@@ -221,8 +241,9 @@ mppi_status mppi_solve(mppi_ctx *ctx, const double x0[13], double t_now, double 
 
 /* The same step driven entirely from device memory, asynchronous on the
  * context stream (nothing is copied to or from the host, nothing waits).
- * d_req: device pointer to MPPI_REQ_DOUBLES doubles, x0 in [0..12] and t_now
- * in [13] (the rest is ignored).  d_u0: device pointer receiving 4 doubles.
+ * d_req: device pointer to MPPI_REQ_DOUBLES doubles, x0 in [0..12], t_now in
+ * [13] and, for MPPI_INPUT_RATE, the measured rotor thrusts in [16..19] (the
+ * rest is ignored).  d_u0: device pointer receiving 4 doubles.
  * Both must stay valid until the stream reaches the end of the solve.  The
  * status and report of the solve are read later with mppi_read_info; a solve
  * whose costs are all non-finite leaves the warm-start state unchanged and
@@ -319,7 +340,8 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
 
 /* One MPPI step for the contexts active[0..n_active-1] (indices into the
  * registered list, distinct; NULL with n_active = n: all, in order).  Solve i
- * reads its request record (layout of mppi_solve_device) at d_reqs + 16 i and
+ * reads its request record (layout of mppi_solve_device) at
+ * d_reqs + MPPI_REQ_DOUBLES i and
  * writes its first input to d_u0s + 4 i; both are device pointers that must
  * stay valid until the stream reaches the end of the step.  Asynchronous. */
 mppi_status mppi_batch_solve_device(mppi_batch *b, const int32_t *active, int32_t n_active,
@@ -410,6 +432,15 @@ const char *mppi_last_error(const mppi_ctx *ctx);
 
 /* Static name of a status code. */
 const char *mppi_status_string(mppi_status s);
+
+/* Host FP64 plant step of the paper's rate model (Sec. III-A) for closed-loop
+ * simulation: x and x_out hold 17 states (the thrusts last), tdot the rotor
+ * thrust rates in N/s held over dt.  Each of the `substeps` equal sub-steps
+ * clips the rates to the range that keeps every thrust within [t_min, t_max]
+ * (the rotors saturate), integrates the 17-state system with RK4 and
+ * renormalises the quaternion.  x_out may alias x. */
+mppi_status mppi_plant_step_rate(const mppi_quad *quad, const double x[17], const double tdot[4],
+                                 double dt, int32_t substeps, double x_out[17]);
 
 /* Host FP64 plant step for closed-loop simulation (not part of a solve):
  * integrates Eq. (2) with RK4 over dt with the input held, using `substeps`

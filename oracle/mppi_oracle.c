@@ -660,11 +660,12 @@ static int solve_iteration(const orc_quad *q, const orc_cfg *c, orc_warm *warm, 
     }
     /* rate model, contouring: the progress speed state.  The previous solve's
      * initial speed advanced over the shift by its averaged accelerations
-     * (clamped to [0, v_max] at each step); an inner iteration keeps it. */
+     * (clamped to [0, v_max] at each step) and held beyond that solution's
+     * horizon; an inner iteration keeps it. */
     double v0 = 0.0;
     if (rate && warm->warm) {
         v0 = warm->vtheta;
-        for (int j = 0; j < shift; ++j) v0 = clampd(v0 + c->dt * warm->V[j < N ? j : N - 1], 0.0, c->v_max);
+        for (int j = 0; j < shift && j < N; ++j) v0 = clampd(v0 + c->dt * warm->V[j], 0.0, c->v_max);
     }
     if (rate) v_prev = v0;
     for (int i = 0; i < 4; ++i) u_used[i] = u_prev[i];

@@ -19,11 +19,13 @@ namespace mppi {
 constexpr int kNMax = 256;
 constexpr int kMaskWords = 9;   // (kNMax + 1) bits
 constexpr int kGMax = 256;      // most gates (the pipelined rollouts stage the table in LDS)
-constexpr int kReqDoubles = 16;
+constexpr int kReqDoubles = 24;    // x0[13], t_now, 2 spare, thrusts[4] (rate model), 4 spare
 constexpr int kFinalThreads = 1024;  // threads of a block of the weighted-average kernel
 constexpr size_t kScratchBytes = (size_t)32 << 20;  // fixed workspace of the allocation-free solve
 
 enum Objective { OBJ_GATE = 0, OBJ_CONTOUR = 1, OBJ_TRACK = 2 };
+enum InputModel { INPUT_THRUST = 0, INPUT_RATE = 1 };
+constexpr int kReqThrust = 16;      // request slots of the measured thrusts (rate model)
 enum Status { ST_OK = 0, ST_INVAL = -1, ST_NOMEM = -2, ST_DEVICE = -3, ST_NONFINITE = -4 };
 
 struct DevWarm {
@@ -34,7 +36,7 @@ struct DevWarm {
     int32_t pad0;
     double t_prev, theta0;
     double x_prev[13];
-    double pad1;
+    double vtheta;              // rate model, contouring: progress speed at the previous solve
 };
 
 struct DevCur {
@@ -71,6 +73,8 @@ struct KArgs {
     int32_t rollout_draw;       // 1: the one-wave rollout draws its samples (no sample kernel)
     int32_t inner;              // 1: an inner iteration of a control step (no shift, the first
                                 // iteration's last applied input)
+    int32_t input_model;        // INPUT_THRUST (13 states) or INPUT_RATE (thrust rates, 17 states)
+    int32_t pad2_;
     uint32_t seed_lo, seed_hi;
     // model
     double inv_mass, gravity, arm_s, c_tau;
@@ -82,6 +86,8 @@ struct KArgs {
     // costs
     double w_lim, q_near, r_near, gate_half;
     double ctrl_cost;           // gamma of the control-cost term (0: off)
+    double rate_lim[2];         // rate model: bounds of the sampled thrust rate, N/s
+    double dv_lim[2];           // rate model, contouring: bounds of the progress acceleration
     double inv_sig2[5];         // 1/sigma_i^2 of the four thrusts and the speed, 0 where sigma_i = 0
     double Q[13], QN[13], R_dT[4];
     double q_l, q_c, Q_w[3], r_dv, mu, v_max;

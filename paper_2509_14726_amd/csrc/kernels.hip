@@ -136,6 +136,18 @@ __device__ __forceinline__ int warm_shift(const KArgs &a, int warm, double t_now
     return solve_shift(warm, t_now, t_prev, a.dt);
 }
 
+// Rate model, contouring: the progress speed state at this solve's time, the
+// previous solve's initial speed advanced over the shift by its averaged
+// accelerations (clamped to [0, v_max] each step) and held beyond that
+// solution's horizon; 0 at a cold start.
+__device__ __forceinline__ double rate_speed0(const KArgs &a, const DevWarm *w, int warm, int shift)
+{
+    if (!warm) return 0.0;
+    double v = w->vtheta;
+    for (int j = 0; j < shift && j < a.N; ++j) v = clampT(v + a.dt * a.wV[j], 0.0, a.v_max);
+    return v;
+}
+
 // Run by all threads of one block (any size up to 512); h is in LDS.
 __device__ void compute_head(const KArgs &a, HeadVals &h)
 {
@@ -220,6 +232,8 @@ __device__ void compute_head(const KArgs &a, HeadVals &h)
         const bool same_step = a.inner && warm && w->t_prev == t_now;
         for (int i = 0; i < 4; ++i) h.u_prev[i] = same_step ? a.cur->u_prev[i] : (warm ? a.wU[i] : a.hover);
         h.v_prev = same_step ? a.cur->v_prev : (warm ? a.wV[0] : 0.0);
+        // the rate model carries the progress speed state in v_prev
+        if (a.input_model == INPUT_RATE) h.v_prev = rate_speed0(a, w, warm, h.shift);
         for (int i = 0; i < 13; ++i) h.x0[i] = a.req[i];
     }
     __syncthreads();
@@ -285,6 +299,53 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
 
     const int m = bx * 256 + threadIdx.x;
     const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max;
+    if (a.input_model == INPUT_RATE) {
+        // the paper's input: thrust rates clipped to their bounds and to the
+        // range that keeps each thrust within [t_min, t_max] over the step,
+        // following the thrust chain from the measured thrusts; contouring's
+        // progress acceleration likewise keeps the speed within [0, v_max].
+        // The chains are integrators and run in binary64 in every precision
+        // (their rounding would otherwise accumulate over the horizon).
+        if (m > K) return;
+        const bool noisy = m < K;
+        const Real rlo = (Real)a.rate_lim[0], rhi = (Real)a.rate_lim[1];
+        const Real dlo = (Real)a.dv_lim[0], dhi = (Real)a.dv_lim[1];
+        const Real sg[4] = {(Real)a.sigma[0], (Real)a.sigma[1], (Real)a.sigma[2], (Real)a.sigma[3]};
+        double T[4];
+        for (int i = 0; i < 4; ++i) T[i] = a.req[kReqThrust + i];
+        double v = rate_speed0(a, w, warm, shift);
+        for (int k = 0; k < N; ++k) {
+            const R4 us = s_us[k];
+            const Real ust[4] = {us.x, us.y, us.z, us.w};
+            Real z[4] = {Real(0), Real(0), Real(0), Real(0)};
+            if (noisy) {
+                const Normal4<Real> n4 = normals4<Real>((uint32_t)m, (uint32_t)k, s, 0u, a.seed_lo, a.seed_hi);
+                z[0] = n4.z0; z[1] = n4.z1; z[2] = n4.z2; z[3] = n4.z3;
+            }
+            Real u[4];
+            for (int i = 0; i < 4; ++i) {
+                const Real raw = noisy ? ust[i] + sg[i] * z[i] : ust[i];
+                const Real r = clampT(raw, rlo, rhi);
+                u[i] = (Real)clampT((double)r, (a.t_min - T[i]) / a.dt, (a.t_max - T[i]) / a.dt);
+                T[i] = T[i] + a.dt * (double)u[i];
+            }
+            R4 o;
+            o.x = u[0]; o.y = u[1]; o.z = u[2]; o.w = u[3];
+            if (noisy) ((R4 *)a.ctrl)[(size_t)k * (size_t)K + (size_t)m] = o;
+            else ((R4 *)a.nomU)[k] = o;
+            if (HAS_V) {
+                Real zv = Real(0);
+                if (noisy) zv = normal1<Real>((uint32_t)m, (uint32_t)k, s, 1u, a.seed_lo, a.seed_hi);
+                const Real raw = noisy ? s_vs[k] + (Real)a.sigma_v * zv : s_vs[k];
+                const Real r = clampT(raw, dlo, dhi);
+                const Real acc = (Real)clampT((double)r, (0.0 - v) / a.dt, (a.v_max - v) / a.dt);
+                v = v + a.dt * (double)acc;
+                if (noisy) ((Real *)a.vctrl)[(size_t)k * (size_t)K + (size_t)m] = acc;
+                else ((Real *)a.nomV)[k] = acc;
+            }
+        }
+        return;
+    }
     if (m == K) {  // the noise-free sample
         for (int k = 0; k < N; ++k) {
             const R4 us = s_us[k];
@@ -478,6 +539,15 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
             inv_ds = (Real)((double)a.P / a.path_len);
         }
 
+        // rate model: the thrust states and the progress speed state, carried
+        // in binary64 in every precision (integrators: in binary32 their
+        // rounding over the horizon reaches the attitude through the small
+        // inertia and the position through the attitude)
+        const bool rate = a.input_model == INPUT_RATE;
+        double T[4];
+        for (int i = 0; i < 4; ++i) T[i] = rate ? a.req[kReqThrust + i] : 0.0;
+        double vs = rate ? cur->v_prev : 0.0;
+
         R4 u;
         Real v = Real(0);
         input(0, u, v);
@@ -508,8 +578,13 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
                     const Real e = st.x[i] - xr[i];
                     term += (Real)a.Q[i] * e * e;
                 }
-                const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
-                term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                if (rate) {  // Eq. (8)'s u_k is the sampled thrust rate
+                    term += (Real)a.R_dT[0] * u.x * u.x + (Real)a.R_dT[1] * u.y * u.y + (Real)a.R_dT[2] * u.z * u.z +
+                            (Real)a.R_dT[3] * u.w * u.w;
+                } else {
+                    const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
+                    term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                }
             } else {  // contouring
                 const Real fl = floor(th_hi * inv_ds);
                 const Real f = ((th_hi - fl * ds) + th_lo) * inv_ds;
@@ -533,14 +608,28 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
                 term += (Real)a.Q_w[0] * st.x[10] * st.x[10] + (Real)a.Q_w[1] * st.x[11] * st.x[11] +
                         (Real)a.Q_w[2] * st.x[12] * st.x[12];
                 const Real vk = v;
-                const Real dv = vk - vp;
-                term += (Real)(a.r_dv / (a.dt * a.dt)) * dv * dv;
-                const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
-                term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
-                term -= (Real)a.mu * vk;
+                Real adv;  // arc length advanced over the step
+                if (rate) {
+                    // Eq. (9) with the progress acceleration as the input and
+                    // the speed as a state, which moves linearly over the step
+                    term += (Real)a.r_dv * vk * vk;
+                    term += (Real)a.R_dT[0] * u.x * u.x + (Real)a.R_dT[1] * u.y * u.y + (Real)a.R_dT[2] * u.z * u.z +
+                            (Real)a.R_dT[3] * u.w * u.w;
+                    term -= (Real)a.mu * (Real)vs;
+                    const double vsn = vs + a.dt * (double)vk;
+                    adv = (Real)(0.5 * a.dt * (vs + vsn));
+                    vs = vsn;
+                } else {
+                    const Real dv = vk - vp;
+                    term += (Real)(a.r_dv / (a.dt * a.dt)) * dv * dv;
+                    const Real d0 = u.x - up[0], d1 = u.y - up[1], d2 = u.z - up[2], d3 = u.w - up[3];
+                    term += rdt[0] * d0 * d0 + rdt[1] * d1 * d1 + rdt[2] * d2 * d2 + rdt[3] * d3 * d3;
+                    term -= (Real)a.mu * vk;
+                    adv = vk * dt;
+                }
                 vp = vk;
-                {   // theta_{k+1} = theta_k + V_k dt (mod L), compensated in binary32
-                    const Real y = vk * dt + th_lo;
+                {   // theta_{k+1} = theta_k + advance (mod L), compensated in binary32
+                    const Real y = adv + th_lo;
                     const Real t = th_hi + y;
                     th_lo = (sizeof(Real) == 4) ? y - (t - th_hi) : Real(0);
                     th_hi = t;
@@ -549,9 +638,22 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
             }
 
             // ---- dynamics
-            const StepInput<Real> in = step_input(M, u.x, u.y, u.z, u.w);
             Real dx[13];
-            rk4_increment(M, in, st.x, dt, dx);
+            if (rate) {
+                // the thrusts move linearly over the step: RK4 of the 17-state
+                // system sees them at the start, middle and end of the step
+                const double h = 0.5 * a.dt, ur[4] = {(double)u.x, (double)u.y, (double)u.z, (double)u.w};
+                const StepInput<Real> in1 = step_input(M, (Real)T[0], (Real)T[1], (Real)T[2], (Real)T[3]);
+                const StepInput<Real> in2 = step_input(M, (Real)(T[0] + h * ur[0]), (Real)(T[1] + h * ur[1]),
+                                                       (Real)(T[2] + h * ur[2]), (Real)(T[3] + h * ur[3]));
+                const StepInput<Real> in4 = step_input(M, (Real)(T[0] + a.dt * ur[0]), (Real)(T[1] + a.dt * ur[1]),
+                                                       (Real)(T[2] + a.dt * ur[2]), (Real)(T[3] + a.dt * ur[3]));
+                rk4_increment_stages(M, in1, in2, in4, st.x, dt, dx);
+                for (int i = 0; i < 4; ++i) T[i] += a.dt * ur[i];
+            } else {
+                const StepInput<Real> in = step_input(M, u.x, u.y, u.z, u.w);
+                rk4_increment(M, in, st.x, dt, dx);
+            }
             commit(st, dx);
 
             // ---- progress and switching (gate)
@@ -2177,7 +2279,7 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     const bool fr_last = head && gate && tid == 0 && N >= 256 && a.front8[256] != 0;
     // (spread over the lanes of wave 0: lane 5 the report's head fields,
     // lane 6 the warm-start fields, lanes 7..19 one state component each)
-    double rep_Jnom = 0.0, rep_theta0 = 0.0, rep_t = 0.0, rep_x = 0.0;
+    double rep_Jnom = 0.0, rep_theta0 = 0.0, rep_t = 0.0, rep_x = 0.0, rep_v = 0.0;
     int32_t rep_g0 = 0, rep_i0 = 0, rep_shift = 0;
     uint32_t rep_s = 0;
     if (head && (tid == 5 || tid == 6)) {
@@ -2188,6 +2290,7 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
         rep_i0 = cur->i0;
         rep_shift = cur->shift;
         rep_s = cur->s;
+        rep_v = cur->v_prev;
     }
     if (head && tid >= 7 && tid < 20) rep_x = cur->x0[tid - 7];
     // J_min within each wave (a minimum does not depend on the grouping, so
@@ -2306,6 +2409,8 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
         w->N = N;
         w->t_prev = rep_t;
         w->theta0 = rep_theta0;
+        // rate model: the progress speed state of this solve
+        w->vtheta = a.input_model == INPUT_RATE ? rep_v : 0.0;
     } else if (tid >= 7 && tid < 20 && ok) {
         w->x_prev[tid - 7] = rep_x;
     }

@@ -145,4 +145,38 @@ __device__ __forceinline__ void rk4_increment(const Model<Real> &M, const StepIn
     for (int i = 0; i < 13; ++i) dx[i] = dt6 * (dx[i] + k[i]);
 }
 
+// The same for the rate model: the thrusts move linearly over the step, so
+// the stages see the inputs in1 (start), in2 (middle, stages 2 and 3) and in4
+// (end of the step).
+template <typename Real>
+__device__ __forceinline__ void rk4_increment_stages(const Model<Real> &M, const StepInput<Real> &in1,
+                                                     const StepInput<Real> &in2, const StepInput<Real> &in4,
+                                                     const Real *x, Real dt, Real *dx)
+{
+    Real k[13], xs[13];
+    const Real h2 = Real(0.5) * dt;
+    deriv(M, in1, x, k);
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        dx[i] = k[i];
+        xs[i] = x[i] + h2 * k[i];
+    }
+    deriv(M, in2, xs, k);
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        dx[i] += Real(2) * k[i];
+        xs[i] = x[i] + h2 * k[i];
+    }
+    deriv(M, in2, xs, k);
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        dx[i] += Real(2) * k[i];
+        xs[i] = x[i] + dt * k[i];
+    }
+    deriv(M, in4, xs, k);
+    const Real dt6 = dt / Real(6);
+#pragma unroll
+    for (int i = 0; i < 13; ++i) dx[i] = dt6 * (dx[i] + k[i]);
+}
+
 }  // namespace mppi

@@ -143,6 +143,12 @@ static mppi_status validate(const mppi_params *p, const mppi_quad *q, const mppi
     if (p->n_iter < 0 || p->n_iter > 64) return fail(nullptr, MPPI_E_INVAL, "n_iter=%d outside [0, 64]", p->n_iter);
     if (!(p->ctrl_cost >= 0.0) || !isfinite(p->ctrl_cost))
         return fail(nullptr, MPPI_E_INVAL, "ctrl_cost must be finite and >= 0");
+    if (p->input_model != MPPI_INPUT_THRUST && p->input_model != MPPI_INPUT_RATE)
+        return fail(nullptr, MPPI_E_INVAL, "unknown input model %d", p->input_model);
+    if (p->input_model == MPPI_INPUT_RATE &&
+        (!finite_all(p->rate_lim, 2) || !finite_all(p->dv_lim, 2) || !(p->rate_lim[0] <= 0.0) ||
+         !(p->rate_lim[1] >= 0.0) || !(p->dv_lim[0] <= 0.0) || !(p->dv_lim[1] >= 0.0)))
+        return fail(nullptr, MPPI_E_INVAL, "rate model bounds must be finite with lower <= 0 <= upper");
     const double sc[] = {p->w_lim, p->q_near, p->r_near, p->q_l, p->q_c, p->r_dv, p->mu, p->v_max};
     if (!finite_all(sc, 8) || !finite_all(p->Q, 13) || !finite_all(p->QN, 13) || !finite_all(p->R_dT, 4) ||
         !finite_all(p->Q_w, 3))
@@ -306,11 +312,15 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.gyro[1] = (q.inertia[0] - q.inertia[2]) / q.inertia[1];
     a.gyro[2] = (q.inertia[1] - q.inertia[0]) / q.inertia[2];
     a.t_min = q.t_min; a.t_max = q.t_max; a.w_max = q.w_max;
-    a.hover = q.mass * q.gravity / 4.0;
+    // cold-start nominal: hover thrust for the thrust input; for the rate
+    // input the zero sequence of Alg. 1, which holds the measured thrusts
+    a.hover = p.input_model == MPPI_INPUT_RATE ? 0.0 : q.mass * q.gravity / 4.0;
     a.dt = p.dt; a.lambda = p.lambda;
     for (int i = 0; i < 4; ++i) { a.sigma[i] = p.sigma[i]; a.R_dT[i] = p.R_dT[i]; }
     a.sigma_v = p.sigma_v;
     a.ctrl_cost = p.ctrl_cost;
+    a.input_model = p.input_model;
+    for (int i = 0; i < 2; ++i) { a.rate_lim[i] = p.rate_lim[i]; a.dv_lim[i] = p.dv_lim[i]; }
     for (int i = 0; i < 4; ++i) a.inv_sig2[i] = p.sigma[i] > 0.0 ? 1.0 / (p.sigma[i] * p.sigma[i]) : 0.0;
     a.inv_sig2[4] = p.sigma_v > 0.0 ? 1.0 / (p.sigma_v * p.sigma_v) : 0.0;
     c->n_iter = p.n_iter > 1 ? p.n_iter : 1;
@@ -323,6 +333,12 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.path_len = problem->path_len;
     a.ref_dt = problem->ref_dt;
     plan_layout(c);
+    if (p.input_model == MPPI_INPUT_RATE) {
+        // a rate sample follows its thrust chain along the horizon, which the
+        // sampling kernel walks per sample: the one-wave rollout reads it
+        a.rollout_waves = 1;
+        a.rollout_draw = 0;
+    }
 
     const size_t rs = c->fp64 ? sizeof(double) : sizeof(float);
     a.C = c->C;
@@ -512,14 +528,18 @@ mppi_status mppi_solve(mppi_ctx *ctx, const double x0[13], double t_now, double 
 {
     if (!ctx) return fail(nullptr, MPPI_E_INVAL, "ctx is NULL");
     if (!x0 || !u0_out) return fail(ctx, MPPI_E_INVAL, "x0 and u0_out are required");
-    if (!finite_all(x0, 13) || !isfinite(t_now)) return fail(ctx, MPPI_E_INVAL, "x0 and t_now must be finite");
+    const bool rate = ctx->args.input_model == MPPI_INPUT_RATE;
+    if (!finite_all(x0, rate ? 17 : 13) || !isfinite(t_now))
+        return fail(ctx, MPPI_E_INVAL, "x0 and t_now must be finite");
     if (ctx->external_ws) return fail(ctx, MPPI_E_INVAL, "context has no workspace of its own (server context)");
     const double qn = x0[6] * x0[6] + x0[7] * x0[7] + x0[8] * x0[8] + x0[9] * x0[9];
     if (!(qn > 0.0)) return fail(ctx, MPPI_E_INVAL, "quaternion of x0 has zero norm");
     ctx->err.clear();
+    for (int i = 0; i < kReqDoubles; ++i) ctx->h_req[i] = 0.0;
     for (int i = 0; i < 13; ++i) ctx->h_req[i] = x0[i];
     ctx->h_req[13] = t_now;
-    ctx->h_req[14] = ctx->h_req[15] = 0.0;
+    if (rate)
+        for (int i = 0; i < 4; ++i) ctx->h_req[kReqThrust + i] = x0[13 + i];
     HIP_TRY(ctx, hipMemcpyAsync(ctx->req, ctx->h_req, sizeof(double) * kReqDoubles, hipMemcpyHostToDevice,
                                 ctx->stream));
     KArgs a = ctx->args;
@@ -595,6 +615,7 @@ mppi_status mppi_get_warm(mppi_ctx *ctx, mppi_warm *out)
     out->t_prev = w.t_prev;
     memcpy(out->x_prev, w.x_prev, sizeof w.x_prev);
     out->theta0 = w.theta0;
+    out->vtheta = w.vtheta;
     return MPPI_OK;
 }
 
@@ -605,7 +626,7 @@ mppi_status mppi_set_warm(mppi_ctx *ctx, const mppi_warm *in)
     if (ctx->objective == MPPI_OBJ_GATE && (in->g0 < 0 || in->g0 >= ctx->G))
         return fail(ctx, MPPI_E_INVAL, "g0=%d outside [0, %d)", in->g0, ctx->G);
     if (!finite_all(in->U, 4 * ctx->N) || !finite_all(in->V, ctx->N) || !finite_all(in->x_prev, 13) ||
-        !isfinite(in->t_prev) || !isfinite(in->theta0))
+        !isfinite(in->t_prev) || !isfinite(in->theta0) || !isfinite(in->vtheta))
         return fail(ctx, MPPI_E_INVAL, "warm state must be finite");
     DevWarm w;
     memset(&w, 0, sizeof w);
@@ -617,6 +638,7 @@ mppi_status mppi_set_warm(mppi_ctx *ctx, const mppi_warm *in)
     w.t_prev = in->t_prev;
     memcpy(w.x_prev, in->x_prev, sizeof w.x_prev);
     w.theta0 = in->theta0;
+    w.vtheta = in->vtheta;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     HIP_TRY(ctx, hipMemcpy(ctx->warm, &w, sizeof w, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(ctx->args.wU, in->U, sizeof(double) * 4 * kNMax, hipMemcpyHostToDevice));
@@ -670,6 +692,39 @@ mppi_status mppi_plant_step(const mppi_quad *quad, const double x[13], const dou
         for (int i = 0; i < 13; ++i) t[i] = s[i] + h * k3[i];
         plant_deriv(quad, t, u, k4);
         for (int i = 0; i < 13; ++i) s[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+        const double nq = sqrt(s[6] * s[6] + s[7] * s[7] + s[8] * s[8] + s[9] * s[9]);
+        for (int i = 6; i < 10; ++i) s[i] /= nq;
+    }
+    memcpy(x_out, s, sizeof s);
+    return MPPI_OK;
+}
+
+mppi_status mppi_plant_step_rate(const mppi_quad *quad, const double x[17], const double tdot[4], double dt,
+                                 int32_t substeps, double x_out[17])
+{
+    if (!quad || !x || !tdot || !x_out || substeps < 1 || !(dt > 0.0))
+        return fail(nullptr, MPPI_E_INVAL, "invalid plant step arguments");
+    double s[17], k1[17], k2[17], k3[17], k4[17], t[17], r[4];
+    memcpy(s, x, sizeof s);
+    const double h = dt / substeps;
+    for (int n = 0; n < substeps; ++n) {
+        // the rotors saturate: a rate may not carry a thrust past its bounds
+        for (int i = 0; i < 4; ++i) {
+            const double lo = (quad->t_min - s[13 + i]) / h, hi = (quad->t_max - s[13 + i]) / h;
+            r[i] = tdot[i] < lo ? lo : (tdot[i] > hi ? hi : tdot[i]);
+        }
+        plant_deriv(quad, s, s + 13, k1);
+        for (int i = 0; i < 4; ++i) k1[13 + i] = r[i];
+        for (int i = 0; i < 17; ++i) t[i] = s[i] + 0.5 * h * k1[i];
+        plant_deriv(quad, t, t + 13, k2);
+        for (int i = 0; i < 4; ++i) k2[13 + i] = r[i];
+        for (int i = 0; i < 17; ++i) t[i] = s[i] + 0.5 * h * k2[i];
+        plant_deriv(quad, t, t + 13, k3);
+        for (int i = 0; i < 4; ++i) k3[13 + i] = r[i];
+        for (int i = 0; i < 17; ++i) t[i] = s[i] + h * k3[i];
+        plant_deriv(quad, t, t + 13, k4);
+        for (int i = 0; i < 4; ++i) k4[13 + i] = r[i];
+        for (int i = 0; i < 17; ++i) s[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
         const double nq = sqrt(s[6] * s[6] + s[7] * s[7] + s[8] * s[8] + s[9] * s[9]);
         for (int i = 6; i < 10; ++i) s[i] /= nq;
     }
@@ -811,9 +866,9 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d is NULL", i);
         if (ctxs[i]->fp64 != ctxs[0]->fp64) return bfail(nullptr, MPPI_E_INVAL, "contexts differ in precision");
-        if (ctxs[i]->n_iter != 1 || ctxs[i]->args.ctrl_cost != 0.0)
-            return bfail(nullptr, MPPI_E_INVAL, "context %d: batches run one iteration without the control-cost term",
-                         i);
+        if (ctxs[i]->n_iter != 1 || ctxs[i]->args.ctrl_cost != 0.0 || ctxs[i]->args.input_model != MPPI_INPUT_THRUST)
+            return bfail(nullptr, MPPI_E_INVAL,
+                         "context %d: batches run the thrust input, one iteration, no control-cost term", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d registered twice", i);
     }
@@ -1292,9 +1347,10 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
     for (int i = 0; i < n; ++i) {
         if (!drones[i] || !drones[i]->external_ws)
             return sfail(nullptr, MPPI_E_INVAL, "drone %d: context must be created with MPPI_FLAG_EXTERNAL_WORKSPACE", i);
-        if (drones[i]->n_iter != 1 || drones[i]->args.ctrl_cost != 0.0)
-            return sfail(nullptr, MPPI_E_INVAL, "drone %d: served solves run one iteration without the control-cost term",
-                         i);
+        if (drones[i]->n_iter != 1 || drones[i]->args.ctrl_cost != 0.0 ||
+            drones[i]->args.input_model != MPPI_INPUT_THRUST)
+            return sfail(nullptr, MPPI_E_INVAL,
+                         "drone %d: served solves run the thrust input, one iteration, no control-cost term", i);
     }
     mppi_server *s = new (std::nothrow) mppi_server();
     if (!s) return sfail(nullptr, MPPI_E_NOMEM, "host allocation failed");

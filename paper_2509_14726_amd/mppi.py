@@ -19,16 +19,19 @@ N_MAX = 256
 K_MAX = 1 << 24
 G_MAX = 256
 MASK_WORDS = 9
-REQ_DOUBLES = 16
+REQ_DOUBLES = 24
+REQ_THRUST = 16      # request slots of the measured thrusts (rate model)
 SCRATCH_BYTES = 32 << 20
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NONFINITE = 0, -1, -2, -3, -4
 OBJ_GATE, OBJ_CONTOUR, OBJ_TRACK = 0, 1, 2
 FP32, FP64 = 0, 1
+INPUT_THRUST, INPUT_RATE = 0, 1
 
 EXPORTS = ["mppi_create", "mppi_destroy", "mppi_solve", "mppi_solve_device",
            "mppi_solve_device_noalloc", "mppi_read_info",
            "mppi_read_samples", "mppi_get_warm", "mppi_set_warm", "mppi_last_error",
-           "mppi_status_string", "mppi_plant_step", "mppi_set_profiling", "mppi_read_profile",
+           "mppi_status_string", "mppi_plant_step", "mppi_plant_step_rate", "mppi_set_profiling",
+           "mppi_read_profile",
            "mppi_batch_create", "mppi_batch_solve_device", "mppi_batch_set_cfg", "mppi_batch_get_cfg",
            "mppi_batch_autotune", "mppi_batch_destroy", "mppi_batch_last_error",
            "mppi_server_create", "mppi_server_submit", "mppi_server_progress", "mppi_server_poll",
@@ -56,7 +59,8 @@ class mppi_params(C.Structure):
                 ("q_l", C.c_double), ("q_c", C.c_double), ("Q_w", C.c_double * 3),
                 ("r_dv", C.c_double), ("mu", C.c_double), ("v_max", C.c_double),
                 ("proj_window", C.c_int32), ("flags", C.c_int32), ("n_iter", C.c_int32),
-                ("ctrl_cost", C.c_double)]
+                ("ctrl_cost", C.c_double), ("input_model", C.c_int32), ("pad_", C.c_int32),
+                ("rate_lim", C.c_double * 2), ("dv_lim", C.c_double * 2)]
 
 
 FLAG_EXTERNAL_WORKSPACE = 1
@@ -93,7 +97,7 @@ class mppi_warm(C.Structure):
     _fields_ = [("warm", C.c_int32), ("g0", C.c_int32), ("solve_index", C.c_uint32),
                 ("N", C.c_int32), ("allow", C.c_uint32 * MASK_WORDS), ("t_prev", C.c_double),
                 ("x_prev", C.c_double * 13), ("theta0", C.c_double),
-                ("U", C.c_double * (N_MAX * 4)), ("V", C.c_double * N_MAX)]
+                ("U", C.c_double * (N_MAX * 4)), ("V", C.c_double * N_MAX), ("vtheta", C.c_double)]
 
 
 class mppi_batch_cfg(C.Structure):
@@ -166,6 +170,8 @@ def _load():
     L.mppi_status_string.restype = C.c_char_p
     L.mppi_plant_step.argtypes = [C.POINTER(mppi_quad), _D, _D, C.c_double, C.c_int32, _D]
     L.mppi_plant_step.restype = C.c_int
+    L.mppi_plant_step_rate.argtypes = [C.POINTER(mppi_quad), _D, _D, C.c_double, C.c_int32, _D]
+    L.mppi_plant_step_rate.restype = C.c_int
     L.mppi_set_profiling.argtypes = [_P, C.c_int32]
     L.mppi_set_profiling.restype = C.c_int
     L.mppi_read_profile.argtypes = [_P, _D, C.POINTER(C.c_int32)]
@@ -242,6 +248,9 @@ def make_params(p: dict, precision: int) -> mppi_params:
     s.flags = p.get("flags", 0)
     s.n_iter = p.get("n_iter", 1)
     s.ctrl_cost = p.get("ctrl_cost", 0.0)
+    s.input_model = p.get("input_model", INPUT_THRUST)
+    s.rate_lim[:] = list(p.get("rate_lim", (-10.0, 10.0)))
+    s.dv_lim[:] = list(p.get("dv_lim", (-20.0, 20.0)))
     return s
 
 
@@ -287,6 +296,7 @@ class Solver:
         self.N = params["N"]
         self.K = params["K"]
         self.objective = params["objective"]
+        self.nx = 17 if params.get("input_model", INPUT_THRUST) == INPUT_RATE else 13
         self._quad = make_quad(quad)
         self._prm = make_params(params, precision)
         pb = mppi_problem()
@@ -320,7 +330,8 @@ class Solver:
             pass
 
     def solve(self, x0, t_now: float = 0.0, want_U: bool = True):
-        x = _f64(x0, 13)
+        """x0: 13 states, 17 for the rate model (the thrusts last)."""
+        x = _f64(x0, self.nx)
         u0 = np.zeros(4)
         U = np.zeros((self.N, 4)) if want_U else None
         info = mppi_info()
@@ -369,6 +380,14 @@ def plant_step(quad: dict, x, u, dt: float, substeps: int = 1):
     q = make_quad(quad)
     x = _f64(x, 13); u = _f64(u, 4); out = np.zeros(13)
     _check(lib.mppi_plant_step(C.byref(q), _dp(x), _dp(u), float(dt), int(substeps), _dp(out)))
+    return out
+
+
+def plant_step_rate(quad: dict, x, tdot, dt: float, substeps: int = 1):
+    """The rate model's host plant: 17 states, thrust rates held over dt."""
+    q = make_quad(quad)
+    x = _f64(x, 17); u = _f64(tdot, 4); out = np.zeros(17)
+    _check(lib.mppi_plant_step_rate(C.byref(q), _dp(x), _dp(u), float(dt), int(substeps), _dp(out)))
     return out
 
 

@@ -69,20 +69,26 @@ def warm_to_oracle(wd: M.mppi_warm, orc: O.Problem) -> O.Warm:
     o.theta0 = wd.theta0
     o.U[:] = list(wd.U)
     o.V[:] = list(wd.V)
+    o.vtheta = wd.vtheta
     return o
 
 
-def sensitivity_bound(orc: O.Problem, ref: dict, dJ, s: int):
+def sensitivity_bound(orc: O.Problem, ref: dict, dJ, s: int, x0=None, v0: float = 0.0):
     """First-order change of Eq. (5) under per-sample cost errors dJ:
     (1/lambda) sum_m w_m |dJ_m| |U^m - U|, N x 4, with the oracle's weights
-    and samples (U^m drawn again by the oracle's own sampler)."""
+    and samples (U^m drawn again by the oracle's own sampler; the rate model
+    follows the thrust chain from x0's thrusts and the speed v0)."""
+    rate = orc.cfg.input_model == O.INPUT_RATE
     lam = orc.cfg.lam
     contrib = ref["w"] * np.abs(dJ)
     B = np.zeros((orc.cfg.N, 4))
     if not (contrib > 0).any():
         return B
     for m in np.nonzero(contrib > 1e-9 * contrib.max())[0]:
-        Um, _ = orc.sample(ref["Ustar"], ref["Vstar"], int(m), s)
+        if rate:
+            Um, _ = orc.sample_rate(ref["Ustar"], ref["Vstar"], int(m), s, np.asarray(x0)[13:17], v0)
+        else:
+            Um, _ = orc.sample(ref["Ustar"], ref["Vstar"], int(m), s)
         B += contrib[m] * np.abs(Um - ref["U"])
     return B / lam
 
@@ -169,7 +175,7 @@ def compare_result(orc: O.Problem, wd: M.mppi_warm, x0, t_now: float, precision:
     if e2e > tol:
         assert not strict_e2e, f"end-to-end controls off by {e2e:.3e} at the benchmark parameters"
         dJ = np.where(finite & ~amb, Jd - r["J"], 0.0)
-        B = sensitivity_bound(orc, ref_e2e, dJ, wd.solve_index)
+        B = sensitivity_bound(orc, ref_e2e, dJ, wd.solve_index + n_iter - 1, x0=x0, v0=ow.vtheta)
         bound = float((B / scale_U).max())
         excess = dU - (tol * scale_U + 2.0 * B)
         assert (excess <= 0).all(), (f"end-to-end controls off by {e2e:.3e}, beyond 1e-4 plus twice the "
@@ -194,6 +200,13 @@ def compare_result(orc: O.Problem, wd: M.mppi_warm, x0, t_now: float, precision:
             (info["J_nom"], r["J_nom"], r["absJ_nom"])
     if cfg.objective == O.OBJ_CONTOUR:
         assert abs(info["theta0"] - r["theta0"]) <= 1e-9 * max(cfg.path_len, 1.0)
+        if wn is not None:
+            # the averaged progress speeds (thrust model) or accelerations
+            # (rate model) handed on, and the rate model's speed state
+            Vd = np.array(wn.V[:cfg.N])
+            err_V = np.abs(Vd - ref["V"]) / np.maximum(np.abs(ref["V"]), max(cfg.sigma_v, 1e-300))
+            assert err_V.max() <= tol, f"progress inputs off by {err_V.max():.3e}"
+            assert abs(wn.vtheta - ow.vtheta) <= 1e-12 * max(abs(ow.vtheta), cfg.v_max), (wn.vtheta, ow.vtheta)
     if wn is not None:
         assert wn.warm == 1 and wn.g0 == r["g0"] and wn.solve_index == wd.solve_index + n_iter
         # the pass mask handed on: bits whose nominal state lies within eps of

@@ -34,8 +34,14 @@ def test_struct_sizes_match_header_layout():
     # sizes implied by the C declarations (x86-64 ABI)
     assert C.sizeof(M.mppi_quad) == 8 * 13
     assert C.sizeof(M.mppi_info) == 5 * 8 + 8 * 4
-    assert C.sizeof(M.mppi_warm) == 4 * 4 + 9 * 4 + 4 + 8 + 13 * 8 + 8 + 256 * 4 * 8 + 256 * 8
+    assert C.sizeof(M.mppi_warm) == 4 * 4 + 9 * 4 + 4 + 8 + 13 * 8 + 8 + 256 * 4 * 8 + 256 * 8 + 8
     assert M.mppi_params.R_dT.offset == 4 * 4 + 8 * 2 + 8 * 4 + 8 + 8 + 8 * 3 + 13 * 8 * 2
+    # the variants and the input model follow the flags
+    off = M.mppi_params.flags.offset + 4
+    assert M.mppi_params.n_iter.offset == off and M.mppi_params.ctrl_cost.offset == off + 8  # padded to 8
+    assert M.mppi_params.input_model.offset == off + 16 and M.mppi_params.rate_lim.offset == off + 24
+    assert C.sizeof(M.mppi_params) == off + 24 + 32
+    assert M.REQ_DOUBLES == 24 and M.REQ_THRUST == 16
 
 
 def test_status_strings():
@@ -47,7 +53,8 @@ def test_status_strings():
 @pytest.mark.parametrize("over,frag", [
     (dict(K=0), "K=0"), (dict(N=0), "N=0"), (dict(N=257), "N=257"), (dict(dt=0.0), "dt"),
     (dict(**{"lambda": -1.0}), "lambda"), (dict(sigma=(1.0, -1.0, 1.0, 1.0)), "sigma[1]"),
-    (dict(objective=7), "objective"),
+    (dict(objective=7), "objective"), (dict(n_iter=65), "n_iter"), (dict(ctrl_cost=-1.0), "ctrl_cost"),
+    (dict(input_model=5), "input model"), (dict(input_model=1, rate_lim=(1.0, 10.0)), "bounds"),
 ])
 def test_create_rejects_invalid_parameters_before_touching_the_device(over, frag):
     w = synth.single_solve_workload(K=64, N=10)
@@ -151,3 +158,25 @@ def test_allocator_needs_both_callbacks():
     out = C.c_void_p()
     st = M.lib.mppi_create(C.byref(prm), C.byref(quad), C.byref(pb), None, C.byref(al), C.byref(out))
     assert st == M.E_INVAL and out.value is None
+
+
+def test_rate_plant_reduces_to_the_thrust_plant_and_saturates():
+    """mppi_plant_step_rate (host, binary64): a zero rate is the thrust
+    plant at the held thrusts; a rate that would carry a thrust past its
+    bound stops it there; the closed-form cubic climb of a thrust ramp."""
+    import numpy as np
+    q = synth.QUAD
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.normal(size=6), [1.0, 0.0, 0.0, 0.0], rng.normal(size=3), rng.uniform(1, 6, 4)])
+    xr = M.plant_step_rate(q, x, np.zeros(4), 0.02, 4)
+    np.testing.assert_array_equal(xr[:13], M.plant_step(q, x[:13], x[13:], 0.02, 4))
+    np.testing.assert_array_equal(xr[13:], x[13:])
+    x[13:] = [6.9, 0.1, 3.0, 3.0]
+    xr = M.plant_step_rate(q, x, np.array([50.0, -50.0, 1.0, -1.0]), 0.02, 4)
+    np.testing.assert_allclose(xr[13:], [q["t_max"], q["t_min"], 3.02, 2.98], rtol=0, atol=1e-12)
+    T0, r, t = 1.7, 3.0, 0.4
+    x = np.array([0, 0, 1.0, 0, 0, 0.5, 1, 0, 0, 0, 0, 0, 0, T0, T0, T0, T0], float)
+    xr = M.plant_step_rate(q, x, np.full(4, r), t, 40)
+    m, g = q["mass"], q["gravity"]
+    z = 1.0 + 0.5 * t + (4 * T0 / m - g) * t * t / 2 + (4 * r / m) * t ** 3 / 6
+    assert abs(xr[2] - z) < 1e-12
