@@ -28,11 +28,13 @@ def fly(solve, quad: dict, x0, steps: int, dt: float, substeps: int = 4) -> dict
     """Close the loop for `steps` control steps of length dt.
 
     solve(x, t) returns (u0, info) for state x at time t; the plant then
-    advances x by dt with u0 held (RK4, `substeps` substeps).  Returns the
-    times t[0..S], states X[0..S] (13 each), inputs U[0..S-1] and the solve
+    advances x by dt with u0 held (RK4, `substeps` substeps).  A 17-component
+    state is the rate input model's (the four thrusts last, u0 their rates).
+    Returns the times t[0..S], states X[0..S], inputs U[0..S-1] and the solve
     reports, S = the number of completed steps (fewer than `steps` when a
     solve raised; `error` then holds its message)."""
     x = np.asarray(x0, dtype=np.float64).copy()
+    plant = M.plant_step_rate if x.size == 17 else M.plant_step
     ts, xs, us, infos = [0.0], [x.copy()], [], []
     error = None
     for i in range(steps):
@@ -43,7 +45,7 @@ def fly(solve, quad: dict, x0, steps: int, dt: float, substeps: int = 4) -> dict
             error = str(e)
             break
         u0 = np.asarray(u0, dtype=np.float64)
-        x = M.plant_step(quad, x, u0, dt, substeps)
+        x = plant(quad, x, u0, dt, substeps)
         ts.append(t + dt)
         xs.append(x.copy())
         us.append(u0.copy())
@@ -150,7 +152,9 @@ def score(flight: dict, w: dict, objective: str) -> dict:
     out = {"pass_error_m_mean": float(pe.mean()), "pass_error_m_max": float(pe.max()),
            "gates_passed_in_order": lp["gates_passed"], "lap_time_s": lp["lap_time"],
            "flight_time_s": float(t[-1])}
-    out.update(thrust_profile(flight["U"], w["quad"]["t_min"], w["quad"]["t_max"]))
+    # the thrusts: the inputs, or the states of the rate model after each step
+    T = flight["X"][1:, 13:17] if flight["X"].shape[1] == 17 else flight["U"]
+    out.update(thrust_profile(T, w["quad"]["t_min"], w["quad"]["t_max"]))
     if objective == "track":
         out["tracking_rmse_m"] = tracking_rmse(P, t, w["xref"], w["ref_dt"])
     return out

@@ -65,6 +65,21 @@ def random_track(seed: int, n_gates: int = 7, box=(30.0, 30.0, 5.0), z0: float =
     return np.array(gates)
 
 
+def loop_track(seed: int, n_gates: int = 7, radius=(9.0, 14.0), height=(1.5, 4.0)) -> np.ndarray:
+    """G x 4 gates of a closed circuit: centres at jittered angles around the
+    origin (radius and height uniform in the given ranges), each gate facing
+    along the closed spline through the centres, so that flying the spline
+    passes every gate front to back."""
+    rng = np.random.default_rng(seed)
+    step = 2.0 * math.pi / n_gates
+    ang = np.arange(n_gates) * step + rng.uniform(-0.25 * step, 0.25 * step, n_gates)
+    r = rng.uniform(radius[0], radius[1], n_gates)
+    c = np.column_stack([r * np.cos(ang), r * np.sin(ang), rng.uniform(height[0], height[1], n_gates)])
+    sp, _ = _periodic_spline(c)
+    d = sp(sp.x[:-1], 1)
+    return np.column_stack([c, np.arctan2(d[:, 1], d[:, 0])])
+
+
 def start_state(gates: np.ndarray, back: float = 2.0) -> np.ndarray:
     """Hover `back` metres in front of gate 0, facing through it."""
     c, yaw = gates[0, :3], gates[0, 3]
@@ -162,6 +177,23 @@ def single_solve_workload(K: int = 1024, N: int = 50, seed: int = 1, track_seed:
         w.update(path=path, path_len=L)
     if objective == "track":
         w.update(xref=reference_table(gates, dt=dt, n_rows=1000 + N + 1), ref_dt=dt)
+    return w
+
+
+def race_workload(K: int = 8192, N: int = 20, objective: str = "gate", seed: int = 1, track_seed: int = 1,
+                  n_gates: int = 7, dt: float = 0.03, steps: int = 1000, **over) -> dict:
+    """A closed-loop race on a seeded circuit (`loop_track`): the solver's
+    parameters, the start 2 m in front of gate 0, and for contouring and
+    tracking the path table and the 5 m/s reference of the same circuit
+    (rows for `steps` control steps plus a horizon)."""
+    gates = loop_track(track_seed, n_gates)
+    prm = params(K, N, objective, seed, dt=dt, **over)
+    w = dict(quad=dict(QUAD), params=prm, gates=gates, x0=start_state(gates))
+    if objective == "contour":
+        path, L = path_table(gates)
+        w.update(path=path, path_len=L)
+    if objective == "track":
+        w.update(xref=reference_table(gates, dt=dt, n_rows=steps + N + 1), ref_dt=dt)
     return w
 
 

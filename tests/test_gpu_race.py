@@ -75,3 +75,27 @@ def test_independent_gate_flights_agree():
         else:
             assert abs(sd[k] - so[k]) <= 1e-9 * max(1.0, abs(so[k])), (k, sd[k], so[k])
     dev.close()
+
+
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
+def test_race_configuration_steps_match_the_oracle(objective):
+    """The race the benchmark flies (thrust-rate input, 8192 samples, 20
+    steps of 0.03 s, its per-objective noise and temperature, the circuit
+    track), binary32, step by step against the oracle for 20 control steps."""
+    import bench
+    st = bench.RACE_SETTINGS[objective]
+    print("[gpu-case] race configuration step by step", objective, st, "K=8192 N=20 20 steps", flush=True)
+    hover = synth.QUAD["mass"] * synth.QUAD["gravity"] / 4.0
+    w = synth.race_workload(K=8192, N=20, objective=objective, seed=1, track_seed=1, dt=0.03, steps=40,
+                            sigma=(st["sigma"],) * 4, sigma_v=5.0, input_model=M.INPUT_RATE,
+                            rate_lim=(-10.0, 10.0), dv_lim=(-20.0, 20.0), **{"lambda": st["lam"]})
+    dev, orc = build_pair(w, M.FP32)
+
+    def solve(x, t):
+        r = solve_and_compare(dev, orc, x, t, M.FP32, sigma=st["sigma"])
+        return r["U"][0], r["info"]
+
+    x0 = np.concatenate([w["x0"], np.full(4, hover)])
+    fl = race.fly(solve, w["quad"], x0, 20, 0.03)
+    assert fl["error"] is None and fl["X"].shape == (21, 17)
+    dev.close()

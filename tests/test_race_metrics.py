@@ -114,3 +114,24 @@ def test_fly_closes_the_loop_with_the_host_plant():
 
     fl = race.fly(failing, q, x0, 10, 0.02)
     assert fl["X"].shape == (4, 13) and "non-finite" in fl["error"]
+
+
+def test_loop_track_gates_face_along_the_path():
+    """The race circuit: flying the path table in the direction of increasing
+    arc length crosses every gate front to back, inside its square, in track
+    order (the race metrics count all of them on one lap of the table)."""
+    from paper_2509_14726_amd import synth
+    for seed in (1, 2, 3):
+        gates = synth.loop_track(seed)
+        path, L = synth.path_table(gates)
+        # start just before gate 0's plane: rotate the table to begin there
+        i0 = int(np.argmin(np.linalg.norm(path[:, :3] - gates[0, :3], axis=1)))
+        P = np.roll(path[:, :3], 5 - i0, axis=0)
+        lp = race.lap(P, np.arange(len(P)) * 0.01, gates, 1.5)
+        assert lp["gates_passed"] == len(gates), seed
+        assert np.all(race.waypoint_pass_errors(P, gates) < 0.05)
+    w = synth.race_workload(objective="track", steps=100)
+    assert w["xref"].shape == (100 + 20 + 1, 13) and w["params"]["N"] == 20 and w["params"]["dt"] == 0.03
+    n = np.array([np.cos(gates[0, 3]), np.sin(gates[0, 3]), 0.0])
+    x0 = synth.start_state(gates)
+    assert abs(float((gates[0, :3] - x0[:3]) @ n) - 2.0) < 1e-12
