@@ -430,8 +430,9 @@ const char *mppi_server_last_error(const mppi_server *s);
  * valid until the next call on the context.  ctx may be NULL (creation). */
 const char *mppi_last_error(const mppi_ctx *ctx);
 
-/* Static name of a status code. */
-const char *mppi_status_string(mppi_status s);
+/* Static name of a status code; "MPPI_E_UNKNOWN" for any other integer (the
+ * argument is an int so that a value outside the enumeration is defined). */
+const char *mppi_status_string(int32_t s);
 
 /* Host FP64 plant step of the paper's rate model (Sec. III-A) for closed-loop
  * simulation: x and x_out hold 17 states (the thrusts last), tdot the rotor

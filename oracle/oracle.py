@@ -14,7 +14,10 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liborc.so")
+# ORACLE_LIBRARY names another build of the oracle (the host-sanitizer build);
+# by default the in-tree one.
+BUILD_PATH = os.path.join(HERE, "liborc.so")
+LIB_PATH = os.environ.get("ORACLE_LIBRARY") or BUILD_PATH
 SRC = os.path.join(HERE, "mppi_oracle.c")
 COUNT_LIB_PATH = os.path.join(HERE, "liborc_count.so")
 COUNT_SRC = os.path.join(HERE, "opcount.cpp")
@@ -29,19 +32,19 @@ OK, EINVAL, ENONFINITE = 0, -1, -4
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C99, no fast-math, no FMA contraction),
     and its op-counting build (the same source as C++ with binary64 counted)."""
-    if force or not os.path.exists(LIB_PATH):
-        tmp = LIB_PATH + ".tmp"
+    if force or not os.path.exists(BUILD_PATH):
+        tmp = BUILD_PATH + ".tmp"
         subprocess.check_call([
             "gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-fopenmp",
             "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB_PATH)
+        os.replace(tmp, BUILD_PATH)
     if force or not os.path.exists(COUNT_LIB_PATH):
         tmp = COUNT_LIB_PATH + ".tmp"
         subprocess.check_call([
             "g++", "-O2", "-std=c++17", "-Wall", "-Wno-unknown-pragmas", "-Wno-unused-variable",
             "-fPIC", "-shared", "-ffp-contract=off", "-o", tmp, COUNT_SRC, "-lm"])
         os.replace(tmp, COUNT_LIB_PATH)
-    return LIB_PATH
+    return BUILD_PATH
 
 
 class Quad(C.Structure):

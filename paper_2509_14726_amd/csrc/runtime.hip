@@ -252,7 +252,7 @@ static mppi_status launch_iterations(mppi_ctx *ctx, KArgs a)
 
 extern "C" {
 
-const char *mppi_status_string(mppi_status s)
+const char *mppi_status_string(int32_t s)
 {
     switch (s) {
     case MPPI_OK: return "MPPI_OK";

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmppi.so")
+# MPPI_LIBRARY names another build of the same library (the host-sanitizer
+# build of paper_2509_14726_amd.sanitize); by default the in-tree one.
+LIB_PATH = os.environ.get("MPPI_LIBRARY") or os.path.join(HERE, "libmppi.so")
 
 N_MAX = 256
 K_MAX = 1 << 24
