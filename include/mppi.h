@@ -135,11 +135,13 @@ typedef struct {
  * same counters and the same arithmetic) instead of reading the N x K sample
  * tensor, which the rollout then does not write: the same result bit for
  * bit, with Philox and Box-Muller work in place of 16 B (20 B contouring) of
- * HBM traffic per sample and step.  It takes effect in the three- and
- * four-wave rollout layouts, whose rollout draws the samples itself
- * (mppi_info.regen_average reports it); batched and served solves keep the
- * tensor.  mppi_read_samples then returns the costs only (MPPI_E_INVAL when
- * U_samples is requested). */
+ * HBM traffic per sample and step.  It takes effect wherever the rollout
+ * draws the samples itself: the three- and four-wave layouts and the
+ * drawing one-wave layout (mppi_info.regen_average reports it), with thrust
+ * as the input, one iteration and no control-cost term.  Batches choose it
+ * per batch (mppi_batch_cfg.regen_average); served solves keep the tensor.
+ * mppi_autotune can choose it instead.  mppi_read_samples then returns the
+ * costs only (MPPI_E_INVAL when U_samples is requested). */
 #define MPPI_FLAG_REGEN_AVERAGE 2
 
 /* Problem data: the inputs of Alg. 1 (waypoints W, path P_arc, tau_ref). */
@@ -277,6 +279,27 @@ mppi_status mppi_solve_device_noalloc(mppi_ctx *ctx, const double *d_req, double
 /* Wait for the context stream and copy the report of the latest solve. */
 mppi_status mppi_read_info(mppi_ctx *ctx, mppi_info *info);
 
+/* Result of mppi_autotune. */
+typedef struct {
+    int32_t regen_average;   /* chosen: 1 the regenerating average, 0 the stored */
+    int32_t from_cache;      /* 1: taken from the cache, nothing timed           */
+    double ms_stored;        /* mean solve time with the stored average, ms (0:
+                                not measured)                                   */
+    double ms_regen;         /* the same with the regenerating average (0: not
+                                measured or not available in this layout)      */
+} mppi_tune_result;
+
+/* Autotuner of one context (Eq. (5) either way): time `reps` solves of the
+ * request record d_req (device, layout of mppi_solve_device) with the stored
+ * and with the regenerating weighted average, where the context's rollout
+ * draws its samples, and keep the faster for the context's later solves; on
+ * a cache hit (cache_path, key kind "ctx", no MPPI_TUNE_FORCE) apply the
+ * cached choice without timing.  The warm-start state and report are
+ * restored after the timed solves.  Synchronous.  MPPI_E_INVAL for a NULL
+ * context or request, reps < 1, or a context with an external workspace. */
+mppi_status mppi_autotune(mppi_ctx *ctx, const double *d_req, int32_t reps, const char *cache_path, int32_t flags,
+                          mppi_tune_result *out);
+
 /* Copy the latest solve's sample costs (K doubles, as computed, in FP64
  * whatever the precision) and optionally the sample controls (N x K x 4
  * doubles, step-major; MPPI_E_INVAL when the context's average regenerates
@@ -328,6 +351,10 @@ typedef struct {
     int32_t sample_groups;     /* workgroups of the sample and reduction kernels;
                                   0: automatic                                   */
     int32_t use_graph;         /* 1: capture the launch sequence in a HIP graph  */
+    int32_t regen_average;     /* 1: with three- or four-wave rollouts, no sample
+                                  tensor: the weighted average draws the samples
+                                  again (see MPPI_FLAG_REGEN_AVERAGE); ignored
+                                  with one- and two-wave rollouts             */
 } mppi_batch_cfg;
 
 /* Register ctxs[0..n-1] (distinct, same precision, each used by no other
@@ -351,13 +378,25 @@ mppi_status mppi_batch_solve_device(mppi_batch *b, const int32_t *active, int32_
 mppi_status mppi_batch_set_cfg(mppi_batch *b, const mppi_batch_cfg *cfg);
 mppi_status mppi_batch_get_cfg(const mppi_batch *b, mppi_batch_cfg *cfg);
 
+/* Autotuner cache: a JSON object in the file cache_path, one entry per key
+ * "<kind>|<gfx arch>|<objective(s)>|<fp32|fp64>|<size buckets>" (size
+ * buckets: floor(log2) of K and N for a context; of the instance count and of
+ * sum K*N for a batch), each holding the chosen launch settings and the mean
+ * time measured for them.  Written through a temporary file and a rename.
+ * cache_path NULL: no cache.  MPPI_TUNE_FORCE: time even on a cache hit. */
+#define MPPI_TUNE_FORCE 1
+
 /* Autotuner: time every candidate launch shape (rollout waves x persistent
- * rollout workgroups x reduction workgroups) over `reps` steps of the whole
- * batch with the given requests, keep the fastest, and report it and its
- * mean step time in ms.  Runs real solves: the warm-start state of every
- * context advances by (candidates x reps) steps. */
+ * rollout workgroups x reduction workgroups, and with three- or four-wave
+ * rollouts the stored and the regenerating average) over `reps` steps of the
+ * whole batch with the given requests, keep the fastest, and report it and
+ * its mean step time in ms; on a cache hit (no MPPI_TUNE_FORCE) apply the
+ * cached shape and time nothing (*best_ms: the cached time, *from_cache 1).
+ * The timed solves are real solves (they write d_u0s), but the warm-start
+ * state and report of every context are restored afterwards. */
 mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u0s, int32_t reps,
-                                mppi_batch_cfg *best, double *best_ms);
+                                const char *cache_path, int32_t flags, mppi_batch_cfg *best, double *best_ms,
+                                int32_t *from_cache);
 
 void mppi_batch_destroy(mppi_batch *b);
 const char *mppi_batch_last_error(const mppi_batch *b);

@@ -463,6 +463,11 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
             o.w = warm ? (Real)a.wU[4 * src + 3] : (Real)a.hover;
             s_us[k] = o;
             if (HAS_V) s_vs[k] = warm ? (Real)a.wV[src] : Real(0);
+            // the weighted average draws the samples again from these rows
+            if (a.regen && blk == (K >> 6)) {
+                ((R4 *)a.nomU)[k] = o;
+                if (HAS_V) ((Real *)a.nomV)[k] = s_vs[k];
+            }
         }
         __syncthreads();
     }
@@ -479,14 +484,24 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
         const size_t ustride = nominal ? 1 : (size_t)K;
         const Real *vrow = nullptr;
         if (OBJ == OBJ_CONTOUR) vrow = nominal ? (const Real *)a.nomV : (const Real *)a.vctrl + m;
-        // the inputs (u, V) of step k: drawn (and stored) or read
-        const bool draw = DRAW && !nominal;
+        // the inputs (u, V) of step k: drawn (and stored, unless the weighted
+        // average draws them again) or read.  Drawing, the nominal clips the
+        // staged rows itself (the values the head kernel wrote to nomU / nomV,
+        // which then hold the unclipped rows of the regenerating average).
+        const bool keep = !a.regen;
         const uint32_t s_solve = cur->s;
         const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max;
         const Real sig0 = (Real)a.sigma[0], sig1 = (Real)a.sigma[1];
         const Real sig2 = (Real)a.sigma[2], sig3 = (Real)a.sigma[3];
         auto input = [&](const int k, R4 &uo, Real &vo) {
-            if (draw) {
+            if (DRAW && nominal) {
+                const R4 us = s_us[k];
+                uo.x = clampT(us.x, tmin, tmax);
+                uo.y = clampT(us.y, tmin, tmax);
+                uo.z = clampT(us.z, tmin, tmax);
+                uo.w = clampT(us.w, tmin, tmax);
+                if (HAS_V) vo = clampT(s_vs[k], Real(0), (Real)a.v_max);
+            } else if (DRAW) {
                 const R4 us = s_us[k];
                 const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, s_solve, 0u, a.seed_lo, a.seed_hi);
                 uo.x = clampT(us.x + sig0 * z.z0, tmin, tmax);
@@ -494,11 +509,11 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
                 uo.z = clampT(us.z + sig2 * z.z2, tmin, tmax);
                 uo.w = clampT(us.w + sig3 * z.z3, tmin, tmax);
                 const size_t idx = (size_t)k * (size_t)K + (size_t)m;
-                store_nt(&((R4 *)a.ctrl)[idx], uo);
+                if (keep) store_nt(&((R4 *)a.ctrl)[idx], uo);
                 if (HAS_V) {
                     const Real zv = normal1<Real>((uint32_t)m, (uint32_t)k, s_solve, 1u, a.seed_lo, a.seed_hi);
                     vo = clampT(s_vs[k] + (Real)a.sigma_v * zv, Real(0), (Real)a.v_max);
-                    store_nt(&((Real *)a.vctrl)[idx], vo);
+                    if (keep) store_nt(&((Real *)a.vctrl)[idx], vo);
                 }
             } else {
                 uo = urow[(size_t)k * ustride];
@@ -2566,7 +2581,9 @@ template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         item = advance_item(b.step_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
-        final_body<Real, Acc, HAS_V, false>(s_a, u - b.step_prefix[item]);
+        // a context whose rollout left no sample tensor: draw the samples again
+        if (s_a.regen) final_body<Real, Acc, HAS_V, true>(s_a, u - b.step_prefix[item]);
+        else final_body<Real, Acc, HAS_V, false>(s_a, u - b.step_prefix[item]);
         __syncthreads();
     }
 }

@@ -52,6 +52,7 @@ struct mppi_ctx {
     size_t ws_bytes = 0;        // size of that scratch
     int device = 0;             // device current at creation
     int n_iter = 1;             // MPPI iterations per solve
+    bool no_tensor = false;     // the last solve's average drew the samples again
     std::string err;
 };
 
@@ -86,6 +87,104 @@ static mppi_status fail(mppi_ctx *c, mppi_status s, const char *fmt, ...)
         if (e_ != hipSuccess)                                                                    \
             return fail((ctx), MPPI_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
     } while (0)
+
+// ------------------------------------------------------------ autotuner cache
+//
+// A JSON object in one file, one entry per line:
+//   "<key>": {"rollout_waves": W, "rollout_groups": R, "sample_groups": S, "regen_average": G, "ms": T},
+// rewritten whole through a temporary file and a rename.
+namespace tune {
+
+struct Entry {
+    int waves = 0, groups = 0, sgroups = 0, regen = 0;
+    double ms = 0.0;
+};
+
+// The gfx architecture of a device, without its feature suffixes.
+static std::string arch_of(int dev)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string s = prop.gcnArchName;
+    const size_t c = s.find(':');
+    return c == std::string::npos ? s : s.substr(0, c);
+}
+
+static int bucket(double x) { return x >= 1.0 ? (int)floor(log2(x)) : 0; }
+
+static const char *prec_name(bool fp64) { return fp64 ? "fp64" : "fp32"; }
+
+static bool field(const std::string &line, const char *name, double &out)
+{
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t i = line.find(pat);
+    if (i == std::string::npos) return false;
+    char *end = nullptr;
+    const char *p = line.c_str() + i + pat.size();
+    out = strtod(p, &end);
+    return end != p;
+}
+
+// Every entry of the file as (key, line); an unreadable file is empty.
+static std::vector<std::pair<std::string, std::string>> read_all(const char *path)
+{
+    std::vector<std::pair<std::string, std::string>> out;
+    FILE *f = fopen(path, "r");
+    if (!f) return out;
+    char buf[1024];
+    while (fgets(buf, sizeof buf, f)) {
+        std::string line(buf);
+        while (!line.empty() && (line.back() == '\n' || line.back() == '\r' || line.back() == ',')) line.pop_back();
+        if (line.size() < 2 || line[0] != '"') continue;
+        const size_t q = line.find('"', 1);
+        if (q == std::string::npos) continue;
+        out.emplace_back(line.substr(1, q - 1), line);
+    }
+    fclose(f);
+    return out;
+}
+
+static bool load(const char *path, const std::string &key, Entry &e)
+{
+    if (!path) return false;
+    for (const auto &kv : read_all(path)) {
+        if (kv.first != key) continue;
+        double w = 0, g = 0, sg = 0, r = 0, ms = 0;
+        if (!field(kv.second, "rollout_waves", w) || !field(kv.second, "rollout_groups", g) ||
+            !field(kv.second, "sample_groups", sg) || !field(kv.second, "regen_average", r) ||
+            !field(kv.second, "ms", ms))
+            return false;
+        e.waves = (int)w; e.groups = (int)g; e.sgroups = (int)sg; e.regen = (int)r; e.ms = ms;
+        return true;
+    }
+    return false;
+}
+
+// Adds or replaces the entry of key; false when the file cannot be written.
+static bool store(const char *path, const std::string &key, const Entry &e)
+{
+    if (!path) return true;
+    auto all = read_all(path);
+    char buf[512];
+    snprintf(buf, sizeof buf,
+             "\"%s\": {\"rollout_waves\": %d, \"rollout_groups\": %d, \"sample_groups\": %d, "
+             "\"regen_average\": %d, \"ms\": %.6f}",
+             key.c_str(), e.waves, e.groups, e.sgroups, e.regen, e.ms);
+    bool found = false;
+    for (auto &kv : all)
+        if (kv.first == key) { kv.second = buf; found = true; }
+    if (!found) all.emplace_back(key, buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    fputs("{\n", f);
+    for (size_t i = 0; i < all.size(); ++i) fprintf(f, "%s%s\n", all[i].second.c_str(), i + 1 < all.size() ? "," : "");
+    fputs("}\n", f);
+    const bool ok = fclose(f) == 0;
+    return ok && rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace tune
 
 static void *dev_alloc(mppi_ctx *c, size_t bytes)
 {
@@ -226,6 +325,16 @@ static void plan_layout(mppi_ctx *c)
     }
 }
 
+// The average can draw the samples again only where the rollout draws them
+// (three- and four-wave layouts, the drawing one-wave layout), with thrust as
+// the input (a rate sample follows its thrust chain), and not when the
+// control-cost term reads the sample tensor.
+static bool can_regen(const KArgs &a)
+{
+    const bool draws = a.rollout_waves >= 3 || (a.rollout_waves == 1 && a.rollout_draw == 1);
+    return draws && a.input_model == INPUT_THRUST && a.ctrl_cost == 0.0;
+}
+
 // Point the per-solve buffers of a at a workspace of ws_layout's size.
 static void bind_workspace(KArgs &a, char *w)
 {
@@ -243,6 +352,7 @@ static void bind_workspace(KArgs &a, char *w)
 // marked inner (no shift, the first iteration's last applied input).
 static mppi_status launch_iterations(mppi_ctx *ctx, KArgs a)
 {
+    ctx->no_tensor = a.regen != 0;
     for (int it = 0; it < ctx->n_iter; ++it) {
         a.inner = it > 0 ? 1 : 0;
         HIP_TRY(ctx, launch_solve(a, ctx->fp64, ctx->acc64, ctx->stream, next_events(ctx)));
@@ -344,10 +454,7 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad, const 
     a.C = c->C;
     a.real_bytes = (int32_t)rs;
     c->external_ws = (params->flags & MPPI_FLAG_EXTERNAL_WORKSPACE) != 0;
-    // the average can draw the samples again only where the rollout draws them,
-    // and not when the control-cost term reads the sample tensor
-    a.regen = ((params->flags & MPPI_FLAG_REGEN_AVERAGE) != 0 && a.rollout_waves >= 3 && p.ctrl_cost == 0.0)
-                  ? 1 : 0;
+    a.regen = ((params->flags & MPPI_FLAG_REGEN_AVERAGE) != 0 && can_regen(a)) ? 1 : 0;
     struct Want { void **dst; size_t bytes; };
     void *gates_d = nullptr, *gates_r = nullptr, *path_d = nullptr, *path_r = nullptr, *xref_r = nullptr;
     void *warm = nullptr, *wU = nullptr, *wV = nullptr, *cur = nullptr, *res = nullptr, *req = nullptr;
@@ -584,9 +691,10 @@ mppi_status mppi_read_samples(mppi_ctx *ctx, double *J, double *U_samples)
         }
     }
     if (U_samples) {
-        if (ctx->args.regen)
+        if (ctx->no_tensor)
             return fail(ctx, MPPI_E_INVAL,
-                        "the context was created with MPPI_FLAG_REGEN_AVERAGE: its solves keep no sample tensor");
+                        "the last solve's weighted average drew the samples again (MPPI_FLAG_REGEN_AVERAGE, the "
+                        "autotuner's or the batch's choice): it kept no sample tensor");
         if (ctx->fp64) {
             HIP_TRY(ctx, hipMemcpy(U_samples, ctx->args.ctrl, sizeof(double) * 4 * K * N, hipMemcpyDeviceToHost));
         } else {
@@ -595,6 +703,129 @@ mppi_status mppi_read_samples(mppi_ctx *ctx, double *J, double *U_samples)
             for (size_t i = 0; i < 4 * K * N; ++i) U_samples[i] = tmp[i];
         }
     }
+    return MPPI_OK;
+}
+
+}  // extern "C"
+
+// What a solve changes on the device besides its workspace: the warm-start
+// state, the handed-on sequences, the per-solve head values and the report.
+// The autotuners copy it aside before timing real solves and back after.
+struct Snapshot {
+    void *buf = nullptr;
+    Snapshot() = default;
+    Snapshot(const Snapshot &) = delete;
+    Snapshot &operator=(const Snapshot &) = delete;
+    static size_t bytes() { return sizeof(DevWarm) + sizeof(double) * kNMax * 5 + sizeof(DevCur) + sizeof(DevResult); }
+    hipError_t take(const KArgs &a, hipStream_t st)
+    {
+        if (!buf) {
+            const hipError_t e = hipMalloc(&buf, bytes());
+            if (e != hipSuccess) { buf = nullptr; return e; }
+        }
+        return copy(a, st, true);
+    }
+    hipError_t restore(const KArgs &a, hipStream_t st) { return copy(a, st, false); }
+    hipError_t copy(const KArgs &a, hipStream_t st, bool out)
+    {
+        char *p = (char *)buf;
+        void *dev[5] = {a.warm, a.wU, a.wV, a.cur, a.res};
+        const size_t sz[5] = {sizeof(DevWarm), sizeof(double) * kNMax * 4, sizeof(double) * kNMax, sizeof(DevCur),
+                              sizeof(DevResult)};
+        for (int i = 0; i < 5; ++i) {
+            const hipError_t e = out ? hipMemcpyAsync(p, dev[i], sz[i], hipMemcpyDeviceToDevice, st)
+                                     : hipMemcpyAsync(dev[i], p, sz[i], hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+            p += sz[i];
+        }
+        return hipSuccess;
+    }
+    ~Snapshot() { if (buf) (void)hipFree(buf); }
+};
+
+static const char *objective_name(int o) { return o == MPPI_OBJ_CONTOUR ? "contour" : (o == MPPI_OBJ_TRACK ? "track" : "gate"); }
+
+extern "C" {
+
+mppi_status mppi_autotune(mppi_ctx *ctx, const double *d_req, int32_t reps, const char *cache_path, int32_t flags,
+                          mppi_tune_result *out)
+{
+    if (!ctx) return fail(nullptr, MPPI_E_INVAL, "ctx is NULL");
+    if (!d_req || reps < 1) return fail(ctx, MPPI_E_INVAL, "a request and reps >= 1 are required");
+    if (ctx->external_ws) return fail(ctx, MPPI_E_INVAL, "context has no workspace of its own (server context)");
+    ctx->err.clear();
+    mppi_tune_result r{};
+    if (!can_regen(ctx->args)) {
+        // one choice only: the stored average
+        ctx->args.regen = 0;
+        if (out) *out = r;
+        return MPPI_OK;
+    }
+    char key[256];
+    snprintf(key, sizeof key, "ctx|%s|%s|%s|K%d|N%d|w%d", tune::arch_of(ctx->device).c_str(),
+             objective_name(ctx->objective), tune::prec_name(ctx->fp64), tune::bucket(ctx->K), tune::bucket(ctx->N),
+             ctx->args.rollout_waves);
+    tune::Entry e;
+    if (!(flags & MPPI_TUNE_FORCE) && tune::load(cache_path, key, e)) {
+        ctx->args.regen = e.regen ? 1 : 0;
+        r.regen_average = ctx->args.regen;
+        r.from_cache = 1;
+        (ctx->args.regen ? r.ms_regen : r.ms_stored) = e.ms;
+        if (out) *out = r;
+        return MPPI_OK;
+    }
+    Snapshot snap;
+    HIP_TRY(ctx, snap.take(ctx->args, ctx->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    // the timed solves stay out of the per-kernel profile
+    const bool profiling = ctx->profiling;
+    ctx->profiling = false;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, MPPI_E_DEVICE, "hipEventCreate failed");
+    }
+    const int keep = ctx->args.regen;
+    double ms[2] = {0.0, 0.0};
+    mppi_status st = MPPI_OK;
+    for (int g = 0; g < 2 && st == MPPI_OK; ++g) {
+        ctx->args.regen = g;
+        KArgs a = ctx->args;
+        a.req = d_req;
+        a.u0_out = nullptr;
+        if ((st = launch_iterations(ctx, a)) != MPPI_OK) break;  // warm-up
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = fail(ctx, MPPI_E_DEVICE, "event record failed"); break; }
+        for (int i = 0; i < reps && st == MPPI_OK; ++i) st = launch_iterations(ctx, a);
+        if (st != MPPI_OK) break;
+        float t = 0.0f;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+            st = fail(ctx, MPPI_E_DEVICE, "timing the candidates failed");
+            break;
+        }
+        ms[g] = t / reps;
+        if (snap.restore(ctx->args, ctx->stream) != hipSuccess) st = fail(ctx, MPPI_E_DEVICE, "restore failed");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->profiling = profiling;
+    if (st != MPPI_OK) {
+        ctx->args.regen = keep;
+        (void)snap.restore(ctx->args, ctx->stream);
+        (void)hipStreamSynchronize(ctx->stream);
+        return st;
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->args.regen = ms[1] < ms[0] ? 1 : 0;
+    r.regen_average = ctx->args.regen;
+    r.ms_stored = ms[0];
+    r.ms_regen = ms[1];
+    e.regen = ctx->args.regen;
+    e.ms = ms[ctx->args.regen];
+    e.waves = ctx->args.rollout_waves;
+    if (!tune::store(cache_path, key, e))
+        return fail(ctx, MPPI_E_INVAL, "cannot write the autotuner cache %s", cache_path);
+    if (out) *out = r;
     return MPPI_OK;
 }
 
@@ -762,6 +993,7 @@ struct mppi_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     KArgs *d_table = nullptr;
+    std::vector<KArgs> h_table;  // host copy of d_table
     std::vector<BatchGroup> groups;
     mppi_batch_cfg cfg{};
     hipGraphExec_t exec = nullptr;
@@ -802,12 +1034,24 @@ static void drop_graph(mppi_batch *b)
 }
 
 // Resolve automatic fields of the launch shape for this batch.
-static void resolve_cfg(mppi_batch *b)
+static hipError_t resolve_cfg(mppi_batch *b)
 {
     mppi_batch_cfg &c = b->cfg;
     int waves = c.rollout_waves;
     const int cu = b->n_cu, tiles = b->total_tiles;
     if (waves < 1 || waves > 4) waves = tiles <= cu ? 4 : (tiles <= 2 * cu ? (b->fp64 ? 2 : 4) : 1);
+    // the regenerating average where the batch's rollout draws the samples
+    // (batched contexts take thrust as the input, one iteration and no
+    // control-cost term)
+    const int regen = (c.regen_average && waves >= 3) ? 1 : 0;
+    bool changed = false;
+    for (auto &t : b->h_table)
+        if (t.regen != regen) { t.regen = regen; changed = true; }
+    if (changed && b->d_table) {
+        const hipError_t e = hipMemcpy(b->d_table, b->h_table.data(), sizeof(KArgs) * b->h_table.size(),
+                                       hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+    }
     // four-wave chunk: the contexts' own when they all agree (a served solve
     // then runs exactly its stand-alone kernel), else by the batch's tiles
     int ring = b->ctxs[0]->args.ring4_b;
@@ -834,6 +1078,7 @@ static void resolve_cfg(mppi_batch *b)
         // kFinalThreads-thread workgroups, two per CU
         g.launch.final_groups = 2 * b->n_cu;
     }
+    return hipSuccess;
 }
 
 static void release_batch(mppi_batch *b)
@@ -876,7 +1121,7 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
     if (!b) return bfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
     b->ctxs.assign(ctxs, ctxs + n);
     b->fp64 = ctxs[0]->fp64;
-    b->cfg = cfg ? *cfg : mppi_batch_cfg{0, 0, 0, 1};
+    b->cfg = cfg ? *cfg : mppi_batch_cfg{0, 0, 0, 1, 0};
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -913,9 +1158,10 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
         b->tiles_of[i] = (c->K + 1 + 63) / 64;
         b->total_tiles += b->tiles_of[i];
     }
-    // device table of kernel arguments
-    std::vector<KArgs> table(n);
-    // batched solves keep the sample tensor (their layout is the batch's own)
+    // device table of kernel arguments; whether the average draws the samples
+    // again is the batch's choice (its layout is its own)
+    std::vector<KArgs> &table = b->h_table;
+    table.resize(n);
     for (int i = 0; i < n; ++i) {
         table[i] = ctxs[i]->args;
         table[i].regen = 0;
@@ -945,7 +1191,10 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
         g.bargs.tile_prefix = (const int32_t *)(d + o_tp);
         g.bargs.step_prefix = (const int32_t *)(d + o_ap);
     }
-    resolve_cfg(b);
+    if (resolve_cfg(b) != hipSuccess) {
+        release_batch(b);
+        return bfail(nullptr, MPPI_E_DEVICE, "upload of the kernel-argument table failed");
+    }
     *out = b;
     return MPPI_OK;
 }
@@ -958,7 +1207,7 @@ mppi_status mppi_batch_set_cfg(mppi_batch *b, const mppi_batch_cfg *cfg)
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     drop_graph(b);
     b->cfg = *cfg;
-    resolve_cfg(b);
+    BHIP_TRY(b, resolve_cfg(b));
     return MPPI_OK;
 }
 
@@ -966,6 +1215,7 @@ mppi_status mppi_batch_get_cfg(const mppi_batch *b, mppi_batch_cfg *cfg)
 {
     if (!b || !cfg) return MPPI_E_INVAL;
     *cfg = b->cfg;
+    if (!b->h_table.empty()) cfg->regen_average = b->h_table[0].regen;
     if (!b->groups.empty()) {
         cfg->rollout_waves = b->groups[0].launch.rollout_waves;
         cfg->rollout_groups = b->groups[0].launch.rollout_groups;
@@ -1007,6 +1257,8 @@ static mppi_status batch_solve(mppi_batch *b, const int32_t *active, int32_t n_a
         seen[r] = 1;
         per[b->group_of[r]].push_back({r, i});
     }
+    for (int r = 0; r < n; ++r)
+        if (seen[r]) b->ctxs[r]->no_tensor = b->h_table[r].regen != 0;
     // the previous step's descriptor copy must have left the pinned buffers
     if (b->copy_pending) BHIP_TRY(b, hipEventSynchronize(b->copy_done));
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
@@ -1077,10 +1329,33 @@ mppi_status mppi_batch_solve_device(mppi_batch *b, const int32_t *active, int32_
 }
 
 mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u0s, int32_t reps,
-                                mppi_batch_cfg *best, double *best_ms)
+                                const char *cache_path, int32_t flags, mppi_batch_cfg *best, double *best_ms,
+                                int32_t *from_cache)
 {
     if (!b || !d_reqs || reps < 1) return bfail(b, MPPI_E_INVAL, "batch, requests and reps >= 1 are required");
     const int n = (int)b->ctxs.size();
+    if (from_cache) *from_cache = 0;
+    // cache key: architecture, objectives, precision, instance count and
+    // total rollout steps
+    int objs = 0;
+    double kn = 0.0;
+    for (const mppi_ctx *c : b->ctxs) {
+        objs |= 1 << c->objective;
+        kn += (double)c->K * (double)c->N;
+    }
+    char key[256];
+    snprintf(key, sizeof key, "batch|%s|obj%d|%s|n%d|KN%d", tune::arch_of(b->ctxs[0]->device).c_str(), objs,
+             tune::prec_name(b->fp64), tune::bucket(n), tune::bucket(kn));
+    tune::Entry ce;
+    if (!(flags & MPPI_TUNE_FORCE) && tune::load(cache_path, key, ce)) {
+        const mppi_batch_cfg c{ce.waves, ce.groups, ce.sgroups, b->cfg.use_graph, ce.regen};
+        const mppi_status st = mppi_batch_set_cfg(b, &c);
+        if (st != MPPI_OK) return st;
+        if (best) *best = c;
+        if (best_ms) *best_ms = ce.ms;
+        if (from_cache) *from_cache = 1;
+        return MPPI_OK;
+    }
     const mppi_batch_cfg saved = b->cfg;
     std::vector<mppi_batch_cfg> cand;
     const int cu = b->n_cu;
@@ -1088,9 +1363,22 @@ mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u
         const int rg_mult[] = {1, 2, 4, 8};
         for (int rm : rg_mult) {
             if (waves >= 2 && rm > 2) continue;  // one or two LDS rings fit one CU
-            for (int sm : {1, 4}) cand.push_back(mppi_batch_cfg{waves, rm * cu, sm * cu, 1});
+            for (int sm : {1, 4})
+                for (int regen = 0; regen <= (waves >= 3 ? 1 : 0); ++regen)
+                    cand.push_back(mppi_batch_cfg{waves, rm * cu, sm * cu, saved.use_graph, regen});
         }
     }
+    // the timed steps are real solves: every context's state is put back after
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    std::vector<Snapshot> snaps(n);
+    for (int i = 0; i < n; ++i) BHIP_TRY(b, snaps[i].take(b->ctxs[i]->args, b->stream));
+    auto restore_all = [&]() -> hipError_t {
+        for (int i = 0; i < n; ++i) {
+            const hipError_t e = snaps[i].restore(b->ctxs[i]->args, b->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipStreamSynchronize(b->stream);
+    };
     hipEvent_t e0, e1;
     BHIP_TRY(b, hipEventCreate(&e0));
     BHIP_TRY(b, hipEventCreate(&e1));
@@ -1111,11 +1399,24 @@ mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u
         (void)hipEventElapsedTime(&ms, e0, e1);
         const double t = ms / reps;
         if (t < best_t) { best_t = t; best_c = c; }
+        if (restore_all() != hipSuccess) { st = MPPI_E_DEVICE; break; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st != MPPI_OK) { (void)mppi_batch_set_cfg(b, &saved); return st; }
+    if (st != MPPI_OK) {
+        (void)mppi_batch_set_cfg(b, &saved);
+        (void)restore_all();
+        return st;
+    }
     if ((st = mppi_batch_set_cfg(b, &best_c)) != MPPI_OK) return st;
+    tune::Entry e;
+    e.waves = best_c.rollout_waves;
+    e.groups = best_c.rollout_groups;
+    e.sgroups = best_c.sample_groups;
+    e.regen = best_c.regen_average;
+    e.ms = best_t;
+    if (!tune::store(cache_path, key, e))
+        return bfail(b, MPPI_E_INVAL, "cannot write the autotuner cache %s", cache_path);
     if (best) *best = best_c;
     if (best_ms) *best_ms = best_t;
     return MPPI_OK;

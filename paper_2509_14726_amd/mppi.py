@@ -33,7 +33,7 @@ EXPORTS = ["mppi_create", "mppi_destroy", "mppi_solve", "mppi_solve_device",
            "mppi_solve_device_noalloc", "mppi_read_info",
            "mppi_read_samples", "mppi_get_warm", "mppi_set_warm", "mppi_last_error",
            "mppi_status_string", "mppi_plant_step", "mppi_plant_step_rate", "mppi_set_profiling",
-           "mppi_read_profile",
+           "mppi_read_profile", "mppi_autotune",
            "mppi_batch_create", "mppi_batch_solve_device", "mppi_batch_set_cfg", "mppi_batch_get_cfg",
            "mppi_batch_autotune", "mppi_batch_destroy", "mppi_batch_last_error",
            "mppi_server_create", "mppi_server_submit", "mppi_server_progress", "mppi_server_poll",
@@ -67,6 +67,7 @@ class mppi_params(C.Structure):
 
 FLAG_EXTERNAL_WORKSPACE = 1
 FLAG_REGEN_AVERAGE = 2
+TUNE_FORCE = 1
 
 
 class mppi_problem(C.Structure):
@@ -104,7 +105,15 @@ class mppi_warm(C.Structure):
 
 class mppi_batch_cfg(C.Structure):
     _fields_ = [("rollout_waves", C.c_int32), ("rollout_groups", C.c_int32),
-                ("sample_groups", C.c_int32), ("use_graph", C.c_int32)]
+                ("sample_groups", C.c_int32), ("use_graph", C.c_int32), ("regen_average", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class mppi_tune_result(C.Structure):
+    _fields_ = [("regen_average", C.c_int32), ("from_cache", C.c_int32), ("ms_stored", C.c_double),
+                ("ms_regen", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -187,7 +196,10 @@ def _load():
     L.mppi_batch_set_cfg.restype = C.c_int
     L.mppi_batch_get_cfg.argtypes = [_P, C.POINTER(mppi_batch_cfg)]
     L.mppi_batch_get_cfg.restype = C.c_int
-    L.mppi_batch_autotune.argtypes = [_P, _P, _P, C.c_int32, C.POINTER(mppi_batch_cfg), _D]
+    L.mppi_batch_autotune.argtypes = [_P, _P, _P, C.c_int32, C.c_char_p, C.c_int32, C.POINTER(mppi_batch_cfg), _D,
+                                      C.POINTER(C.c_int32)]
+    L.mppi_autotune.argtypes = [_P, _P, C.c_int32, C.c_char_p, C.c_int32, C.POINTER(mppi_tune_result)]
+    L.mppi_autotune.restype = C.c_int
     L.mppi_batch_autotune.restype = C.c_int
     L.mppi_batch_destroy.argtypes = [_P]
     L.mppi_batch_destroy.restype = None
@@ -344,6 +356,15 @@ class Solver:
     def solve_device(self, d_req: int, d_u0: int):
         _check(lib.mppi_solve_device(self.ctx, _P(d_req), _P(d_u0)), self.ctx)
 
+    def autotune(self, d_req: int, reps: int = 5, cache_path=None, force=False) -> dict:
+        """mppi_autotune: stored or regenerating weighted average for this
+        context's later solves (the warm state is restored afterwards)."""
+        r = mppi_tune_result()
+        path = cache_path.encode() if cache_path else None
+        _check(lib.mppi_autotune(self.ctx, _P(d_req), int(reps), path, TUNE_FORCE if force else 0, C.byref(r)),
+               self.ctx)
+        return r.as_dict()
+
     def solve_device_noalloc(self, d_req: int, d_u0: int):
         """mppi_solve_device on the library's fixed per-GPU workspace."""
         _check(lib.mppi_solve_device_noalloc(self.ctx, _P(d_req), _P(d_u0)), self.ctx)
@@ -402,11 +423,12 @@ class Batch:
     """A batch of registered solvers stepped together (mppi_batch_*)."""
 
     def __init__(self, solvers, stream=None, rollout_waves=0, rollout_groups=0, sample_groups=0,
-                 use_graph=True):
+                 use_graph=True, regen_average=False):
         self.solvers = list(solvers)
         arr = (_P * len(self.solvers))(*[sv.ctx.value if hasattr(sv.ctx, "value") else sv.ctx
                                          for sv in self.solvers])
-        cfg = mppi_batch_cfg(rollout_waves, rollout_groups, sample_groups, 1 if use_graph else 0)
+        cfg = mppi_batch_cfg(rollout_waves, rollout_groups, sample_groups, 1 if use_graph else 0,
+                             1 if regen_average else 0)
         b = _P()
         _bcheck(lib.mppi_batch_create(arr, len(self.solvers), _P(stream) if stream else None,
                                       C.byref(cfg), C.byref(b)))
@@ -420,8 +442,9 @@ class Batch:
             a = (C.c_int32 * len(active))(*[int(i) for i in active])
             _bcheck(lib.mppi_batch_solve_device(self.b, a, len(active), _P(d_reqs), _P(d_u0s)), self.b)
 
-    def set_cfg(self, rollout_waves=0, rollout_groups=0, sample_groups=0, use_graph=True):
-        cfg = mppi_batch_cfg(rollout_waves, rollout_groups, sample_groups, 1 if use_graph else 0)
+    def set_cfg(self, rollout_waves=0, rollout_groups=0, sample_groups=0, use_graph=True, regen_average=False):
+        cfg = mppi_batch_cfg(rollout_waves, rollout_groups, sample_groups, 1 if use_graph else 0,
+                             1 if regen_average else 0)
         _bcheck(lib.mppi_batch_set_cfg(self.b, C.byref(cfg)), self.b)
 
     def get_cfg(self) -> dict:
@@ -429,12 +452,17 @@ class Batch:
         _bcheck(lib.mppi_batch_get_cfg(self.b, C.byref(cfg)), self.b)
         return cfg.as_dict()
 
-    def autotune(self, d_reqs: int, d_u0s: int, reps: int = 3):
+    def autotune(self, d_reqs: int, d_u0s: int, reps: int = 3, cache_path=None, force=False):
+        """mppi_batch_autotune: (best launch shape, its mean step ms, whether
+        it came from the cache)."""
         best = mppi_batch_cfg()
         ms = C.c_double()
-        _bcheck(lib.mppi_batch_autotune(self.b, _P(d_reqs), _P(d_u0s), int(reps), C.byref(best),
-                                        C.byref(ms)), self.b)
-        return best.as_dict(), ms.value
+        hit = C.c_int32()
+        path = cache_path.encode() if cache_path else None
+        _bcheck(lib.mppi_batch_autotune(self.b, _P(d_reqs), _P(d_u0s), int(reps), path,
+                                        TUNE_FORCE if force else 0, C.byref(best), C.byref(ms), C.byref(hit)),
+                self.b)
+        return best.as_dict(), ms.value, bool(hit.value)
 
     def close(self):
         if getattr(self, "b", None):

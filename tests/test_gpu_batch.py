@@ -123,7 +123,9 @@ def test_batch_rejects_bad_arguments():
     B.close()
 
 
-def test_autotuner_picks_a_valid_shape():
+def test_autotuner_picks_a_valid_shape(tmp_path):
+    import json
+
     import torch
     say("autotune")
     inst = make_instances(8, seed=4)
@@ -133,9 +135,25 @@ def test_autotuner_picks_a_valid_shape():
     for i, w in enumerate(inst):
         reqs[i, :13] = torch.from_numpy(w["x0"])
     u0s = torch.zeros((len(S), 4), dtype=torch.float64, device="cuda")
-    best, ms = B.autotune(reqs.data_ptr(), u0s.data_ptr(), reps=2)
-    say("  best", best, ms)
-    assert best["rollout_waves"] in (1, 2, 3, 4) and best["rollout_groups"] > 0 and ms > 0
+    before = [sv.get_warm() for sv in S]
+    cache = str(tmp_path / "tune.json")
+    best, ms, hit = B.autotune(reqs.data_ptr(), u0s.data_ptr(), reps=2, cache_path=cache)
+    say("  best", best, ms, hit)
+    assert not hit and best["rollout_waves"] in (1, 2, 3, 4) and best["rollout_groups"] > 0 and ms > 0
+    assert best["regen_average"] in (0, 1) and (best["rollout_waves"] >= 3 or best["regen_average"] == 0)
+    got = B.get_cfg()
+    assert got["rollout_waves"] == best["rollout_waves"] and got["regen_average"] == best["regen_average"]
+    # the timed steps left every context's warm state as it was
+    for sv, wb in zip(S, before):
+        wa = sv.get_warm()
+        assert wa.solve_index == wb.solve_index and wa.warm == wb.warm
+        assert list(wa.U) == list(wb.U)
+    # the cache holds the choice: a second tuner applies it without timing
+    data = json.load(open(cache))
+    assert len(data) == 1 and list(data.values())[0]["rollout_waves"] == best["rollout_waves"]
+    B.set_cfg()
+    best2, ms2, hit2 = B.autotune(reqs.data_ptr(), u0s.data_ptr(), reps=2, cache_path=cache)
+    assert hit2 and best2 == best and ms2 == pytest.approx(ms, rel=1e-5)
     assert B.get_cfg()["rollout_waves"] == best["rollout_waves"]
     B.close()
 
@@ -238,3 +256,48 @@ def test_batch_against_the_oracle(waves):
     B.close()
     for d, _ in pairs:
         d.close()
+
+
+@pytest.mark.parametrize("precision", [M.FP32, M.FP64])
+@pytest.mark.parametrize("waves", [4, 3])
+def test_batch_regenerating_average_equals_stored(precision, waves, monkeypatch):
+    """A batch whose rollout writes no sample tensor and whose average draws
+    the samples again gives the same first inputs, costs and warm state, bit
+    for bit, as the same batch with the stored tensor; with one-wave rollouts
+    the setting has no effect."""
+    import torch
+    say("batch regen vs stored", precision, "waves", waves)
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", str(waves))
+    inst = make_instances(9, seed=11, objectives=("gate", "contour", "track"), precision=precision)
+    A = [solver_for(w, precision) for w in inst]
+    S = [solver_for(w, precision) for w in inst]
+    BA = M.Batch(A, rollout_waves=waves, regen_average=True)
+    BS = M.Batch(S, rollout_waves=waves)
+    assert BA.get_cfg()["regen_average"] == 1 and BS.get_cfg()["regen_average"] == 0
+    n = len(inst)
+    reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    ua = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    us = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    xs = [w["x0"].copy() for w in inst]
+    for step in range(3):
+        for i, w in enumerate(inst):
+            reqs[i, :13] = torch.from_numpy(xs[i])
+            reqs[i, 13] = step * w["params"]["dt"]
+        BA.solve_device(reqs.data_ptr(), ua.data_ptr())
+        BS.solve_device(reqs.data_ptr(), us.data_ptr())
+        torch.cuda.synchronize()
+        assert torch.equal(ua, us), step
+        for i, w in enumerate(inst):
+            Ja, _ = A[i].read_samples()
+            Js, _ = S[i].read_samples()
+            assert np.array_equal(Ja, Js)
+            assert list(A[i].get_warm().U) == list(S[i].get_warm().U)
+            xs[i] = M.plant_step(w["quad"], xs[i], us[i].cpu().numpy(), w["params"]["dt"], 2)
+    # its solves kept no sample tensor to read
+    with pytest.raises(M.MppiError):
+        A[0].read_samples(want_U=True)
+    S[0].read_samples(want_U=True)
+    BA.set_cfg(rollout_waves=1, regen_average=True)
+    assert BA.get_cfg()["regen_average"] == 0
+    BA.close()
+    BS.close()

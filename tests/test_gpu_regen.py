@@ -161,3 +161,89 @@ def test_regenerated_average_at_extreme_shapes(precision, K, N):
         x = M.plant_step(w["quad"], x, u0a, w["params"]["dt"], 2)
     plain.close()
     regen.close()
+
+
+@pytest.mark.parametrize("objective", ["gate", "contour", "track"])
+def test_regenerated_average_in_the_drawing_one_wave_layout(objective, monkeypatch):
+    """The one-wave rollout that draws its own samples (binary32) writes no
+    sample tensor under the flag; the average draws the samples again with
+    the rollout's counters and arithmetic: the same bits, solve after solve
+    (K + 1 = 3001: a ragged last tile)."""
+    say("regen bits, drawing one-wave layout", objective, "K=3000 N=41")
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "1")
+    monkeypatch.setenv("MPPI_ROLLOUT_DRAW", "1")
+    w = synth.single_solve_workload(K=3000, N=41, objective=objective, seed=24, track_seed=5,
+                                    **{"lambda": 5.0})
+    plain, regen = _pair(w, M.FP32)
+    x = np.array(w["x0"], dtype=np.float64)
+    for step in range(4):
+        t = step * w["params"]["dt"]
+        u0a, Ua, ia = plain.solve(x, t)
+        u0b, Ub, ib = regen.solve(x, t)
+        assert ia["regen_average"] == 0 and ib["regen_average"] == 1
+        assert ib["rollout_waves"] == 1 and ib["rollout_draw"] == 1 and ia["rollout_draw"] == 1
+        np.testing.assert_array_equal(u0a, u0b)
+        np.testing.assert_array_equal(Ua, Ub)
+        for f in ("J_min", "S", "ess", "J_nom", "theta0", "g0", "solve_index"):
+            assert ia[f] == ib[f], f
+        Ja, _ = plain.read_samples()
+        Jb, _ = regen.read_samples()
+        np.testing.assert_array_equal(Ja, Jb)
+        for a, b in zip(_warm_arrays(plain), _warm_arrays(regen)):
+            np.testing.assert_array_equal(a, b)
+        x = M.plant_step(w["quad"], x, u0a, w["params"]["dt"], 2)
+    with pytest.raises(M.MppiError, match="REGEN"):
+        regen.read_samples(want_U=True)
+    plain.close()
+    regen.close()
+
+
+def test_context_autotuner_chooses_restores_and_caches(tmp_path):
+    """mppi_autotune at the benchmark point (four-wave layout): both averages
+    timed, the faster kept, the warm state as before the timed solves, the
+    choice written to the cache and taken from it the next time; the tuned
+    context then solves as an untuned twin does, bit for bit."""
+    import json
+
+    import torch
+    say("context autotuner", "K=8192 N=100")
+    w = synth.single_solve_workload(K=8192, N=100, seed=1)
+    a, b = _pair(w, M.FP32)
+    b.close()
+    twin = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32)
+    x = np.array(w["x0"], dtype=np.float64)
+    a.solve(x, 0.0)
+    twin.solve(x, 0.0)
+    before = _warm_arrays(a)
+    req = torch.zeros(M.REQ_DOUBLES, dtype=torch.float64, device="cuda")
+    req[:13] = torch.from_numpy(x)
+    req[13] = 0.02
+    cache = str(tmp_path / "tune.json")
+    r = a.autotune(req.data_ptr(), reps=2, cache_path=cache)
+    say("  ", r)
+    assert r["from_cache"] == 0 and r["ms_stored"] > 0 and r["ms_regen"] > 0
+    assert r["regen_average"] == (1 if r["ms_regen"] < r["ms_stored"] else 0)
+    for p, q in zip(before, _warm_arrays(a)):
+        np.testing.assert_array_equal(p, q)
+    data = json.load(open(cache))
+    (key, ent), = data.items()
+    assert key.startswith("ctx|gfx") and "|gate|fp32|K13|N6|w4" in key and ent["regen_average"] == r["regen_average"]
+    r2 = a.autotune(req.data_ptr(), reps=2, cache_path=cache)
+    assert r2["from_cache"] == 1 and r2["regen_average"] == r["regen_average"]
+    u0a, Ua, ia = a.solve(x, 0.02)
+    u0t, Ut, it = twin.solve(x, 0.02)
+    assert ia["regen_average"] == r["regen_average"]
+    np.testing.assert_array_equal(u0a, u0t)
+    np.testing.assert_array_equal(Ua, Ut)
+    # where the rollout reads a sample tensor there is one choice, not timed
+    ws = synth.single_solve_workload(K=1000, N=20, seed=2)
+    import os
+    os.environ["MPPI_ROLLOUT_WAVES"] = "2"
+    try:
+        c = M.Solver(ws["quad"], ws["params"], gates=ws["gates"], precision=M.FP32)
+    finally:
+        del os.environ["MPPI_ROLLOUT_WAVES"]
+    rc = c.autotune(req.data_ptr(), reps=2, cache_path=cache)
+    assert rc == {"regen_average": 0, "from_cache": 0, "ms_stored": 0.0, "ms_regen": 0.0}
+    for s in (a, twin, c):
+        s.close()
