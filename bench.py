@@ -30,8 +30,10 @@ sys.path.insert(0, ROOT)
 # cost of Eq. (6)-(7), the switch test and the rate penalty.  A CPU test
 # recounts it.
 FLOPS_PER_ROLLOUT_STEP = 568.1
-# Peak FP32 vector throughput of MI355X (256 CUs, 2.4 GHz, packed FMA)
+# Peak vector throughput of MI355X (256 CUs, 2.4 GHz): FP32 with packed FMA,
+# FP64
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a run
@@ -44,10 +46,10 @@ PEAK_HBM_GBPS = 8000.0
 # or drawing the samples again) and the device sources they were taken on
 # (sha256 of kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order);
 # otherwise the traffic is reported as null.
-TRAFFIC_SOURCES = "5110996d92cfe6c215cdf924be05ad137f4d79b2c004add7a8fda4b49be57ab8"
+TRAFFIC_SOURCES = "c3676bf7b10bae21669e80f88d0a534208a617ec00f4292f5715cf4b158680aa"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.3, 262144.0 / 262144.0
-TRAFFIC_KIB = {("k_rollout4", 0): (224.4, 12836.4), ("k_final", 0): (6578.0, 6.6),
-               ("k_rollout4", 1): (224.3, 38.0), ("k_final", 1): (195.2, 6.6)}
+TRAFFIC_KIB = {("k_rollout4", 0): (224.1, 12836.4), ("k_final", 0): (6575.5, 6.6),
+               ("k_rollout4", 1): (224.1, 38.0), ("k_final", 1): (212.7, 6.6)}
 TRAFFIC_WORKLOADS = {(8192, 100, "fp32", 0), (8192, 100, "fp32", 1)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
@@ -595,6 +597,8 @@ def main():
         avg_bytes -= K * N * 16
     flops = FLOPS_PER_ROLLOUT_STEP * K * N
     achieved = flops / (roll_ms * 1e-3) / 1e12
+    # the rollout computes in the precision of the solve
+    peak = PEAK_FP32_TFLOPS if prec == M.FP32 else PEAK_FP64_TFLOPS
     out = {
         "metric": f"rollout-steps/sec (K*N/s) at K={K},N={N}",
         "value": value,
@@ -614,8 +618,8 @@ def main():
                    "average": "regenerated" if info["regen_average"] else "stored samples"},
         "kernels_ms": {"sample": float(kern_ms[0]), "rollout": roll_ms, "average": float(kern_ms[2]),
                        "solves_timed": n_prof},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_bytes(rk, wl),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic_bytes(rk, wl),
                      "kernel": rk, "flops_per_launch": flops},
         # the weighted average streams the sample tensor once: HBM-bound
         "average_kernel": {"bound": "hbm", "kernel": "k_final", "bytes_per_launch": avg_bytes,

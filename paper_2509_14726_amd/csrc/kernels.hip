@@ -2224,12 +2224,12 @@ template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
 // nomV, with the same operations as the rollout's draw, so the weighted sums
 // are the same bit for bit: Philox and Box-Muller arithmetic in place of
 // 16 B (20 B contouring) of HBM traffic per sample and step.
-template <typename Real, typename Acc, bool HAS_V, bool REGEN>
+template <typename Real, typename Acc, bool HAS_V, bool REGEN, int UR = 4>
 __device__ __forceinline__ void final_body(const KArgs &a, int k)
 {
     constexpr int C = HAS_V ? 5 : 4;
     constexpr int NV = C + 2;
-    constexpr int NT = kFinalThreads, NWV = NT / 64, UR = 4;
+    constexpr int NT = kFinalThreads, NWV = NT / 64;
     typedef typename Vec4<Real>::T R4;
     static_assert(NV <= NWV, "one wave per reduced value");
     __shared__ Acc s_part[NV][NT];
@@ -2431,10 +2431,10 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     }
 }
 
-template <typename Real, typename Acc, bool HAS_V, bool REGEN>
+template <typename Real, typename Acc, bool HAS_V, bool REGEN, int UR>
 __global__ __launch_bounds__(kFinalThreads) void k_final(KArgs a)
 {
-    final_body<Real, Acc, HAS_V, REGEN>(a, blockIdx.x);
+    final_body<Real, Acc, HAS_V, REGEN, UR>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- batched (persistent)
@@ -2651,10 +2651,22 @@ hipError_t launch_setup(const KArgs &a, bool fp64, hipStream_t st)
 template <typename Real, typename Acc, bool HAS_V>
 static hipError_t launch_average_t(const KArgs &a, hipStream_t st)
 {
-    if (a.regen)
-        hipLaunchKernelGGL((k_final<Real, Acc, HAS_V, true>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_final<Real, Acc, HAS_V, false>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
+    // binary32: all of a thread's samples in one round of loads when they are
+    // at most eight, else (and in binary64, whose registers hold half as
+    // many) rounds of four with the next round's loads in flight; the
+    // accumulation order, and so the result, is the same either way
+    const bool one_round = sizeof(Real) == 4 && a.K <= 8 * kFinalThreads;
+    if (a.regen) {
+        if (one_round)
+            hipLaunchKernelGGL((k_final<Real, Acc, HAS_V, true, 8>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_final<Real, Acc, HAS_V, true, 4>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
+    } else {
+        if (one_round)
+            hipLaunchKernelGGL((k_final<Real, Acc, HAS_V, false, 8>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_final<Real, Acc, HAS_V, false, 4>), dim3(a.N), dim3(kFinalThreads), 0, st, a);
+    }
     return hipGetLastError();
 }
 
