@@ -182,6 +182,16 @@ def cpu_baseline(w, seconds: float = 12.0, single_seconds: float = 6.0):
             "thread_cap": "16 threads: the CPU share of one GPU on the GPU host"}
 
 
+def _timing_stream():
+    """The stream the extras time on: the current one, or a new one when the
+    current one is the null stream (a context given the null stream makes a
+    stream of its own, and events on the null stream would then time
+    nothing of it)."""
+    import torch
+    s = torch.cuda.current_stream()
+    return s if s.cuda_stream != 0 else torch.cuda.Stream()
+
+
 def batched_bench(steps: int = 20, n: int = 256):
     """256 uneven instances (K in {1024..16384}, N in [30, 150], 5-12 gates),
     one persistent launch sequence per step under a captured HIP graph, launch
@@ -192,7 +202,7 @@ def batched_bench(steps: int = 20, n: int = 256):
     specs = synth.batch_instances(n)
     ws = [synth.single_solve_workload(K=d["K"], N=d["N"], n_gates=d["n_gates"], track_seed=d["track_seed"],
                                       seed=d["seed"]) for d in specs]
-    stream = torch.cuda.current_stream()
+    stream = _timing_stream()
     solvers = [M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32) for w in ws]
     B = M.Batch(solvers, stream=stream.cuda_stream)
     reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
@@ -314,7 +324,7 @@ def paper_table_config(steps: int = 200):
     for name, over in (("thrust_input", {}),
                        ("rate_input", dict(input_model=M.INPUT_RATE, rate_lim=(-10.0, 10.0), sigma=(20.0,) * 4))):
         w = synth.single_solve_workload(K=8192, N=20, dt=0.03, seed=1, **{"lambda": 0.01}, **over)
-        stream = torch.cuda.current_stream()
+        stream = _timing_stream()
         sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32, stream=stream.cuda_stream)
         x0 = w["x0"] if not over else np.concatenate([w["x0"], np.full(4, hover)])
         req = torch.zeros((steps, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
@@ -322,11 +332,8 @@ def paper_table_config(steps: int = 200):
         req[:, M.REQ_THRUST:M.REQ_THRUST + 4] = hover
         req[:, 13] = torch.arange(steps, dtype=torch.float64, device="cuda") * 0.03
         u0 = torch.zeros((steps, 4), dtype=torch.float64, device="cuda")
-        # a few hundred warm-up solves: the legs before this one leave the GPU
-        # idle for seconds (host-driven flights), and its clocks ramp up again
-        for r in range(3):
-            for i in range(steps):
-                sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
+        for i in range(10):
+            sv.solve_device(req[i].data_ptr(), u0[i].data_ptr())
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -354,7 +361,7 @@ def fp64_solve(steps: int = 100):
     from paper_2509_14726_amd import mppi as M
     from paper_2509_14726_amd import synth
     w = synth.single_solve_workload(K=8192, N=100, seed=1)
-    stream = torch.cuda.current_stream()
+    stream = _timing_stream()
     sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP64, stream=stream.cuda_stream)
     req = torch.zeros((steps + 10, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
     req[:, :13] = torch.from_numpy(w["x0"]).cuda()
@@ -383,7 +390,7 @@ def large_bench(steps: int = 5):
     from paper_2509_14726_amd import mppi as M
     from paper_2509_14726_amd import synth
     w = synth.single_solve_workload(K=262144, N=200, dt=0.01, n_gates=12, track_seed=5, seed=5)
-    stream = torch.cuda.current_stream()
+    stream = _timing_stream()
     sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32, stream=stream.cuda_stream)
     req = torch.zeros((steps + 1, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
     req[:, :13] = torch.from_numpy(w["x0"]).cuda()
@@ -455,7 +462,7 @@ def layout_sweep(steps: int = 30):
     import torch
     from paper_2509_14726_amd import mppi as M
     from paper_2509_14726_amd import synth
-    stream = torch.cuda.current_stream()
+    stream = _timing_stream()
     rows = []
     for N in (50, 100, 200):
         for K in (8192, 16383, 16384, 32767, 32768, 65000):
