@@ -117,7 +117,8 @@ typedef struct {
      * [t_min, t_max] over the step; the contouring acceleration likewise to
      * dv_lim and to the range that keeps the progress speed within
      * [0, v_max].  The rate model runs the one-wave rollout with a separate
-     * sampling kernel, and batches and servers refuse it. */
+     * sampling kernel; a batch or server holding such a context runs all its
+     * contexts with one-wave rollouts. */
     int32_t input_model;
     int32_t pad_;
     double rate_lim[2];   /* thrust-rate bounds, N/s (lower <= 0 <= upper)    */
@@ -450,9 +451,10 @@ typedef struct {
 mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_server_cfg *cfg,
                                mppi_server **out);
 /* Queue a solve of drone `drone` from state x0 at time t_now (the same
- * arguments as mppi_solve); t_arrival only stamps the result.  MPPI_E_NOMEM
+ * arguments as mppi_solve: 13 doubles, or 17 for a drone with the rate input,
+ * its four thrusts last); t_arrival only stamps the result.  MPPI_E_NOMEM
  * when that drone's workspace alone exceeds the arena. */
-mppi_status mppi_server_submit(mppi_server *s, int32_t drone, const double x0[13], double t_now, double t_arrival,
+mppi_status mppi_server_submit(mppi_server *s, int32_t drone, const double *x0, double t_now, double t_arrival,
                                uint64_t *ticket);
 /* Retire finished launches (non-blocking) and launch what can be admitted;
  * `now` is the caller's clock, used only for the result stamps. */

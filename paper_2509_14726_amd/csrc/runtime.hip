@@ -1002,6 +1002,7 @@ struct mppi_batch {
     bool copy_pending = false;
     int n_cu = 256;
     int total_tiles = 0;
+    bool has_rate = false;       // a context takes the rate input: one-wave rollouts only
     std::string err;
 };
 
@@ -1040,6 +1041,9 @@ static hipError_t resolve_cfg(mppi_batch *b)
     int waves = c.rollout_waves;
     const int cu = b->n_cu, tiles = b->total_tiles;
     if (waves < 1 || waves > 4) waves = tiles <= cu ? 4 : (tiles <= 2 * cu ? (b->fp64 ? 2 : 4) : 1);
+    // a rate sample follows its thrust chain, which the sample kernel walks
+    // per sample: the one-wave rollout reads it
+    if (b->has_rate) waves = 1;
     // the regenerating average where the batch's rollout draws the samples
     // (batched contexts take thrust as the input, one iteration and no
     // control-cost term)
@@ -1111,9 +1115,8 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d is NULL", i);
         if (ctxs[i]->fp64 != ctxs[0]->fp64) return bfail(nullptr, MPPI_E_INVAL, "contexts differ in precision");
-        if (ctxs[i]->n_iter != 1 || ctxs[i]->args.ctrl_cost != 0.0 || ctxs[i]->args.input_model != MPPI_INPUT_THRUST)
-            return bfail(nullptr, MPPI_E_INVAL,
-                         "context %d: batches run the thrust input, one iteration, no control-cost term", i);
+        if (ctxs[i]->n_iter != 1 || ctxs[i]->args.ctrl_cost != 0.0)
+            return bfail(nullptr, MPPI_E_INVAL, "context %d: batches run one iteration and no control-cost term", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d registered twice", i);
     }
@@ -1121,6 +1124,7 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
     if (!b) return bfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
     b->ctxs.assign(ctxs, ctxs + n);
     b->fp64 = ctxs[0]->fp64;
+    for (int i = 0; i < n; ++i) b->has_rate = b->has_rate || ctxs[i]->args.input_model == MPPI_INPUT_RATE;
     b->cfg = cfg ? *cfg : mppi_batch_cfg{0, 0, 0, 1, 0};
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
@@ -1359,7 +1363,7 @@ mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u
     const mppi_batch_cfg saved = b->cfg;
     std::vector<mppi_batch_cfg> cand;
     const int cu = b->n_cu;
-    for (int waves = 1; waves <= 4; ++waves) {
+    for (int waves = 1; waves <= (b->has_rate ? 1 : 4); ++waves) {
         const int rg_mult[] = {1, 2, 4, 8};
         for (int rm : rg_mult) {
             if (waves >= 2 && rm > 2) continue;  // one or two LDS rings fit one CU
@@ -1477,7 +1481,7 @@ struct Arena {
 
 struct Request {
     uint64_t ticket;
-    double x0[13];
+    double x0[17];              // 13 states, then the four thrusts of the rate input
     double t_now, t_arrival;
 };
 
@@ -1605,6 +1609,7 @@ static mppi_status admit(mppi_server *s, double now, int32_t *n_launched)
             const int i = (int)active.size();
             for (int c = 0; c < 13; ++c) sl.h_req[kReqDoubles * i + c] = rq.x0[c];
             sl.h_req[kReqDoubles * i + 13] = rq.t_now;
+            for (int c = 0; c < 4; ++c) sl.h_req[kReqDoubles * i + kReqThrust + c] = rq.x0[13 + c];
             active.push_back(d);
             ws.push_back(s->arena_base + off);
             sl.flight.push_back(InFlight{d, rq.ticket, rq.t_arrival, now, off});
@@ -1648,10 +1653,8 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
     for (int i = 0; i < n; ++i) {
         if (!drones[i] || !drones[i]->external_ws)
             return sfail(nullptr, MPPI_E_INVAL, "drone %d: context must be created with MPPI_FLAG_EXTERNAL_WORKSPACE", i);
-        if (drones[i]->n_iter != 1 || drones[i]->args.ctrl_cost != 0.0 ||
-            drones[i]->args.input_model != MPPI_INPUT_THRUST)
-            return sfail(nullptr, MPPI_E_INVAL,
-                         "drone %d: served solves run the thrust input, one iteration, no control-cost term", i);
+        if (drones[i]->n_iter != 1 || drones[i]->args.ctrl_cost != 0.0)
+            return sfail(nullptr, MPPI_E_INVAL, "drone %d: served solves run one iteration and no control-cost term", i);
     }
     mppi_server *s = new (std::nothrow) mppi_server();
     if (!s) return sfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
@@ -1695,12 +1698,13 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
     return MPPI_OK;
 }
 
-mppi_status mppi_server_submit(mppi_server *s, int32_t drone, const double x0[13], double t_now, double t_arrival,
+mppi_status mppi_server_submit(mppi_server *s, int32_t drone, const double *x0, double t_now, double t_arrival,
                                uint64_t *ticket)
 {
     if (!s || !x0) return sfail(s, MPPI_E_INVAL, "server and x0 are required");
     if (drone < 0 || drone >= (int)s->drones.size()) return sfail(s, MPPI_E_INVAL, "drone %d out of range", drone);
-    if (!finite_all(x0, 13) || !isfinite(t_now)) return sfail(s, MPPI_E_INVAL, "x0 and t_now must be finite");
+    const int nx = s->drones[drone]->args.input_model == MPPI_INPUT_RATE ? 17 : 13;
+    if (!finite_all(x0, nx) || !isfinite(t_now)) return sfail(s, MPPI_E_INVAL, "x0 and t_now must be finite");
     const double qn = x0[6] * x0[6] + x0[7] * x0[7] + x0[8] * x0[8] + x0[9] * x0[9];
     if (!(qn > 0.0)) return sfail(s, MPPI_E_INVAL, "quaternion of x0 has zero norm");
     if (align_up(s->drones[drone]->ws_bytes, 256) > s->arena.size)
@@ -1708,7 +1712,8 @@ mppi_status mppi_server_submit(mppi_server *s, int32_t drone, const double x0[13
                      s->drones[drone]->ws_bytes, s->arena.size);
     Request r;
     r.ticket = s->next_ticket++;
-    memcpy(r.x0, x0, sizeof r.x0);
+    memset(r.x0, 0, sizeof r.x0);
+    memcpy(r.x0, x0, sizeof(double) * nx);
     r.t_now = t_now;
     r.t_arrival = t_arrival;
     s->queue[drone].push_back(r);

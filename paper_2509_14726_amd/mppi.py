@@ -497,7 +497,7 @@ class Server:
         self._buf = (mppi_result * 4096)()
 
     def submit(self, drone: int, x0, t_now: float, t_arrival: float) -> int:
-        x = _f64(x0, 13)
+        x = _f64(x0, self.solvers[drone].nx)
         t = C.c_uint64()
         _scheck(lib.mppi_server_submit(self.s, int(drone), _dp(x), float(t_now), float(t_arrival),
                                        C.byref(t)), self.s)

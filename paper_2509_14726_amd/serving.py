@@ -4,7 +4,8 @@ batches them as launch slots and device memory free up.
 
 Each drone has its own seeded track, K in {2048, 8192}, N in {50, 100} and a
 gate-progress or contouring objective (50/50), fixed for the drone (its warm
-start needs a stable shape).  Between two of its requests a drone's FP64 host
+start needs a stable shape), thrust as the sampled input with 0.15 N of
+noise per rotor and lambda = 10.  Between two of its requests a drone's FP64 host
 plant advances with the last control it received (RK4, substeps of at most
 5 ms).  A drone whose state leaves a sane envelope (non-finite, more than
 1 km from the origin, or spinning faster than 1000 rad/s) is counted as a
@@ -31,7 +32,10 @@ def drone_workloads(n_drones: int, seed: int = 4):
         K = int(rng.choice([2048, 8192]))
         N = int(rng.choice([50, 100]))
         obj = "gate" if rng.uniform() < 0.5 else "contour"
-        w = synth.single_solve_workload(K=K, N=N, objective=obj, seed=4000 + d, track_seed=4000 + d)
+        # thrust noise of 0.15 N with lambda = 10: with 1 N per rotor and step
+        # the samples spin this airframe and the drones tumble
+        w = synth.single_solve_workload(K=K, N=N, objective=obj, seed=4000 + d, track_seed=4000 + d,
+                                        sigma=(0.15,) * 4, **{"lambda": 10.0})
         w["params"] = dict(w["params"], flags=M.FLAG_EXTERNAL_WORKSPACE)
         out.append(w)
     return out

@@ -3,8 +3,9 @@ Sec. III-A; contouring with the progress acceleration as input, Eq. (9))
 against the FP64 oracle, through the C ABI: closed loops of warm-started
 solves with the rate model's host plant for the three objectives in both
 precisions, the operating point of the paper's simulation table (Table I:
-8192 samples, 20 steps of 0.03 s, lambda = 0.01), and the layout and
-refusal rules of the model."""
+8192 samples, 20 steps of 0.03 s, lambda = 0.01), the layout rule of the
+model, rate contexts in batches and served by a server against their solo
+twins, and the allocation-free entry point."""
 import sys
 
 import numpy as np
@@ -73,18 +74,102 @@ def test_rate_model_at_the_paper_table_operating_point(precision):
     dev.close()
 
 
-def test_rate_model_is_refused_by_batches_and_servers():
-    w = rate_workload(256, 10)
-    sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32)
-    with pytest.raises(M.MppiError) as e:
-        M.Batch([sv])
-    assert e.value.status == M.E_INVAL
-    w2 = rate_workload(256, 10, flags=M.FLAG_EXTERNAL_WORKSPACE)
-    sv2 = M.Solver(w2["quad"], w2["params"], gates=w2["gates"], precision=M.FP32)
-    with pytest.raises(M.MppiError):
-        M.Server([sv2], budget_bytes=1 << 26)
-    sv.close()
-    sv2.close()
+def _mixed_instances(external=False):
+    """Three rate contexts (one per objective) and one thrust context, of
+    uneven sizes (ragged last tiles)."""
+    out = []
+    for i, (obj, K, N, rate) in enumerate([("gate", 1000, 30, True), ("contour", 1500, 20, True),
+                                           ("track", 700, 40, True), ("gate", 1200, 25, False)]):
+        over = dict(seed=60 + i, track_seed=60 + i, **{"lambda": 20.0})
+        w = rate_workload(K, N, obj, **over) if rate else synth.single_solve_workload(K=K, N=N, objective=obj,
+                                                                                      **over)
+        if external:
+            w["params"] = dict(w["params"], flags=M.FLAG_EXTERNAL_WORKSPACE)
+        out.append(w)
+    return out
+
+
+def _solver(w):
+    return M.Solver(w["quad"], w["params"], gates=w["gates"], path=w.get("path"), path_len=w.get("path_len", 0.0),
+                    xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0), precision=M.FP32)
+
+
+def _plant(w, x, u0):
+    if x.size == 17:
+        return M.plant_step_rate(w["quad"], x, u0, w["params"]["dt"], 2)
+    return M.plant_step(w["quad"], x, u0, w["params"]["dt"], 2)
+
+
+def test_rate_contexts_in_a_batch_match_their_solo_solves(monkeypatch):
+    """A batch holding rate contexts runs every context with one-wave rollouts
+    (the sample kernel walks each rate sample's thrust chain); each context's
+    first inputs, costs and warm state equal its solo twin's, bit for bit,
+    over three warm-started steps (the solo twins forced to one wave too)."""
+    import torch
+    say("rate contexts in a batch vs solo")
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "1")
+    inst = _mixed_instances()
+    solo = [_solver(w) for w in inst]
+    bat = [_solver(w) for w in inst]
+    B = M.Batch(bat, rollout_waves=4)
+    assert B.get_cfg()["rollout_waves"] == 1
+    n = len(inst)
+    reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    u0s = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    xs = [np.array(w["x0"], dtype=np.float64) for w in inst]
+    for step in range(3):
+        for i, w in enumerate(inst):
+            reqs[i].zero_()
+            reqs[i, :13] = torch.from_numpy(xs[i][:13])
+            reqs[i, 13] = step * w["params"]["dt"]
+            if xs[i].size == 17:
+                reqs[i, M.REQ_THRUST:M.REQ_THRUST + 4] = torch.from_numpy(xs[i][13:])
+        B.solve_device(reqs.data_ptr(), u0s.data_ptr())
+        torch.cuda.synchronize()
+        got = u0s.cpu().numpy()
+        for i, w in enumerate(inst):
+            u0, U, info = solo[i].solve(xs[i], step * w["params"]["dt"])
+            assert np.array_equal(got[i], u0), (step, i, got[i], u0)
+            Jb, _ = bat[i].read_samples()
+            Js, _ = solo[i].read_samples()
+            assert np.array_equal(Jb, Js), (step, i)
+            wb, ws = bat[i].get_warm(), solo[i].get_warm()
+            assert list(wb.U) == list(ws.U) and list(wb.V) == list(ws.V) and wb.vtheta == ws.vtheta
+            xs[i] = _plant(w, xs[i], u0)
+    B.close()
+    for sv in solo + bat:
+        sv.close()
+
+
+def test_served_rate_drones_match_their_solo_solves(monkeypatch):
+    """Rate drones (17-state requests) served in mixed launches with a thrust
+    drone give the first inputs their solo twins give, bit for bit."""
+    say("served rate drones vs solo")
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "1")
+    ws = _mixed_instances(external=True)
+    wa = _mixed_instances(external=False)
+    served = [_solver(w) for w in ws]
+    alone = [_solver(w) for w in wa]
+    S = M.Server(served, budget_bytes=256 * 2 ** 20, n_slots=2, max_batch=3)
+    xs = [np.array(w["x0"], dtype=np.float64) for w in wa]
+    expected, tick = {}, {}
+    for k in range(3):
+        for d, w in enumerate(wa):
+            t = k * w["params"]["dt"]
+            u0, _, _ = alone[d].solve(xs[d], t)
+            expected[(d, k)] = u0
+            tick[S.submit(d, xs[d].copy(), t, float(k))] = (d, k)
+            xs[d] = _plant(w, xs[d], u0)
+        S.drain(1e9)
+    res = S.poll()
+    assert len(res) == 3 * len(wa)
+    for r in res:
+        d, k = tick[r["ticket"]]
+        assert r["status"] == M.OK
+        assert np.array_equal(np.array(r["u0"]), expected[(d, k)]), (d, k)
+    S.close()
+    for sv in served + alone:
+        sv.close()
 
 
 def test_rate_model_on_the_fixed_workspace_matches_its_own_workspace():
