@@ -314,6 +314,11 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
         double T[4];
         for (int i = 0; i < 4; ++i) T[i] = a.req[kReqThrust + i];
         double v = rate_speed0(a, w, warm, shift);
+        // the range bounds divide by dt: multiplied by 1/dt instead (a binary64
+        // quotient is a long instruction sequence; the bound moves by at most
+        // one unit in the last place of binary64)
+        const double inv_dt = 1.0 / a.dt;
+#pragma unroll 2
         for (int k = 0; k < N; ++k) {
             const R4 us = s_us[k];
             const Real ust[4] = {us.x, us.y, us.z, us.w};
@@ -326,7 +331,7 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
             for (int i = 0; i < 4; ++i) {
                 const Real raw = noisy ? ust[i] + sg[i] * z[i] : ust[i];
                 const Real r = clampT(raw, rlo, rhi);
-                u[i] = (Real)clampT((double)r, (a.t_min - T[i]) / a.dt, (a.t_max - T[i]) / a.dt);
+                u[i] = (Real)clampT((double)r, (a.t_min - T[i]) * inv_dt, (a.t_max - T[i]) * inv_dt);
                 T[i] = T[i] + a.dt * (double)u[i];
             }
             R4 o;
@@ -338,7 +343,7 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
                 if (noisy) zv = normal1<Real>((uint32_t)m, (uint32_t)k, s, 1u, a.seed_lo, a.seed_hi);
                 const Real raw = noisy ? s_vs[k] + (Real)a.sigma_v * zv : s_vs[k];
                 const Real r = clampT(raw, dlo, dhi);
-                const Real acc = (Real)clampT((double)r, (0.0 - v) / a.dt, (a.v_max - v) / a.dt);
+                const Real acc = (Real)clampT((double)r, (0.0 - v) * inv_dt, (a.v_max - v) * inv_dt);
                 v = v + a.dt * (double)acc;
                 if (noisy) ((Real *)a.vctrl)[(size_t)k * (size_t)K + (size_t)m] = acc;
                 else ((Real *)a.nomV)[k] = acc;
