@@ -19,6 +19,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -1790,16 +1791,21 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                 }
 #pragma unroll
                 for (int i = 0; i < 3; ++i) w[i] += dw[i];
-                // the body rates after the step ride in the free fourth
-                // component of stages 1-3: the attitude wave adds their
-                // rate-limit term
-                stv[0].w = Real(0);
-                stv[1].w = w[0];
-                stv[2].w = w[1];
-                stv[3].w = w[2];
 #pragma unroll
-                for (int st = 0; st < 4; ++st) slot[st][lane] = stv[st];
+                for (int st = 0; st < 4; ++st) {
+                    stv[st].w = Real(0);
+                    slot[st][lane] = stv[st];
+                }
                 if (OBJ != OBJ_GATE) J.add(term);
+                // rate limit on the body rates after the step (here rather than
+                // on the attitude wave, whose recurrence sets the pipeline's pace)
+                Real rl = Real(0);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const Real e = fmax(fabs(w[i]) - w_max, Real(0));
+                    rl += w_lim * e * e;
+                }
+                J.add(rl);
             };
             // the chunk's LDS inputs are loaded before the first step uses them
             if (ke - kb == B) {
@@ -1862,14 +1868,6 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
 #pragma unroll
                 for (int i = 0; i < 4; ++i) q[i] += dq[i];
                 renormalize(q);
-                // rate limit on the body rates after the step
-                Real term = Real(0);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const Real e = fmax(fabs(wst[1 + i].w) - w_max, Real(0));
-                    term += w_lim * e * e;
-                }
-                J.add(term);
             };
             if (ke - kb == B) {
                 R4 wpre[B][4];
@@ -1890,7 +1888,10 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
         } else if (wave == 2 && c >= 3 && c <= nch + 2) {
             // position and velocity over chunk c - 3
             const int kb = (c - 3) * B, ke = min(N, kb + B);
-            auto trans_step = [&](const int k, const int j, const Real fm, const R4 *qstage) {
+            // drag is a launch constant: the branch sits outside the step, so the
+            // stages of a step (independent without drag) schedule together
+            auto trans_step = [&](const int k, const int j, const Real fm, const R4 *qstage, auto drag_tag) {
+                constexpr bool DRAG = decltype(drag_tag)::value;
                 if (OBJ == OBJ_TRACK) {
                     int r = i0 + k;
                     if (r > a.R - 1) r = a.R - 1;
@@ -1923,7 +1924,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                     kv[0] = fm2 * (qq.y * qq.w + qq.x * qq.z);
                     kv[1] = fm2 * (qq.z * qq.w - qq.x * qq.y);
                     kv[2] = fm * r3z - M.g;
-                    if (M.drag) {
+                    if (DRAG) {
                         const Real qw = qq.x, qx = qq.y, qy = qq.z, qz = qq.w;
                         const Real r11 = Real(1) - Real(2) * (qy * qy + qz * qz), r12 = Real(2) * (qx * qy - qw * qz);
                         const Real r21 = Real(2) * (qx * qy + qw * qz), r22 = Real(1) - Real(2) * (qx * qx + qz * qz);
@@ -1974,14 +1975,20 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
 #pragma unroll
                     for (int st = 0; st < 4; ++st) qpre[j][st] = s_q[(c - 3) & 1][j][st][lane];
                 }
+                if (M.drag) {
 #pragma unroll
-                for (int j = 0; j < B; ++j) trans_step(kb + j, j, fpre[j], qpre[j]);
+                    for (int j = 0; j < B; ++j) trans_step(kb + j, j, fpre[j], qpre[j], std::true_type{});
+                } else {
+#pragma unroll
+                    for (int j = 0; j < B; ++j) trans_step(kb + j, j, fpre[j], qpre[j], std::false_type{});
+                }
             } else {
                 for (int k = kb; k < ke; ++k) {
                     R4 qst[4];
 #pragma unroll
                     for (int st = 0; st < 4; ++st) qst[st] = s_q[(c - 3) & 1][k - kb][st][lane];
-                    trans_step(k, k - kb, s_in[(c - 3) % 4][k - kb][lane].x, qst);
+                    if (M.drag) trans_step(k, k - kb, s_in[(c - 3) % 4][k - kb][lane].x, qst, std::true_type{});
+                    else trans_step(k, k - kb, s_in[(c - 3) % 4][k - kb][lane].x, qst, std::false_type{});
                 }
             }
             if (POS && c == nch + 2) {
