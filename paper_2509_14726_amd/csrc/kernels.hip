@@ -1856,8 +1856,10 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
 #pragma unroll
                         for (int i = 0; i < 4; ++i) dq[i] += Real(2) * kq[i];
                     } else {
+                        // the last stage closes the step in one multiply-add
+                        // per component (this wave's recurrence sets the pace)
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) dq[i] = dt12 * (dq[i] + kq[i]);
+                        for (int i = 0; i < 4; ++i) q[i] = q[i] + dt12 * (dq[i] + kq[i]);
                     }
                     if (st < 3) {
                         const Real hq = st < 2 ? h4 : h2;
@@ -1865,8 +1867,6 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
                         for (int i = 0; i < 4; ++i) qs[i] = q[i] + hq * kq[i];
                     }
                 }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) q[i] += dq[i];
                 renormalize(q);
             };
             if (ke - kb == B) {
