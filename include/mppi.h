@@ -207,7 +207,10 @@ typedef struct {
                                           at the previous solve's time          */
 } mppi_warm;
 
-/* Create a solver context.  Validates every argument (K, N, dt, lambda, sigma,
+/* Create a solver context: the inputs of Alg. 1 (sample count M = K, horizon
+ * K = N, temperature lambda, noise covariance Sigma, the waypoints / path /
+ * reference of the objective; Sec. III-B and IV) bound to the quadrotor of
+ * Eq. (2).  Validates every argument (K, N, dt, lambda, sigma,
  * objective and the data it needs: 1..MPPI_G_MAX gates, P >= 2 path points,
  * R >= 1 reference rows), copies the problem data to the device and allocates all
  * device buffers: the N x K x 4 sample tensor (step-major: sample m of step k
@@ -227,10 +230,13 @@ mppi_status mppi_create(const mppi_params *params, const mppi_quad *quad,
                         const mppi_problem *problem, void *stream,
                         const mppi_allocator *allocator, mppi_ctx **out);
 
-/* Release every device and host resource of the context.  NULL is a no-op. */
+/* Release every device and host resource of the context (the end of the
+ * receding-horizon loop of Alg. 1).  NULL is a no-op. */
 void mppi_destroy(mppi_ctx *ctx);
 
-/* One MPPI step from host memory, synchronous on the context stream.
+/* One MPPI step from host memory, synchronous on the context stream: one
+ * pass of Alg. 1's loop body (sample Eq. (3), roll out Eq. (2) with the costs
+ * of Eq. (6)-(9), weigh Eq. (4), update Eq. (5), shift the warm start).
  * x0: current state (finite, |q| > 0): 13 doubles, or 17 for MPPI_INPUT_RATE
  * (the measured rotor thrusts appended).  t_now: time of x0 in s; the previous
  * solution is shifted by max(1, round((t_now - t_prev)/dt)) steps and, for
