@@ -269,15 +269,18 @@ __device__ void solve_head(const KArgs &a)
 
 // ---------------------------------------------------------------- sample
 
-// One block of 256 samples over all N steps; block 0 also runs the head.  The
-// shifted warm start (R4 per step) is staged in LDS once, so each step is the
-// noise and the clipped samples of 256 samples with one coalesced store.
-template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body(const KArgs &a, int bx)
+// One block of 256 samples over the steps [k0, k1); the block of the first
+// samples and steps also runs the head.  The shifted warm start (R4 per step)
+// is staged in LDS once, so each step is the noise and the clipped samples of
+// 256 samples with one coalesced store.  Every sample and step is drawn from
+// its own counters, so any split of the steps gives the same samples.
+template <typename Real, bool HAS_V>
+__device__ __forceinline__ void sample_body(const KArgs &a, int bx, int k0, int k1)
 {
     typedef typename Vec4<Real>::T R4;
     __shared__ R4 s_us[kNMax];
     __shared__ Real s_vs[HAS_V ? kNMax : 1];
-    if (bx == 0) solve_head(a);
+    if (bx == 0 && k0 == 0) solve_head(a);
 
     // nominal of this solve: the previous solution shifted, or hover (cold)
     const DevWarm *w = a.warm;
@@ -285,7 +288,7 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
     const int shift = warm_shift(a, warm, a.req[13], w->t_prev);
     const uint32_t s = w->s;
     const int N = a.N, K = a.K;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += blockDim.x) {
         int src = k + shift;
         if (src > N - 1) src = N - 1;
         R4 o;
@@ -301,26 +304,18 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
     const int m = bx * 256 + threadIdx.x;
     const Real tmin = (Real)a.t_min, tmax = (Real)a.t_max;
     if (a.input_model == INPUT_RATE) {
-        // the paper's input: thrust rates clipped to their bounds and to the
-        // range that keeps each thrust within [t_min, t_max] over the step,
-        // following the thrust chain from the measured thrusts; contouring's
-        // progress acceleration likewise keeps the speed within [0, v_max].
-        // The chains are integrators and run in binary64 in every precision
-        // (their rounding would otherwise accumulate over the horizon).
+        // the paper's input: thrust rates (and contouring's progress
+        // acceleration) clipped to their bounds.  The clip to the range that
+        // keeps each thrust within [t_min, t_max] (the speed within [0, v_max])
+        // follows the sample's own thrust chain: the rollout applies it step
+        // by step, where that chain is integrated, and writes the result back.
         if (m > K) return;
         const bool noisy = m < K;
         const Real rlo = (Real)a.rate_lim[0], rhi = (Real)a.rate_lim[1];
         const Real dlo = (Real)a.dv_lim[0], dhi = (Real)a.dv_lim[1];
         const Real sg[4] = {(Real)a.sigma[0], (Real)a.sigma[1], (Real)a.sigma[2], (Real)a.sigma[3]};
-        double T[4];
-        for (int i = 0; i < 4; ++i) T[i] = a.req[kReqThrust + i];
-        double v = rate_speed0(a, w, warm, shift);
-        // the range bounds divide by dt: multiplied by 1/dt instead (a binary64
-        // quotient is a long instruction sequence; the bound moves by at most
-        // one unit in the last place of binary64)
-        const double inv_dt = 1.0 / a.dt;
 #pragma unroll 2
-        for (int k = 0; k < N; ++k) {
+        for (int k = k0; k < k1; ++k) {
             const R4 us = s_us[k];
             const Real ust[4] = {us.x, us.y, us.z, us.w};
             Real z[4] = {Real(0), Real(0), Real(0), Real(0)};
@@ -329,12 +324,7 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
                 z[0] = n4.z0; z[1] = n4.z1; z[2] = n4.z2; z[3] = n4.z3;
             }
             Real u[4];
-            for (int i = 0; i < 4; ++i) {
-                const Real raw = noisy ? ust[i] + sg[i] * z[i] : ust[i];
-                const Real r = clampT(raw, rlo, rhi);
-                u[i] = (Real)clampT((double)r, (a.t_min - T[i]) * inv_dt, (a.t_max - T[i]) * inv_dt);
-                T[i] = T[i] + a.dt * (double)u[i];
-            }
+            for (int i = 0; i < 4; ++i) u[i] = clampT(noisy ? ust[i] + sg[i] * z[i] : ust[i], rlo, rhi);
             R4 o;
             o.x = u[0]; o.y = u[1]; o.z = u[2]; o.w = u[3];
             if (noisy) ((R4 *)a.ctrl)[(size_t)k * (size_t)K + (size_t)m] = o;
@@ -342,10 +332,7 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
             if (HAS_V) {
                 Real zv = Real(0);
                 if (noisy) zv = normal1<Real>((uint32_t)m, (uint32_t)k, s, 1u, a.seed_lo, a.seed_hi);
-                const Real raw = noisy ? s_vs[k] + (Real)a.sigma_v * zv : s_vs[k];
-                const Real r = clampT(raw, dlo, dhi);
-                const Real acc = (Real)clampT((double)r, (0.0 - v) * inv_dt, (a.v_max - v) * inv_dt);
-                v = v + a.dt * (double)acc;
+                const Real acc = clampT(noisy ? s_vs[k] + (Real)a.sigma_v * zv : s_vs[k], dlo, dhi);
                 if (noisy) ((Real *)a.vctrl)[(size_t)k * (size_t)K + (size_t)m] = acc;
                 else ((Real *)a.nomV)[k] = acc;
             }
@@ -353,7 +340,7 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
         return;
     }
     if (m == K) {  // the noise-free sample
-        for (int k = 0; k < N; ++k) {
+        for (int k = k0; k < k1; ++k) {
             const R4 us = s_us[k];
             R4 o;
             o.x = clampT(us.x, tmin, tmax); o.y = clampT(us.y, tmin, tmax);
@@ -365,7 +352,7 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
         const Real sig0 = (Real)a.sigma[0], sig1 = (Real)a.sigma[1];
         const Real sig2 = (Real)a.sigma[2], sig3 = (Real)a.sigma[3];
 #pragma unroll 2
-        for (int k = 0; k < N; ++k) {
+        for (int k = k0; k < k1; ++k) {
             const R4 us = s_us[k];
             const Normal4<Real> z = normals4<Real>((uint32_t)m, (uint32_t)k, s, 0u, a.seed_lo, a.seed_hi);
             R4 o;
@@ -384,9 +371,14 @@ template <typename Real, bool HAS_V> __device__ __forceinline__ void sample_body
     __syncthreads();
 }
 
+// Steps per block of the sample kernel: the draws are independent, so the
+// grid spreads them over (samples, steps) and every CU takes a share.
+constexpr int kSampleSteps = 4;
+
 template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_sample(KArgs a)
 {
-    sample_body<Real, HAS_V>(a, blockIdx.x);
+    const int k0 = (int)blockIdx.y * kSampleSteps;
+    sample_body<Real, HAS_V>(a, blockIdx.x, k0, min(a.N, k0 + kSampleSteps));
 }
 
 // The head and the nominal's clipped inputs, for a rollout that draws its
@@ -569,6 +561,9 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
         for (int i = 0; i < 4; ++i) T[i] = rate ? a.req[kReqThrust + i] : 0.0;
         double vs = rate ? cur->v_prev : 0.0;
 
+        // the rate input's range clips (multiplied by 1/dt: the bound can
+        // differ from the quotient in the last binary64 place)
+        const double inv_dt = 1.0 / a.dt;
         R4 u;
         Real v = Real(0);
         input(0, u, v);
@@ -576,6 +571,24 @@ __device__ __forceinline__ void rollout1_body(const KArgs &a, int blk)
             R4 un = u;
             Real vn = v;
             if (k + 1 < N) input(k + 1, un, vn);
+            if (rate) {
+                // clip the drawn rates to the range that keeps each thrust of
+                // this sample's chain within [t_min, t_max] over the step (the
+                // progress acceleration: the speed within [0, v_max]); the
+                // clipped inputs replace the drawn ones for the average
+                u.x = (Real)clampT((double)u.x, (a.t_min - T[0]) * inv_dt, (a.t_max - T[0]) * inv_dt);
+                u.y = (Real)clampT((double)u.y, (a.t_min - T[1]) * inv_dt, (a.t_max - T[1]) * inv_dt);
+                u.z = (Real)clampT((double)u.z, (a.t_min - T[2]) * inv_dt, (a.t_max - T[2]) * inv_dt);
+                u.w = (Real)clampT((double)u.w, (a.t_min - T[3]) * inv_dt, (a.t_max - T[3]) * inv_dt);
+                if (HAS_V) v = (Real)clampT((double)v, (0.0 - vs) * inv_dt, (a.v_max - vs) * inv_dt);
+                if (nominal) {
+                    ((R4 *)a.nomU)[k] = u;
+                    if (HAS_V) ((Real *)a.nomV)[k] = v;
+                } else {
+                    ((R4 *)a.ctrl)[(size_t)k * (size_t)K + (size_t)m] = u;
+                    if (HAS_V) ((Real *)a.vctrl)[(size_t)k * (size_t)K + (size_t)m] = v;
+                }
+            }
             Real term = Real(0);
 
             // ---- stage terms at state k
@@ -2509,7 +2522,7 @@ template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void kb_s
         if (u >= total) break;
         item = advance_item(b.sample_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
-        sample_body<Real, HAS_V>(s_a, u - b.sample_prefix[item]);
+        sample_body<Real, HAS_V>(s_a, u - b.sample_prefix[item], 0, s_a.N);
     }
 }
 
@@ -2686,7 +2699,7 @@ template <typename Real, int OBJ>
 static hipError_t launch_solve_t(const KArgs &a, bool acc64, hipStream_t st, hipEvent_t *ev)
 {
     constexpr bool HAS_V = OBJ == OBJ_CONTOUR;
-    const dim3 gs((a.K + 1 + 255) / 256);
+    const dim3 gs((a.K + 1 + 255) / 256, (a.N + kSampleSteps - 1) / kSampleSteps);
     if (ev) (void)hipEventRecord(ev[0], st);
     // a one-wave rollout that draws its samples (binary32) needs only the head first
     const bool draw = sizeof(Real) == 4 && a.rollout_draw;
