@@ -46,10 +46,10 @@ PEAK_HBM_GBPS = 8000.0
 # or drawing the samples again) and the device sources they were taken on
 # (sha256 of kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order);
 # otherwise the traffic is reported as null.
-TRAFFIC_SOURCES = "c3676bf7b10bae21669e80f88d0a534208a617ec00f4292f5715cf4b158680aa"
+TRAFFIC_SOURCES = "4276b30019e5743ba3c6da9ddeb3298286755f756f40ce65420e1c5c01746898"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.3, 262144.0 / 262144.0
-TRAFFIC_KIB = {("k_rollout4", 0): (224.1, 12836.4), ("k_final", 0): (6575.5, 6.6),
-               ("k_rollout4", 1): (224.1, 38.0), ("k_final", 1): (212.7, 6.6)}
+TRAFFIC_KIB = {("k_rollout4", 0): (196.7, 12836.4), ("k_final", 0): (6574.5, 6.6),
+               ("k_rollout4", 1): (196.6, 38.0), ("k_final", 1): (208.8, 6.6)}
 TRAFFIC_WORKLOADS = {(8192, 100, "fp32", 0), (8192, 100, "fp32", 1)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
