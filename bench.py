@@ -659,6 +659,14 @@ def main():
                                               budget_bytes=32 * 2 ** 30, n_slots=4)
         except Exception as e:
             out["serving"] = {"error": repr(e)}
+        try:
+            # the same drones with the contouring half on the paper's rate input
+            from paper_2509_14726_amd import serving
+            out["serving_rate_contour"] = serving.simulate(n_drones=512, seconds=args.serving_seconds,
+                                                           rate_hz=50.0, budget_bytes=32 * 2 ** 30, n_slots=4,
+                                                           contour_input="rate")
+        except Exception as e:
+            out["serving_rate_contour"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         # the FP64 oracle from each measured solve's exported warm state

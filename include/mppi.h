@@ -117,8 +117,8 @@ typedef struct {
      * [t_min, t_max] over the step; the contouring acceleration likewise to
      * dv_lim and to the range that keeps the progress speed within
      * [0, v_max].  The rate model runs the one-wave rollout with a separate
-     * sampling kernel; a batch or server holding such a context runs all its
-     * contexts with one-wave rollouts. */
+     * sampling kernel; a batch holding such a context runs all its contexts
+     * with one-wave rollouts (a server launches each layout on its own). */
     int32_t input_model;
     int32_t pad_;
     double rate_lim[2];   /* thrust-rate bounds, N/s (lower <= 0 <= upper)    */
@@ -420,13 +420,13 @@ const char *mppi_batch_last_error(const mppi_batch *b);
  * idle launch slot (a stream with its own batch and graph), admits queued
  * heads in arrival order as long as their workspace (sample tensor, costs,
  * tile minima) fits in the free part of a device arena of budget_bytes, and
- * launches them as one batch.  Requests that arrive while others run are
- * admitted as slots and memory free up; the slots' work overlaps on the
- * device.  A solve's result is the same as that of the context stepped alone:
- * bit for bit when all of the server's contexts use one rollout layout (each
- * context picks its layout from K at creation, or from MPPI_ROLLOUT_WAVES; the
- * server's launches then use it), else to rounding (the layouts group the
- * cost terms of a step differently). */
+ * launches them as one batch.  A launch holds the drones of one rollout
+ * layout (mppi_info.rollout_waves and the four-wave chunk, which each context
+ * picks from K at creation, or from MPPI_ROLLOUT_WAVES), the layout of the
+ * oldest queued head, and runs them in that layout.  Requests that arrive
+ * while others run are admitted as slots and memory free up; the slots' work
+ * overlaps on the device.  A solve's result is the same as that of the
+ * context stepped alone, bit for bit. */
 typedef struct mppi_server mppi_server;
 
 typedef struct {

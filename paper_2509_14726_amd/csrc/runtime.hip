@@ -1493,7 +1493,7 @@ struct InFlight {
 };
 
 struct Slot {
-    mppi_batch *batch = nullptr;
+    std::vector<mppi_batch *> batches;           // one per layout class of the drones
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     double *h_req = nullptr, *d_req = nullptr;   // n x 16
@@ -1506,6 +1506,11 @@ struct Slot {
 
 struct mppi_server {
     std::vector<mppi_ctx *> drones;
+    // Drones are grouped by rollout layout (waves, four-wave chunk): a launch
+    // holds drones of one class only and runs their own layout, so a served
+    // solve repeats the stand-alone solve bit for bit and a one-wave class
+    // (the rate input) does not slow the others down.
+    std::vector<int> cls, local;                 // per drone: class, index in the class's batch
     mppi_server_cfg cfg{};
     std::vector<std::vector<Request>> queue;     // per drone, FIFO (front at index head[d])
     std::vector<size_t> head;
@@ -1538,7 +1543,7 @@ static void release_server(mppi_server *s)
     if (!s) return;
     for (auto &sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.batch) release_batch(sl.batch);
+        for (mppi_batch *b : sl.batches) release_batch(b);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.h_req) (void)hipHostFree(sl.h_req);
         if (sl.h_u0) (void)hipHostFree(sl.h_u0);
@@ -1599,10 +1604,13 @@ static mppi_status admit(mppi_server *s, double now, int32_t *n_launched)
         std::stable_sort(ready.begin(), ready.end(), [&](int x, int y) {
             return s->queue[x][s->head[x]].t_arrival < s->queue[y][s->head[y]].t_arrival;
         });
+        // the launch takes the class of the oldest head
+        const int c = s->cls[ready[0]];
         std::vector<int32_t> active;
         std::vector<char *> ws;
         for (int d : ready) {
             if (s->cfg.max_batch > 0 && (int)active.size() >= s->cfg.max_batch) break;
+            if (s->cls[d] != c) continue;
             size_t off = 0;
             if (!s->arena.alloc(s->drones[d]->ws_bytes, &off)) continue;  // waits for memory
             const Request &rq = s->queue[d][s->head[d]];
@@ -1610,7 +1618,7 @@ static mppi_status admit(mppi_server *s, double now, int32_t *n_launched)
             for (int c = 0; c < 13; ++c) sl.h_req[kReqDoubles * i + c] = rq.x0[c];
             sl.h_req[kReqDoubles * i + 13] = rq.t_now;
             for (int c = 0; c < 4; ++c) sl.h_req[kReqDoubles * i + kReqThrust + c] = rq.x0[13 + c];
-            active.push_back(d);
+            active.push_back(s->local[d]);
             ws.push_back(s->arena_base + off);
             sl.flight.push_back(InFlight{d, rq.ticket, rq.t_arrival, now, off});
             s->busy[d] = 1;
@@ -1623,8 +1631,8 @@ static mppi_status admit(mppi_server *s, double now, int32_t *n_launched)
         if (hipMemcpyAsync(sl.d_req, sl.h_req, sizeof(double) * kReqDoubles * n, hipMemcpyHostToDevice, sl.stream) !=
             hipSuccess)
             return sfail(s, MPPI_E_DEVICE, "request copy failed");
-        mppi_status st = batch_solve(sl.batch, active.data(), n, sl.d_req, sl.d_u0, ws.data());
-        if (st != MPPI_OK) return sfail(s, st, "batch launch failed: %s", sl.batch->err.c_str());
+        mppi_status st = batch_solve(sl.batches[c], active.data(), n, sl.d_req, sl.d_u0, ws.data());
+        if (st != MPPI_OK) return sfail(s, st, "batch launch failed: %s", sl.batches[c]->err.c_str());
         if (hipMemcpyAsync(sl.h_u0, sl.d_u0, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
             hipEventRecord(sl.done, sl.stream) != hipSuccess)
             return sfail(s, MPPI_E_DEVICE, "result copy failed");
@@ -1663,6 +1671,23 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
     s->queue.resize(n);
     s->head.assign(n, 0);
     s->busy.assign(n, 0);
+    // layout classes in order of first appearance
+    std::vector<int> cls_key;
+    std::vector<std::vector<mppi_ctx *>> members;
+    s->cls.resize(n);
+    s->local.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const int key = 8 * drones[i]->args.rollout_waves + drones[i]->args.ring4_b;
+        int c = 0;
+        while (c < (int)cls_key.size() && cls_key[c] != key) ++c;
+        if (c == (int)cls_key.size()) {
+            cls_key.push_back(key);
+            members.emplace_back();
+        }
+        s->cls[i] = c;
+        s->local[i] = (int)members[c].size();
+        members[c].push_back(drones[i]);
+    }
     const size_t arena = (size_t)cfg->budget_bytes;
     if (hipMalloc((void **)&s->arena_base, arena) != hipSuccess) {
         release_server(s);
@@ -1681,17 +1706,17 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
             release_server(s);
             return sfail(nullptr, MPPI_E_NOMEM, "slot resources could not be allocated");
         }
-        // the contexts' own rollout layout when they share one, so that a
-        // served solve repeats the stand-alone solve bit for bit
-        int layout = drones[0]->args.rollout_waves;
-        for (int i = 1; i < n; ++i)
-            if (drones[i]->args.rollout_waves != layout) layout = 0;
-        mppi_batch_cfg bc{layout, 0, 0, cfg->use_graph ? 1 : 0};
-        mppi_status st = mppi_batch_create(drones, n, sl.stream, &bc, &sl.batch);
-        if (st != MPPI_OK) {
-            std::string e = g_create_err;
-            release_server(s);
-            return sfail(nullptr, st, "slot batch: %s", e.c_str());
+        // one batch per class, in the class's own rollout layout
+        for (size_t c = 0; c < members.size(); ++c) {
+            mppi_batch_cfg bc{cls_key[c] / 8, 0, 0, cfg->use_graph ? 1 : 0};
+            mppi_batch *bt = nullptr;
+            mppi_status st = mppi_batch_create(members[c].data(), (int32_t)members[c].size(), sl.stream, &bc, &bt);
+            if (st != MPPI_OK) {
+                std::string e = g_create_err;
+                release_server(s);
+                return sfail(nullptr, st, "slot batch: %s", e.c_str());
+            }
+            sl.batches.push_back(bt);
         }
     }
     *out = s;

@@ -141,11 +141,15 @@ def test_rate_contexts_in_a_batch_match_their_solo_solves(monkeypatch):
         sv.close()
 
 
-def test_served_rate_drones_match_their_solo_solves(monkeypatch):
-    """Rate drones (17-state requests) served in mixed launches with a thrust
-    drone give the first inputs their solo twins give, bit for bit."""
-    say("served rate drones vs solo")
-    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "1")
+@pytest.mark.parametrize("one_wave_everywhere", [True, False])
+def test_served_rate_drones_match_their_solo_solves(one_wave_everywhere, monkeypatch):
+    """Rate drones (17-state requests) served beside a thrust drone give the
+    first inputs their solo twins give, bit for bit: with every context on
+    one-wave rollouts (one launch class), and with the thrust drone on its own
+    layout (two launch classes)."""
+    say("served rate drones vs solo", one_wave_everywhere)
+    if one_wave_everywhere:
+        monkeypatch.setenv("MPPI_ROLLOUT_WAVES", "1")
     ws = _mixed_instances(external=True)
     wa = _mixed_instances(external=False)
     served = [_solver(w) for w in ws]

@@ -94,21 +94,24 @@ def test_server_rejects_oversized_and_plain_contexts():
         served[0].solve(ws[0]["x0"], 0.0)  # no workspace of its own
 
 
-def test_served_solves_against_the_oracle():
+@pytest.mark.parametrize("contour_input", ["thrust", "rate"])
+def test_served_solves_against_the_oracle(contour_input):
     """Drones of the serving workload (K in {2048, 8192}, N in {50, 100},
-    gate or contouring objective, lambda = 1, sigma = 1 N): every served
+    gate objective with thrust as the input, contouring with thrust or the
+    rate input model, lambda = 10): every served
     solve over three rounds of requests compared with the FP64 oracle from
     the drone's exported warm state.  A served solve's workspace is lent
     back to the server when it retires, so its sample costs (needed to replay
     a decision within the ambiguity margin) come from a twin context of the
     same drone stepped alone, whose result must equal the served one bit for
-    bit."""
+    bit (a launch holds drones of one rollout layout, here the thrust drones'
+    four-wave or the rate drones' one-wave layout)."""
     from oracle import oracle as O
     from paper_2509_14726_amd import serving
     from tests.parity import EPS_DEC, compare_result
-    ws = serving.drone_workloads(6)
+    ws = serving.drone_workloads(6, contour_input=contour_input)
     shapes = [(w["params"]["K"], w["params"]["N"], w["params"]["objective"]) for w in ws]
-    say("served vs oracle", shapes)
+    say("served vs oracle", contour_input, shapes)
     assert {K for K, _, _ in shapes} == {2048, 8192} and {N for _, N, _ in shapes} == {50, 100}
     served = [solver(w) for w in ws]
     twins = [solver(dict(w, params=dict(w["params"], flags=0))) for w in ws]
@@ -140,7 +143,8 @@ def test_served_solves_against_the_oracle():
             c = compare_result(orcs[d], wds[d], xs[d], t, M.FP32, u0, U, info, Jd=Jd, wn=wn)
             worst = max(worst, c["err_U_e2e"])
             n_amb += c["n_amb"]
-            xs[d] = M.plant_step(ws[d]["quad"], xs[d], u0, 0.02, 4)
+            plant = M.plant_step_rate if xs[d].size == 17 else M.plant_step
+            xs[d] = plant(ws[d]["quad"], xs[d], u0, 0.02, 4)
         say("  round", k, "worst end-to-end control error", worst, "ambiguous samples so far", n_amb)
     S.close()
     for sv in served + twins:
