@@ -11,8 +11,7 @@ thrust rates with 10 N/s of noise, bounds +-10 N/s, the progress
 acceleration with 5 m/s^2 of noise, lambda = 10, the thrusts as four more
 states.  Over these 1-2 s horizons contouring drones with thrust as the input
 fall away from the path and those with thrust rates follow it; rate drones
-run one-wave rollouts, and so does every launch that holds one, which costs
-latency.  Between two of its requests a drone's FP64 host plant advances
+run one-wave rollouts, in launches of their own, which costs latency.  Between two of its requests a drone's FP64 host plant advances
 with the last control it received (RK4, substeps of at most 5 ms).  A drone whose state leaves a sane envelope (non-finite, more than
 1 km from the origin, or spinning faster than 1000 rad/s) is counted as a
 crash and respawned at its start (its solver keeps the warm state and
