@@ -139,8 +139,9 @@ typedef struct {
  * HBM traffic per sample and step.  It takes effect wherever the rollout
  * draws the samples itself: the three- and four-wave layouts and the
  * drawing one-wave layout (mppi_info.regen_average reports it), with thrust
- * as the input, one iteration and no control-cost term.  Batches choose it
- * per batch (mppi_batch_cfg.regen_average); served solves keep the tensor.
+ * as the input and no control-cost term.  Batches choose it per batch
+ * (mppi_batch_cfg.regen_average; not with a control-cost term in the
+ * batch); served solves keep the tensor.
  * mppi_autotune can choose it instead.  mppi_read_samples then returns the
  * costs only (MPPI_E_INVAL when U_samples is requested). */
 #define MPPI_FLAG_REGEN_AVERAGE 2
@@ -333,8 +334,10 @@ mppi_status mppi_read_profile(mppi_ctx *ctx, double mean_ms[3], int32_t *n_solve
  * differ).  Each mppi_batch_solve_device call runs one MPPI step for a chosen
  * subset of them in a single launch sequence: a grid-stride sample kernel, a
  * persistent rollout kernel that pulls 64-sample tiles from a device queue in
- * order of decreasing horizon, and a grid-stride weighted-average kernel
- * (one unit per context and horizon step), per group
+ * order of decreasing horizon, a grid-stride control-cost kernel where a
+ * context has the term (one unit per context and 64-sample tile), and a
+ * grid-stride weighted-average kernel (one unit per context and horizon
+ * step), repeated n_iter times (the contexts' shared n_iter), per group
  * of contexts sharing an objective and accumulation type.  Grids are fixed
  * and the work description lives in device memory, so the sequence is
  * captured once in a HIP graph (cfg.use_graph) and replayed for any subset.
@@ -364,9 +367,8 @@ typedef struct {
                                   with one- and two-wave rollouts             */
 } mppi_batch_cfg;
 
-/* Register ctxs[0..n-1] (distinct, same precision, each used by no other
- * batch or call while the batch runs; one iteration per solve and no
- * control-cost term: MPPI_E_INVAL otherwise).  stream: hipStream_t of the batch's
+/* Register ctxs[0..n-1] (distinct, same precision and n_iter, each used by
+ * no other batch or call while the batch runs: MPPI_E_INVAL otherwise).  stream: hipStream_t of the batch's
  * launches (NULL: one owned by the batch).  cfg NULL: all automatic, graph on.
  * The contexts must outlive the batch. */
 mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, const mppi_batch_cfg *cfg,
@@ -411,8 +413,7 @@ const char *mppi_batch_last_error(const mppi_batch *b);
 /* ---- Serving: continuous batching of solves from many drones ----
  *
  * The server owns no drone state: it registers contexts created with
- * MPPI_FLAG_EXTERNAL_WORKSPACE (one per drone, all of one precision, one
- * iteration per solve and no control-cost term; each
+ * MPPI_FLAG_EXTERNAL_WORKSPACE (one per drone, all of one precision; each
  * keeps its warm-start state, gate index and problem data resident on the
  * device).  Requests queue per drone in arrival order; a drone has at most
  * one solve in flight, since each solve starts from the previous one's warm
@@ -420,10 +421,10 @@ const char *mppi_batch_last_error(const mppi_batch *b);
  * idle launch slot (a stream with its own batch and graph), admits queued
  * heads in arrival order as long as their workspace (sample tensor, costs,
  * tile minima) fits in the free part of a device arena of budget_bytes, and
- * launches them as one batch.  A launch holds the drones of one rollout
- * layout (mppi_info.rollout_waves and the four-wave chunk, which each context
- * picks from K at creation, or from MPPI_ROLLOUT_WAVES), the layout of the
- * oldest queued head, and runs them in that layout.  Requests that arrive
+ * launches them as one batch.  A launch holds the drones of one class, that of
+ * the oldest queued head: one rollout layout (mppi_info.rollout_waves and the
+ * four-wave chunk, which each context picks from K at creation, or from
+ * MPPI_ROLLOUT_WAVES) and one n_iter, and runs them in that layout.  Requests that arrive
  * while others run are admitted as slots and memory free up; the slots' work
  * overlaps on the device.  A solve's result is the same as that of the
  * context stepped alone, bit for bit. */

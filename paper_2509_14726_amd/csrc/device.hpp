@@ -153,7 +153,8 @@ struct BatchDesc {
     int32_t n_tiles;            // sum over items of ceil((K+1)/64)
     int32_t n_steps;            // sum over items of N (units of the weighted-average kernel)
     uint32_t queue;             // rollout tile counter, reset by the sample kernel
-    uint32_t sample_queue;      // sample unit counter
+    uint32_t sample_queue;      // sample unit counter (both also reset by the
+                                // average kernel, for the step's next iteration)
     uint32_t pad[2];
 };
 

@@ -2186,10 +2186,10 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(192) void k_rollo
 // step order.  One wave per 64-sample tile reads its samples step by step
 // (64 consecutive records per step) and rewrites the tile's smallest finite
 // cost.
-template <typename Real, bool HAS_V> __global__ __launch_bounds__(64) void k_ctrl_cost(KArgs a)
+template <typename Real, bool HAS_V> __device__ __forceinline__ void ctrl_cost_body(const KArgs &a, int tile)
 {
     typedef typename Vec4<Real>::T R4;
-    const int tile = blockIdx.x, m = tile * 64 + (int)threadIdx.x;
+    const int m = tile * 64 + (int)threadIdx.x;
     const int K = a.K, N = a.N;
     const DevCur *cur = a.cur;
     const int shift = cur->shift;
@@ -2220,6 +2220,11 @@ template <typename Real, bool HAS_V> __global__ __launch_bounds__(64) void k_ctr
         ((Real *)a.J)[m] = Jm;
     }
     store_tile_min(Jm, m < K && isfinite(Jm), a.tmin, tile);
+}
+
+template <typename Real, bool HAS_V> __global__ __launch_bounds__(64) void k_ctrl_cost(KArgs a)
+{
+    ctrl_cost_body<Real, HAS_V>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- weighted average
@@ -2593,12 +2598,36 @@ template <int OBJ, typename Real, int B> __global__ __launch_bounds__(256) void 
     }
 }
 
-// One unit per (item, step) of the weighted average.
+// One unit per (item, 64-sample tile) of the control-cost term; items
+// without the term are skipped.
+template <typename Real, bool HAS_V> __global__ __launch_bounds__(64) void kb_ctrl_cost(BArgs b)
+{
+    __shared__ KArgs s_a;
+    __shared__ int s_ctx;
+    if (threadIdx.x == 0) s_ctx = -1;
+    __syncthreads();
+    const int n = b.desc->n, total = b.desc->n_tiles;
+    int item = 0;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        item = advance_item(b.tile_prefix, n, u, item);
+        stage_args(s_a, s_ctx, b, item);
+        if (s_a.ctrl_cost != 0.0) ctrl_cost_body<Real, HAS_V>(s_a, u - b.tile_prefix[item]);
+        __syncthreads();
+    }
+}
+
+// One unit per (item, step) of the weighted average.  The sample and rollout
+// kernels of this step have finished, so their work queues are reset here
+// for the next iteration of the step.
 template <typename Real, typename Acc, bool HAS_V> __global__ __launch_bounds__(kFinalThreads) void kb_final(BArgs b)
 {
     __shared__ KArgs s_a;
     __shared__ int s_ctx;
     if (threadIdx.x == 0) s_ctx = -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.desc->queue = 0u;
+        b.desc->sample_queue = 0u;
+    }
     // every thread reads s_ctx in stage_args before its first barrier
     __syncthreads();
     const int n = b.desc->n, total = b.desc->n_steps;
@@ -2634,6 +2663,8 @@ static hipError_t launch_batch_t(const BArgs &b, const BatchLaunch &L, hipStream
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 2>), dim3(L.rollout_groups), dim3(128), 0, st, b);
     else
         hipLaunchKernelGGL((kb_rollout<OBJ, Real, 1>), dim3(L.rollout_groups), dim3(64), 0, st, b);
+    if (L.ctrl_groups > 0)
+        hipLaunchKernelGGL((kb_ctrl_cost<Real, HAS_V>), dim3(L.ctrl_groups), dim3(64), 0, st, b);
     if (L.acc64 || sizeof(Real) == 8)
         hipLaunchKernelGGL((kb_final<Real, double, HAS_V>), dim3(L.final_groups), dim3(kFinalThreads), 0, st, b);
     else

@@ -30,6 +30,7 @@ struct BatchLaunch {
     int rollout_groups;   // persistent rollout workgroups
     int sample_groups;    // grid-stride workgroups of the sample kernel
     int final_groups;     // grid-stride workgroups of the weighted-average kernel
+    int ctrl_groups;      // grid-stride workgroups of the control-cost kernel (0: no item has the term)
 };
 
 // Enqueue one batched MPPI step over the items described in device memory.

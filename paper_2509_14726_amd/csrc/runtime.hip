@@ -980,6 +980,7 @@ struct BatchGroup {
     BArgs bargs{};
     BatchLaunch launch{};
     int active = 0;              // items in the current step
+    bool ctrl = false;           // a context of the group adds the control-cost term
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -1003,6 +1004,8 @@ struct mppi_batch {
     int n_cu = 256;
     int total_tiles = 0;
     bool has_rate = false;       // a context takes the rate input: one-wave rollouts only
+    bool any_ctrl = false;       // a context adds the control-cost term: the tensor is kept
+    int n_iter = 1;              // MPPI iterations per step, shared by the contexts
     std::string err;
 };
 
@@ -1044,10 +1047,9 @@ static hipError_t resolve_cfg(mppi_batch *b)
     // a rate sample follows its thrust chain, which the sample kernel walks
     // per sample: the one-wave rollout reads it
     if (b->has_rate) waves = 1;
-    // the regenerating average where the batch's rollout draws the samples
-    // (batched contexts take thrust as the input, one iteration and no
-    // control-cost term)
-    const int regen = (c.regen_average && waves >= 3) ? 1 : 0;
+    // the regenerating average where the batch's rollout draws the samples,
+    // unless a context's control-cost term reads the sample tensor
+    const int regen = (c.regen_average && waves >= 3 && !b->any_ctrl) ? 1 : 0;
     bool changed = false;
     for (auto &t : b->h_table)
         if (t.regen != regen) { t.regen = regen; changed = true; }
@@ -1081,6 +1083,8 @@ static hipError_t resolve_cfg(mppi_batch *b)
         g.launch.sample_groups = sg;
         // kFinalThreads-thread workgroups, two per CU
         g.launch.final_groups = 2 * b->n_cu;
+        // one-wave workgroups of the control-cost term, eight per CU
+        g.launch.ctrl_groups = g.ctrl ? 8 * b->n_cu : 0;
     }
     return hipSuccess;
 }
@@ -1115,8 +1119,8 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
     for (int i = 0; i < n; ++i) {
         if (!ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d is NULL", i);
         if (ctxs[i]->fp64 != ctxs[0]->fp64) return bfail(nullptr, MPPI_E_INVAL, "contexts differ in precision");
-        if (ctxs[i]->n_iter != 1 || ctxs[i]->args.ctrl_cost != 0.0)
-            return bfail(nullptr, MPPI_E_INVAL, "context %d: batches run one iteration and no control-cost term", i);
+        if (ctxs[i]->n_iter != ctxs[0]->n_iter)
+            return bfail(nullptr, MPPI_E_INVAL, "context %d: the contexts of a batch share n_iter", i);
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return bfail(nullptr, MPPI_E_INVAL, "context %d registered twice", i);
     }
@@ -1124,7 +1128,11 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
     if (!b) return bfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
     b->ctxs.assign(ctxs, ctxs + n);
     b->fp64 = ctxs[0]->fp64;
-    for (int i = 0; i < n; ++i) b->has_rate = b->has_rate || ctxs[i]->args.input_model == MPPI_INPUT_RATE;
+    for (int i = 0; i < n; ++i) {
+        b->has_rate = b->has_rate || ctxs[i]->args.input_model == MPPI_INPUT_RATE;
+        b->any_ctrl = b->any_ctrl || ctxs[i]->args.ctrl_cost != 0.0;
+    }
+    b->n_iter = ctxs[0]->n_iter;
     b->cfg = cfg ? *cfg : mppi_batch_cfg{0, 0, 0, 1, 0};
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess)
@@ -1158,20 +1166,28 @@ mppi_status mppi_batch_create(mppi_ctx *const *ctxs, int32_t n, void *stream, co
             gi = (int)b->groups.size() - 1;
         }
         b->groups[gi].regs.push_back(i);
+        b->groups[gi].ctrl = b->groups[gi].ctrl || c->args.ctrl_cost != 0.0;
         b->group_of[i] = gi;
         b->tiles_of[i] = (c->K + 1 + 63) / 64;
         b->total_tiles += b->tiles_of[i];
     }
     // device table of kernel arguments; whether the average draws the samples
-    // again is the batch's choice (its layout is its own)
+    // again is the batch's choice (its layout is its own).  With several
+    // iterations per step a second copy, marked inner, serves the later ones.
     std::vector<KArgs> &table = b->h_table;
-    table.resize(n);
+    const int copies = b->n_iter > 1 ? 2 : 1;
+    table.resize((size_t)copies * n);
     for (int i = 0; i < n; ++i) {
         table[i] = ctxs[i]->args;
         table[i].regen = 0;
+        table[i].inner = 0;
+        if (copies == 2) {
+            table[n + i] = table[i];
+            table[n + i].inner = 1;
+        }
     }
-    if (hipMalloc((void **)&b->d_table, sizeof(KArgs) * n) != hipSuccess ||
-        hipMemcpy(b->d_table, table.data(), sizeof(KArgs) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMalloc((void **)&b->d_table, sizeof(KArgs) * table.size()) != hipSuccess ||
+        hipMemcpy(b->d_table, table.data(), sizeof(KArgs) * table.size(), hipMemcpyHostToDevice) != hipSuccess) {
         release_batch(b);
         return bfail(nullptr, MPPI_E_NOMEM, "device table allocation failed");
     }
@@ -1228,11 +1244,18 @@ mppi_status mppi_batch_get_cfg(const mppi_batch *b, mppi_batch_cfg *cfg)
     return MPPI_OK;
 }
 
+// The launch sequence of one step: n_iter iterations, the later ones reading
+// the inner copy of the argument table (no shift, the first iteration's last
+// applied input), each group's kernels in turn.
 static mppi_status enqueue_groups(mppi_batch *b, bool skip_empty)
 {
-    for (auto &g : b->groups) {
-        if (skip_empty && g.active == 0) continue;
-        BHIP_TRY(b, launch_batch(g.bargs, g.launch, b->stream));
+    for (int it = 0; it < b->n_iter; ++it) {
+        for (auto &g : b->groups) {
+            if (skip_empty && g.active == 0) continue;
+            BArgs ba = g.bargs;
+            if (it > 0) ba.table = b->d_table + b->ctxs.size();
+            BHIP_TRY(b, launch_batch(ba, g.launch, b->stream));
+        }
     }
     return MPPI_OK;
 }
@@ -1340,7 +1363,8 @@ mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u
     const int n = (int)b->ctxs.size();
     if (from_cache) *from_cache = 0;
     // cache key: architecture, objectives, precision, instance count and
-    // total rollout steps
+    // total rollout steps; then the rate input, several iterations and the
+    // control-cost term where a context has them
     int objs = 0;
     double kn = 0.0;
     for (const mppi_ctx *c : b->ctxs) {
@@ -1348,8 +1372,13 @@ mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u
         kn += (double)c->K * (double)c->N;
     }
     char key[256];
-    snprintf(key, sizeof key, "batch|%s|obj%d|%s|n%d|KN%d", tune::arch_of(b->ctxs[0]->device).c_str(), objs,
-             tune::prec_name(b->fp64), tune::bucket(n), tune::bucket(kn));
+    snprintf(key, sizeof key, "batch|%s|obj%d|%s|n%d|KN%d%s%s", tune::arch_of(b->ctxs[0]->device).c_str(), objs,
+             tune::prec_name(b->fp64), tune::bucket(n), tune::bucket(kn), b->has_rate ? "|rate" : "",
+             b->any_ctrl ? "|cc" : "");
+    if (b->n_iter > 1) {
+        const size_t used = strlen(key);
+        snprintf(key + used, sizeof key - used, "|it%d", b->n_iter);
+    }
     tune::Entry ce;
     if (!(flags & MPPI_TUNE_FORCE) && tune::load(cache_path, key, ce)) {
         const mppi_batch_cfg c{ce.waves, ce.groups, ce.sgroups, b->cfg.use_graph, ce.regen};
@@ -1368,7 +1397,7 @@ mppi_status mppi_batch_autotune(mppi_batch *b, const double *d_reqs, double *d_u
         for (int rm : rg_mult) {
             if (waves >= 2 && rm > 2) continue;  // one or two LDS rings fit one CU
             for (int sm : {1, 4})
-                for (int regen = 0; regen <= (waves >= 3 ? 1 : 0); ++regen)
+                for (int regen = 0; regen <= (waves >= 3 && !b->any_ctrl ? 1 : 0); ++regen)
                     cand.push_back(mppi_batch_cfg{waves, rm * cu, sm * cu, saved.use_graph, regen});
         }
     }
@@ -1506,10 +1535,11 @@ struct Slot {
 
 struct mppi_server {
     std::vector<mppi_ctx *> drones;
-    // Drones are grouped by rollout layout (waves, four-wave chunk): a launch
-    // holds drones of one class only and runs their own layout, so a served
-    // solve repeats the stand-alone solve bit for bit and a one-wave class
-    // (the rate input) does not slow the others down.
+    // Drones are grouped by rollout layout (waves, four-wave chunk) and
+    // iterations per solve: a launch holds drones of one class only and runs
+    // their own layout, so a served solve repeats the stand-alone solve bit
+    // for bit and a one-wave class (the rate input) does not slow the others
+    // down.
     std::vector<int> cls, local;                 // per drone: class, index in the class's batch
     mppi_server_cfg cfg{};
     std::vector<std::vector<Request>> queue;     // per drone, FIFO (front at index head[d])
@@ -1661,8 +1691,6 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
     for (int i = 0; i < n; ++i) {
         if (!drones[i] || !drones[i]->external_ws)
             return sfail(nullptr, MPPI_E_INVAL, "drone %d: context must be created with MPPI_FLAG_EXTERNAL_WORKSPACE", i);
-        if (drones[i]->n_iter != 1 || drones[i]->args.ctrl_cost != 0.0)
-            return sfail(nullptr, MPPI_E_INVAL, "drone %d: served solves run one iteration and no control-cost term", i);
     }
     mppi_server *s = new (std::nothrow) mppi_server();
     if (!s) return sfail(nullptr, MPPI_E_NOMEM, "host allocation failed");
@@ -1671,17 +1699,19 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
     s->queue.resize(n);
     s->head.assign(n, 0);
     s->busy.assign(n, 0);
-    // layout classes in order of first appearance
-    std::vector<int> cls_key;
+    // launch classes (rollout layout, iterations per solve) in order of
+    // first appearance
+    std::vector<int> cls_key, cls_waves;
     std::vector<std::vector<mppi_ctx *>> members;
     s->cls.resize(n);
     s->local.resize(n);
     for (int i = 0; i < n; ++i) {
-        const int key = 8 * drones[i]->args.rollout_waves + drones[i]->args.ring4_b;
+        const int key = (8 * drones[i]->args.rollout_waves + drones[i]->args.ring4_b) * 128 + drones[i]->n_iter;
         int c = 0;
         while (c < (int)cls_key.size() && cls_key[c] != key) ++c;
         if (c == (int)cls_key.size()) {
             cls_key.push_back(key);
+            cls_waves.push_back(drones[i]->args.rollout_waves);
             members.emplace_back();
         }
         s->cls[i] = c;
@@ -1708,7 +1738,7 @@ mppi_status mppi_server_create(mppi_ctx *const *drones, int32_t n, const mppi_se
         }
         // one batch per class, in the class's own rollout layout
         for (size_t c = 0; c < members.size(); ++c) {
-            mppi_batch_cfg bc{cls_key[c] / 8, 0, 0, cfg->use_graph ? 1 : 0};
+            mppi_batch_cfg bc{cls_waves[c], 0, 0, cfg->use_graph ? 1 : 0};
             mppi_batch *bt = nullptr;
             mppi_status st = mppi_batch_create(members[c].data(), (int32_t)members[c].size(), sl.stream, &bc, &bt);
             if (st != MPPI_OK) {

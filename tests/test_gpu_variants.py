@@ -2,7 +2,8 @@
 several iterations per control step and the information-theoretic
 control-cost term (both off in the paper's method), alone and together, in
 both precisions and for the three objectives, over warm-started closed-loop
-steps; and their refusal where they are not supported (batches, servers)."""
+steps; and in batches and servers, where each context's result must equal
+its stand-alone solve bit for bit."""
 import sys
 
 import numpy as np
@@ -75,19 +76,114 @@ def test_control_cost_at_the_benchmark_size_in_every_layout(monkeypatch):
         dev.close()
 
 
-def test_variants_are_refused_by_batches_and_servers():
-    w = synth.single_solve_workload(K=256, N=10, seed=5, n_iter=2)
-    sv = M.Solver(w["quad"], w["params"], gates=w["gates"], precision=M.FP32)
+def _variant_instances(n_iter, external=False):
+    """Uneven contexts of the three objectives sharing n_iter, half of them
+    with the control-cost term (ragged last tiles)."""
+    out = []
+    for i, (obj, K, N, gam) in enumerate([("gate", 1000, 30, 4.0), ("contour", 700, 25, 0.0),
+                                          ("track", 1300, 40, 4.0), ("gate", 500, 20, 0.0),
+                                          ("contour", 900, 35, 2.0)]):
+        prm = dict(seed=70 + i, track_seed=70 + i, n_iter=n_iter, ctrl_cost=gam, **{"lambda": 20.0})
+        if external:
+            prm["flags"] = M.FLAG_EXTERNAL_WORKSPACE
+        out.append(synth.single_solve_workload(K=K, N=N, objective=obj, **prm))
+    return out
+
+
+def _solver(w, precision=M.FP32):
+    return M.Solver(w["quad"], w["params"], gates=w["gates"], path=w.get("path"), path_len=w.get("path_len", 0.0),
+                    xref=w.get("xref"), ref_dt=w.get("ref_dt", 0.0), precision=precision)
+
+
+@pytest.mark.parametrize("precision", [M.FP32, M.FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("n_iter,waves,use_graph", [(2, 4, True), (3, 1, True), (1, 3, False), (2, 2, True)])
+def test_variants_in_a_batch_match_their_solo_solves(precision, n_iter, waves, use_graph, monkeypatch):
+    """Several iterations per step and the control-cost term in a batch:
+    each context's first input, costs, report and warm state equal its solo
+    twin's, bit for bit, over three warm-started steps, in the given rollout
+    layout (the twins forced to it too); the regenerating average is asked
+    for and stays off (the term reads the sample tensor)."""
+    import torch
+    say("variants in a batch", precision, "n_iter", n_iter, "waves", waves, "graph", use_graph)
+    monkeypatch.setenv("MPPI_ROLLOUT_WAVES", str(waves))
+    inst = _variant_instances(n_iter)
+    solo = [_solver(w, precision) for w in inst]
+    bat = [_solver(w, precision) for w in inst]
+    B = M.Batch(bat, rollout_waves=waves, use_graph=use_graph, regen_average=True)
+    cfg = B.get_cfg()
+    assert cfg["rollout_waves"] == waves and cfg["regen_average"] == 0
+    n = len(inst)
+    reqs = torch.zeros((n, M.REQ_DOUBLES), dtype=torch.float64, device="cuda")
+    u0s = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    xs = [w["x0"].copy() for w in inst]
+    for step in range(3):
+        for i, w in enumerate(inst):
+            reqs[i, :13] = torch.from_numpy(xs[i])
+            reqs[i, 13] = step * w["params"]["dt"]
+        torch.cuda.synchronize()
+        B.solve_device(reqs.data_ptr(), u0s.data_ptr())
+        torch.cuda.synchronize()
+        got = u0s.cpu().numpy()
+        for i, w in enumerate(inst):
+            u0, U, info = solo[i].solve(xs[i], step * w["params"]["dt"])
+            st, info_b = bat[i].read_info()
+            assert st == M.OK
+            assert np.array_equal(got[i], u0), (step, i, got[i], u0)
+            for key in ("J_min", "g0", "shift", "solve_index", "ess"):
+                assert info_b[key] == info[key], (step, i, key)
+            Jb, _ = bat[i].read_samples()
+            Js, _ = solo[i].read_samples()
+            assert np.array_equal(Jb, Js), (step, i)
+            wb, ws = bat[i].get_warm(), solo[i].get_warm()
+            assert list(wb.U) == list(ws.U) and list(wb.V) == list(ws.V) and wb.solve_index == ws.solve_index
+            xs[i] = M.plant_step(w["quad"], xs[i], u0, w["params"]["dt"], 2)
+    B.close()
+    for sv in solo + bat:
+        sv.close()
+
+
+def test_served_variants_match_their_solo_solves():
+    """Drones with several iterations per solve and the control-cost term,
+    served beside plain drones (three launch classes: n_iter 1, 2 and 3):
+    each served first input equals its solo twin's, bit for bit."""
+    say("served variants vs solo")
+    ws, wa = [], []
+    for n_iter in (1, 2, 3):
+        ws += _variant_instances(n_iter, external=True)[:3]
+        wa += _variant_instances(n_iter)[:3]
+    served = [_solver(w) for w in ws]
+    alone = [_solver(w) for w in wa]
+    S = M.Server(served, budget_bytes=256 * 2 ** 20, n_slots=2, max_batch=4)
+    xs = [w["x0"].copy() for w in wa]
+    expected, tick = {}, {}
+    for k in range(3):
+        for d, w in enumerate(wa):
+            t = k * w["params"]["dt"]
+            u0, _, _ = alone[d].solve(xs[d], t)
+            expected[(d, k)] = u0
+            tick[S.submit(d, xs[d].copy(), t, float(k))] = (d, k)
+            xs[d] = M.plant_step(w["quad"], xs[d], u0, w["params"]["dt"], 2)
+        S.drain(1e9)
+    res = S.poll()
+    assert len(res) == 3 * len(wa)
+    for r in res:
+        d, k = tick[r["ticket"]]
+        assert r["status"] == M.OK
+        assert np.array_equal(np.array(r["u0"]), expected[(d, k)]), (d, k)
+    S.close()
+    for sv in served + alone:
+        sv.close()
+
+
+def test_batch_refuses_contexts_that_differ_in_n_iter():
+    w1 = synth.single_solve_workload(K=256, N=10, seed=5, n_iter=2)
+    w2 = synth.single_solve_workload(K=256, N=10, seed=6)
+    s1, s2 = _solver(w1), _solver(w2)
     with pytest.raises(M.MppiError) as e:
-        M.Batch([sv])
-    assert e.value.status == M.E_INVAL
-    w2 = synth.single_solve_workload(K=256, N=10, seed=5, ctrl_cost=1.0, flags=M.FLAG_EXTERNAL_WORKSPACE)
-    sv2 = M.Solver(w2["quad"], w2["params"], gates=w2["gates"], precision=M.FP32)
-    with pytest.raises(M.MppiError) as e:
-        M.Server([sv2], budget_bytes=1 << 26)
-    assert e.value.status == M.E_INVAL
-    sv.close()
-    sv2.close()
+        M.Batch([s1, s2])
+    assert e.value.status == M.E_INVAL and "n_iter" in str(e.value)
+    s1.close()
+    s2.close()
 
 
 def test_invalid_variant_settings_are_refused():
