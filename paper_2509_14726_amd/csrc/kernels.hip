@@ -408,16 +408,47 @@ template <typename Real, bool HAS_V> __global__ __launch_bounds__(256) void k_he
 
 // ---------------------------------------------------------------- rollout
 
+// Minimum over the 64 lanes of a wave (all lanes active), returned to every
+// lane.  Binary32 goes through DPP moves, each a few cycles instead of an
+// LDS-crossbar round trip: two quad permutes ([1,0,3,2], [2,3,0,1]), row
+// shifts by 4 and 8 (lane 15 of each row then holds the row's minimum), the
+// broadcast of lane 15 into rows 1 and 3 and of lane 31 into rows 2 and 3
+// (lane 63 then holds the wave's minimum); a lane without a source keeps
+// +inf.  Binary64 uses lane shuffles.  A minimum does not depend on the
+// order of the comparisons, so either way every caller sees the same value.
+template <int CTRL, int ROW_MASK = 0xf> __device__ __forceinline__ float dpp_or_inf(float v)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(INFINITY), __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+    float o;
+    o = dpp_or_inf<0xb1>(v);       v = o < v ? o : v;
+    o = dpp_or_inf<0x4e>(v);       v = o < v ? o : v;
+    o = dpp_or_inf<0x114>(v);      v = o < v ? o : v;
+    o = dpp_or_inf<0x118>(v);      v = o < v ? o : v;
+    o = dpp_or_inf<0x142, 0xa>(v); v = o < v ? o : v;
+    o = dpp_or_inf<0x143, 0xc>(v); v = o < v ? o : v;
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
 // Smallest finite sample cost of a 64-sample tile (+inf when there is none),
 // stored by lane 0 of the wave that holds the tile's costs.  The weighted
 // average takes J_min as the minimum over tiles: no atomics, nothing to reset.
 template <typename Real> __device__ __forceinline__ void store_tile_min(Real v, bool use, void *tmin, int tile)
 {
-    v = use ? v : Real(INFINITY);
-    for (int off = 32; off > 0; off >>= 1) {
-        const Real o = __shfl_xor(v, off, 64);
-        v = o < v ? o : v;
-    }
+    v = wave_min(use ? v : Real(INFINITY));
     if ((threadIdx.x & 63) == 0) ((Real *)tmin)[tile] = v;
 }
 
@@ -2299,13 +2330,9 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
         }
     };
 
-    // loads: tile minima (every wave reads all of them), the first UR samples
-    // of this thread
-    Real mn = Real(INFINITY);
-    for (int t = lane; t < a.n_tiles; t += 64) {
-        const Real v = ((const Real *)a.tmin)[t];
-        mn = v < mn ? v : mn;
-    }
+    // loads: the first UR samples of this thread, then the tile minima (every
+    // wave reads all of them), four per lane before the first comparison, so
+    // that one round trip to memory covers all of them
     Real Jm[UR], vm[UR];
     R4 u[UR];
 #pragma unroll
@@ -2318,6 +2345,17 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
                 if (HAS_V) vm[i] = vctrl[m];
             }
         }
+    }
+    Real mn = Real(INFINITY);
+    for (int t0 = lane; t0 < a.n_tiles; t0 += 4 * 64) {
+        Real tv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = t0 + 64 * j;
+            tv[j] = t < a.n_tiles ? ((const Real *)a.tmin)[t] : Real(INFINITY);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mn = tv[j] < mn ? tv[j] : mn;
     }
     // head values for the report and the hand-over (block of step 0)
     const bool fr = head && gate && tid <= N && tid < 256 && a.front8[tid] != 0;
@@ -2340,11 +2378,7 @@ __device__ __forceinline__ void final_body(const KArgs &a, int k)
     if (head && tid >= 7 && tid < 20) rep_x = cur->x0[tid - 7];
     // J_min within each wave (a minimum does not depend on the grouping, so
     // every wave of every block finds the same value without a block barrier)
-    for (int off = 32; off > 0; off >>= 1) {
-        const Real o = __shfl_xor(mn, off, 64);
-        mn = o < mn ? o : mn;
-    }
-    const Real jmin = mn;
+    const Real jmin = wave_min(mn);
 
     // weighted sums, UR samples per round in sample order; the next round's
     // loads are issued before this round's arithmetic
