@@ -161,6 +161,10 @@ __device__ void compute_head(const KArgs &a, HeadVals &h)
 
     double theta0 = 0.0;
     if (a.objective == OBJ_CONTOUR) {
+        // the block size, read once (a read from the dispatch's implicit
+        // arguments, which inside the barrier loop below would be repeated
+        // at every barrier)
+        const int nthr = (int)blockDim.x;
         const int P = a.P;
         const double L = a.path_len, ds = L / (double)P;
         const bool global = !warm;
@@ -174,7 +178,7 @@ __device__ void compute_head(const KArgs &a, HeadVals &h)
         double best = INFINITY, best_th = 0.0;
         int best_j = 0x7fffffff;
         const double p0 = a.req[0], p1 = a.req[1], p2 = a.req[2];
-        for (int j = tid; j < count; j += blockDim.x) {
+        for (int j = tid; j < count; j += nthr) {
             const int i = global ? j : (((ic + (j - W)) % P) + P) % P;
             const int i1 = (i + 1) % P;
             const double *A = a.path_d + 6 * i, *B = a.path_d + 6 * i1;
@@ -191,7 +195,7 @@ __device__ void compute_head(const KArgs &a, HeadVals &h)
         __syncthreads();
         // smallest distance, ties to the first candidate in search order
         for (int st = 256; st > 0; st >>= 1) {
-            if (tid < st && tid + st < (int)blockDim.x) {
+            if (tid < st && tid + st < nthr) {
                 const double d_o = s_d2[tid + st];
                 const int j_o = s_j[tid + st];
                 if (d_o < s_d2[tid] || (d_o == s_d2[tid] && j_o < s_j[tid])) {
