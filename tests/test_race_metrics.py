@@ -135,3 +135,26 @@ def test_loop_track_gates_face_along_the_path():
     n = np.array([np.cos(gates[0, 3]), np.sin(gates[0, 3]), 0.0])
     x0 = synth.start_state(gates)
     assert abs(float((gates[0, :3] - x0[:3]) @ n) - 2.0) < 1e-12
+
+
+def test_serving_drones_take_the_rate_input_only_for_contouring_when_asked():
+    """The serving workload's drones: thrust input for every drone by
+    default; with contour_input="rate" the contouring drones take the rate
+    input model (17-state start, thrusts at hover) and the gate drones keep
+    thrust."""
+    from paper_2509_14726_amd import mppi as M
+    from paper_2509_14726_amd import serving, synth
+    ws = serving.drone_workloads(24)
+    assert all(w["x0"].size == 13 and w["params"].get("input_model", M.INPUT_THRUST) == M.INPUT_THRUST
+               for w in ws)
+    wr = serving.drone_workloads(24, contour_input="rate")
+    objs = {w["params"]["objective"] for w in wr}
+    assert objs == {synth.OBJ_GATE, synth.OBJ_CONTOUR}
+    for w0, w in zip(ws, wr):
+        assert w["params"]["K"] == w0["params"]["K"] and w["params"]["N"] == w0["params"]["N"]
+        if w["params"]["objective"] == synth.OBJ_CONTOUR:
+            assert w["params"]["input_model"] == M.INPUT_RATE and w["x0"].size == 17
+            assert np.allclose(w["x0"][13:], synth.hover_thrust(w["quad"]))
+            assert np.array_equal(w["x0"][:13], w0["x0"])
+        else:
+            assert w["x0"].size == 13 and w["params"].get("input_model", M.INPUT_THRUST) == M.INPUT_THRUST
