@@ -149,18 +149,20 @@ __device__ __forceinline__ double rate_speed0(const KArgs &a, const DevWarm *w, 
     return v;
 }
 
-// Run by all threads of one block (any size up to 512); h is in LDS.
-__device__ void compute_head(const KArgs &a, HeadVals &h)
+// Run by all threads of one block (any size up to 512); h is in LDS.  A
+// kernel built for another objective than contouring passes CONTOUR = false
+// and allocates no LDS for the projection.
+template <bool CONTOUR = true> __device__ void compute_head(const KArgs &a, HeadVals &h)
 {
-    __shared__ double s_d2[512];   // one entry per thread, up to 512 threads
-    __shared__ double s_th[512];
-    __shared__ int s_j[512];
     const int tid = threadIdx.x;
     const DevWarm *w = a.warm;
     const int warm = w->warm;
 
     double theta0 = 0.0;
-    if (a.objective == OBJ_CONTOUR) {
+    if (CONTOUR && a.objective == OBJ_CONTOUR) {
+        __shared__ double s_d2[512];   // one entry per thread, up to 512 threads
+        __shared__ double s_th[512];
+        __shared__ int s_j[512];
         // the block size, read once (a read from the dispatch's implicit
         // arguments, which inside the barrier loop below would be repeated
         // at every barrier)
@@ -1776,6 +1778,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
 #pragma unroll
                 for (int i = 0; i < NS; ++i) put(kb + k_first + 2 * i, k_first + 2 * i, uu[i], vv[i]);
             } else if (ke - kb == B) {
+                static_assert(B % ND8 == 0, "each drawing wave takes B / ND8 steps of a chunk");
                 constexpr int NS = B / ND8;
                 R4 uu[NS];
                 Real vv[NS];
@@ -2199,7 +2202,7 @@ __device__ __forceinline__ void rollout4_body(const KArgs &a, int blk, const Hea
 template <int OBJ, typename Real, int B> __global__ __launch_bounds__(512) void k_rollout4(KArgs a)
 {
     __shared__ HeadVals h;
-    compute_head(a, h);
+    compute_head<OBJ == OBJ_CONTOUR>(a, h);
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_head(a, h);
     rollout4_body<OBJ, Real, B>(a, blockIdx.x, h);
 }
@@ -2207,7 +2210,7 @@ template <int OBJ, typename Real, int B> __global__ __launch_bounds__(512) void 
 template <int OBJ, typename Real> __global__ __launch_bounds__(192) void k_rollout3(KArgs a)
 {
     __shared__ HeadVals h;
-    compute_head(a, h);
+    compute_head<OBJ == OBJ_CONTOUR>(a, h);
     if (blockIdx.x == 0 && threadIdx.x == 0) publish_head(a, h);
     rollout3_body<OBJ, Real>(a, blockIdx.x, h);
 }
@@ -2607,7 +2610,7 @@ template <int OBJ, typename Real> __global__ __launch_bounds__(192) void kb_roll
         item = advance_item(b.tile_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
         const int blk = u - b.tile_prefix[item];
-        compute_head(s_a, h);
+        compute_head<OBJ == OBJ_CONTOUR>(s_a, h);
         if (blk == 0 && threadIdx.x == 0) publish_head(s_a, h);
         rollout3_body<OBJ, Real>(s_a, blk, h);
     }
@@ -2630,7 +2633,7 @@ template <int OBJ, typename Real, int B> __global__ __launch_bounds__(256) void 
         item = advance_item(b.tile_prefix, n, u, item);
         stage_args(s_a, s_ctx, b, item);
         const int blk = u - b.tile_prefix[item];
-        compute_head(s_a, h);
+        compute_head<OBJ == OBJ_CONTOUR>(s_a, h);
         if (blk == 0 && threadIdx.x == 0) publish_head(s_a, h);
         rollout4_body<OBJ, Real, B>(s_a, blk, h);
     }
