@@ -2267,7 +2267,27 @@ template <typename Real, bool HAS_V> __global__ __launch_bounds__(64) void k_ctr
 
 // ---------------------------------------------------------------- weighted average
 
-template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
+// Sum over the 64 lanes of a wave (all lanes active) by a fixed tree,
+// returned to every lane: binary32 through the DPP moves of wave_min (a lane
+// without a source adds 0; lane 63 ends with the sum), binary64 through lane
+// shuffles.
+template <int CTRL, int ROW_MASK = 0xf> __device__ __forceinline__ float dpp_or_zero(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v += dpp_or_zero<0xb1>(v);
+    v += dpp_or_zero<0x4e>(v);
+    v += dpp_or_zero<0x114>(v);
+    v += dpp_or_zero<0x118>(v);
+    v += dpp_or_zero<0x142, 0xa>(v);
+    v += dpp_or_zero<0x143, 0xc>(v);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -2279,12 +2299,12 @@ template <typename Acc> __device__ __forceinline__ Acc wave_sum(Acc v)
 // Thread t adds the samples t, t + kFinalThreads, ... in that order.  The
 // thread sums go to LDS; lane l of wave i then adds value i of threads l,
 // l + 64, ..., l + kFinalThreads - 64 in that order and the lanes are added
-// by a fixed tree, one value per wave, all values at once.  S and
-// sum_m w~_m^2 come out of the same loop in every block, bit for bit, so no
-// block waits for another.  The block of step 0 also writes the first input,
-// the report, the nominal's pass mask for the next solve and the warm-start
-// hand-over.  Every load the block needs (tile minima, its first samples,
-// head values) is issued before the first of them is used.
+// by the fixed tree of wave_sum, one value per wave, all values at once.  S
+// and sum_m w~_m^2 come out of the same loop in every block, bit for bit, so
+// no block waits for another.  The block of step 0 also writes the first
+// input, the report, the nominal's pass mask for the next solve and the
+// warm-start hand-over.  The samples are loaded first, then the tile minima,
+// so that one wait covers all of them.
 //
 // REGEN: the samples are not read from the sample tensor (which the rollout
 // then does not write) but drawn again from the counter-based noise of this
