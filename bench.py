@@ -39,17 +39,17 @@ PEAK_HBM_GBPS = 8000.0
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a run
 # of its own, WRITE_SIZE (KiB per dispatch, mean of 12 dispatches of the
 # benchmark workload), scaled by what the same counters read for a plain
-# 256 MiB device copy (FETCH_SIZE 131085.3 KiB -> x 2.0, WRITE_SIZE
+# 256 MiB device copy (FETCH_SIZE 131085.2 KiB -> x 2.0, WRITE_SIZE
 # 262144.0 KiB -> x 1.0); see profiles/k_rollout4_gate_k8192_n100_traffic.md.
 # They hold only for the workload (K = 8192, N = 100, gate, binary32, the
 # four-wave layout with 4-step chunks; the average reading the sample tensor
 # or drawing the samples again) and the device sources they were taken on
 # (sha256 of kernels.hip, device.hpp, rollout.hpp, noise.hpp in that order);
 # otherwise the traffic is reported as null.
-TRAFFIC_SOURCES = "76873254f76bdc3c3fcf45327a1eaada449ae582084e53d9530098c409b5aad9"
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.3, 262144.0 / 262144.0
-TRAFFIC_KIB = {("k_rollout4", 0): (195.6, 12836.4), ("k_final", 0): (6569.5, 6.6),
-               ("k_rollout4", 1): (195.5, 38.0), ("k_final", 1): (213.2, 6.6)}
+TRAFFIC_SOURCES = "fb4b8f90baacc8aedb9d869f966968959d580ebad4ea0565a29b5417ce29b7b9"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131085.2, 262144.0 / 262144.0
+TRAFFIC_KIB = {("k_rollout4", 0): (185.7, 12836.4), ("k_final", 0): (6575.5, 6.6),
+               ("k_rollout4", 1): (185.6, 38.0), ("k_final", 1): (211.5, 6.6)}
 TRAFFIC_WORKLOADS = {(8192, 100, "fp32", 0), (8192, 100, "fp32", 1)}
 ROLLOUT_KERNELS = {1: "k_rollout", 2: "k_rollout_split", 3: "k_rollout3", 4: "k_rollout4"}
 
